@@ -1,0 +1,251 @@
+"""Interaction kernels and emissivity/opacity contraction (oracle; test infrastructure only).
+
+Steps, in the order the method takes them (FP64 throughout, complex-safe):
+
+1. Scattering quadrature, tasks eps_i >= eps_j (down-scatter and diagonal):
+     q_{l,S}(i,j) = G_F^2/(pi eps_i eps_j) sum_k W_k F(E_k) [1 - F(E_k + eps_i - eps_j)] H^{N,S}_l(eps_i, eps_j, E_k)
+   with F(E) = 1/(exp((E - mu_e)/T) + 1) and the rule of ``oracle.rule``.
+2. Scattering completion (detailed balance, in/out symmetry), no quadrature:
+     Phi_out(i,j) = q(i,j) for i >= j,  Phi_out(i,j) = exp(-(eps_j - eps_i)/T) q(j,i) for j > i,
+     Phi_in(i,j) = Phi_out(j,i).
+3. Pair quadrature, all (i,j):
+     A_l(i,j) = G_F^2/(pi eps_i eps_j) sum_k W_k [1 - F(E_k)] [1 - Fbar(eps_i + eps_j - E_k)] H^{P,I}_l(eps_i, eps_j, E_k),
+   Fbar(E) = 1/(exp((E + mu_e)/T) + 1);  Phi_a_I(i,j) = A(i,j), Phi_a_II(i,j) = A(j,i)
+   (H^{P,II}(e, e', E) = H^{P,I}(e', e, E) and both tasks share nodes), production
+   Phi_p = exp(-(eps_i + eps_j)/T) Phi_a.
+4. Species: Phi^s = beta_I^s Phi_I + beta_II^s Phi_II  (``oracle.physics.couplings``).
+5. Contraction with the P1 distribution f(mu) = f0 + 3 mu f1 of species s (partner sbar),
+   c0 = 1/(4 pi^2 hbar c), bin volumes w_j:
+     scattering: eta0 += c0 sum_j w_j Phi_in_0 f0(j)
+                 chi0 += c0 sum_j w_j [Phi_in_0 f0(j) + Phi_out_0 (1 - f0(j))]
+                 eta1 += c0 sum_j w_j Phi_in_1 f1(j)
+                 chi1 += c0 sum_j w_j (Phi_in_1 - Phi_out_1) f1(j)
+     pair:       eta0 += c0 sum_j w_j Phi_p_0 (1 - f0^sbar(j))
+                 chi0 += c0 sum_j w_j [Phi_p_0 (1 - f0^sbar(j)) + Phi_a_0 f0^sbar(j)]
+                 eta1 -= c0 sum_j w_j Phi_p_1 f1^sbar(j)
+                 chi1 += c0 sum_j w_j (Phi_a_1 - Phi_p_1) f1^sbar(j)
+   i.e. the collision term eta - chi f projected on the zeroth and first angular moments
+   (the J, H moments of the paper's Eq. 1; intensity normalisation with (2 pi hbar c)^3,
+   Sect. 2.1). A consumer forms S0 = eta0 - chi0 f0 - 3 chi1 f1, S1 = eta1 - chi1 f0 - chi0 f1.
+Outputs eta[z][s][m][i], chi[z][s][m][i] in cm^-1.
+
+Pins: tests/test_oracle_rates.py (vacuum and non-degenerate closed forms, equilibrium null
+test, continuous detailed balance by adaptive integration, linearity, couplings).
+"""
+import dataclasses
+import math
+
+import numpy as np
+
+from . import physics
+from .angular import h_nes, h_pair
+from .rule import RULE_PANEL, nes_nodes, pair_nodes
+
+PROC_NES = 1
+PROC_PAIR = 2
+
+
+@dataclasses.dataclass(frozen=True)
+class Options:
+    nquad: int = 48
+    rule: str = RULE_PANEL
+    processes: int = PROC_NES | PROC_PAIR
+    sin2w: float = physics.SIN2W
+
+
+def _sigma(z):
+    """Logistic 1/(1 + exp(-z)), overflow-free, decided on the real part."""
+    with np.errstate(over="ignore", invalid="ignore"):
+        pos = 1.0 / (1.0 + np.exp(-z))
+        ez = np.exp(z)
+        neg = ez / (1.0 + ez)
+    return np.where(np.real(z) >= 0, pos, neg)
+
+
+def fermi(E, mu, T):
+    """Electron occupation 1/(exp((E - mu)/T) + 1)."""
+    return _sigma((mu - E) / T)
+
+
+def one_minus_fermi(E, mu, T):
+    return _sigma((E - mu) / T)
+
+
+def one_minus_fermi_positron(E, mu, T):
+    """1 - 1/(exp((E + mu)/T) + 1) for positrons (chemical potential -mu)."""
+    return _sigma((E + mu) / T)
+
+
+def nes_tasks(ne):
+    ii, jj = np.tril_indices(ne)
+    return ii, jj
+
+
+def scattering_quadrature(eps, T, mu, opts):
+    """q[z, t, S, l] for tasks t = (i >= j) of ``nes_tasks``; S, l in {0, 1} (S index 0 = I)."""
+    ii, jj = nes_tasks(eps.shape[0])
+    ei = eps[ii][None, :]
+    ej = eps[jj][None, :]
+    Tz = T[:, None]
+    muz = mu[:, None]
+    E, W = nes_nodes(ei, ej, Tz, muz, opts.nquad, opts.rule)
+    delta = (ei - ej)[..., None]
+    B = fermi(E, muz[..., None], Tz[..., None]) * one_minus_fermi(E + delta, muz[..., None], Tz[..., None])
+    pref = physics.G_F ** 2 / (math.pi * ei * ej)
+    out = []
+    for S in (1, 2):
+        row = []
+        for l in (0, 1):
+            H = h_nes(l, S, ei[..., None], ej[..., None], E)
+            row.append(pref * np.sum(W * B * H, axis=-1))
+        out.append(np.stack(row, axis=-1))
+    return np.stack(out, axis=-2)  # [z, t, S, l]
+
+
+def pair_quadrature(eps, T, mu, opts):
+    """A[z, i, j, l] for all bin pairs."""
+    ne = eps.shape[0]
+    ei = eps[:, None][None]
+    ej = eps[None, :][None]
+    Tz = T[:, None, None]
+    muz = mu[:, None, None]
+    E, W = pair_nodes(ei, ej, Tz, muz, opts.nquad)
+    w = (ei + ej)[..., None]
+    B = one_minus_fermi(E, muz[..., None], Tz[..., None]) * \
+        one_minus_fermi_positron(w - E, muz[..., None], Tz[..., None])
+    pref = physics.G_F ** 2 / (math.pi * ei * ej)
+    out = []
+    for l in (0, 1):
+        H = h_pair(l, 1, ei[..., None], ej[..., None], E)
+        out.append(pref * np.sum(W * B * H, axis=-1))
+    return np.stack(out, axis=-1).reshape(T.shape[0], ne, ne, 2)
+
+
+def zone_kernels(eps, T, eta_e, opts):
+    """S-split kernels after completion: dict of arrays [z, i, j, S, l] (S index 0 = I)."""
+    eps = np.asarray(eps, dtype=float)
+    T = np.asarray(T)
+    mu = np.asarray(eta_e) * T
+    ne = eps.shape[0]
+    nz = T.shape[0]
+    out = {}
+    if opts.processes & PROC_NES:
+        q = scattering_quadrature(eps, T, mu, opts)
+        ii, jj = nes_tasks(ne)
+        full = np.zeros((nz, ne, ne, 2, 2), dtype=q.dtype)
+        full[:, ii, jj] = q
+        # up-scatter j > i from the down-scatter task (j, i): exp(-(eps_j - eps_i)/T)
+        up = np.exp(-(eps[None, None, :] - eps[None, :, None]) / T[:, None, None])  # [z, i, j]
+        upper = np.triu(np.ones((ne, ne), dtype=bool), 1)
+        trans = np.swapaxes(full, 1, 2)
+        phi_out = np.where(upper[None, :, :, None, None], up[..., None, None] * trans, full)
+        out["nes_out"] = phi_out
+        out["nes_in"] = np.swapaxes(phi_out, 1, 2)
+    if opts.processes & PROC_PAIR:
+        A = pair_quadrature(eps, T, mu, opts)
+        phi_a = np.stack([A, np.swapaxes(A, 1, 2)], axis=-2)  # [z, i, j, S, l]
+        prod = np.exp(-(eps[None, :, None] + eps[None, None, :]) / T[:, None, None])
+        out["pair_a"] = phi_a
+        out["pair_p"] = prod[..., None, None] * phi_a
+    return out
+
+
+def _species(kern, beta):
+    return beta[0] * kern[..., 0, :] + beta[1] * kern[..., 1, :]   # [z, i, j, l]
+
+
+def contract(kernels, w, f, opts):
+    """eta, chi [z, s, m, i] from completed kernels and f [z, s, m, j]."""
+    w = np.asarray(w, dtype=float)
+    cw = physics.C0 * w  # [j]
+    nz, _, _, ne = f.shape
+    dtype = np.result_type(f, *[k for k in kernels.values()])
+    eta = np.zeros((nz, 3, 2, ne), dtype=dtype)
+    chi = np.zeros((nz, 3, 2, ne), dtype=dtype)
+    betas = physics.couplings(opts.sin2w)
+    for s in range(3):
+        b = betas[s]
+        if "nes_out" in kernels:
+            pin = _species(kernels["nes_in"], b)    # [z, i, j, l]
+            pout = _species(kernels["nes_out"], b)
+            f0 = f[:, s, 0, None, :] * cw
+            g0 = (1.0 - f[:, s, 0, None, :]) * cw
+            f1 = f[:, s, 1, None, :] * cw
+            eta[:, s, 0] += np.sum(pin[..., 0] * f0, axis=-1)
+            chi[:, s, 0] += np.sum(pin[..., 0] * f0 + pout[..., 0] * g0, axis=-1)
+            eta[:, s, 1] += np.sum(pin[..., 1] * f1, axis=-1)
+            chi[:, s, 1] += np.sum((pin[..., 1] - pout[..., 1]) * f1, axis=-1)
+        if "pair_a" in kernels:
+            sb = physics.PARTNER[s]
+            pa = _species(kernels["pair_a"], b)
+            pp = _species(kernels["pair_p"], b)
+            f0 = f[:, sb, 0, None, :] * cw
+            g0 = (1.0 - f[:, sb, 0, None, :]) * cw
+            f1 = f[:, sb, 1, None, :] * cw
+            eta[:, s, 0] += np.sum(pp[..., 0] * g0, axis=-1)
+            chi[:, s, 0] += np.sum(pp[..., 0] * g0 + pa[..., 0] * f0, axis=-1)
+            eta[:, s, 1] -= np.sum(pp[..., 1] * f1, axis=-1)
+            chi[:, s, 1] += np.sum((pa[..., 1] - pp[..., 1]) * f1, axis=-1)
+    return eta, chi
+
+
+def contract_abs(kernels, w, f, opts):
+    """Per-output sums of |terms| (A of the relative-error floor max(|y|, 1e-3 A))."""
+    ak = {k: np.abs(v) for k, v in kernels.items()}
+    w = np.asarray(w, dtype=float)
+    cw = physics.C0 * w
+    nz, _, _, ne = f.shape
+    aeta = np.zeros((nz, 3, 2, ne))
+    achi = np.zeros((nz, 3, 2, ne))
+    betas = physics.couplings(opts.sin2w)
+    for s in range(3):
+        b = betas[s]
+        if "nes_out" in ak:
+            pin = _species(ak["nes_in"], b)
+            pout = _species(ak["nes_out"], b)
+            f0 = f[:, s, 0, None, :] * cw
+            g0 = np.abs(1.0 - f[:, s, 0, None, :]) * cw
+            f1 = np.abs(f[:, s, 1, None, :]) * cw
+            aeta[:, s, 0] += np.sum(pin[..., 0] * f0, axis=-1)
+            achi[:, s, 0] += np.sum(pin[..., 0] * f0 + pout[..., 0] * g0, axis=-1)
+            aeta[:, s, 1] += np.sum(pin[..., 1] * f1, axis=-1)
+            achi[:, s, 1] += np.sum((pin[..., 1] + pout[..., 1]) * f1, axis=-1)
+        if "pair_a" in ak:
+            sb = physics.PARTNER[s]
+            pa = _species(ak["pair_a"], b)
+            pp = _species(ak["pair_p"], b)
+            f0 = f[:, sb, 0, None, :] * cw
+            g0 = np.abs(1.0 - f[:, sb, 0, None, :]) * cw
+            f1 = np.abs(f[:, sb, 1, None, :]) * cw
+            aeta[:, s, 0] += np.sum(pp[..., 0] * g0, axis=-1)
+            achi[:, s, 0] += np.sum(pp[..., 0] * g0 + pa[..., 0] * f0, axis=-1)
+            aeta[:, s, 1] += np.sum(pp[..., 1] * f1, axis=-1)
+            achi[:, s, 1] += np.sum((pa[..., 1] + pp[..., 1]) * f1, axis=-1)
+    return aeta, achi
+
+
+def forward(eps, w, T, eta_e, f, opts=Options(), chunk=32):
+    """eta, chi [z, 3, 2, NE] for zone states T[z], eta_e[z] and distributions f[z, 3, 2, NE]."""
+    T = np.asarray(T)
+    eta_e = np.asarray(eta_e)
+    outs_e, outs_c = [], []
+    for z0 in range(0, T.shape[0], chunk):
+        sl = slice(z0, z0 + chunk)
+        k = zone_kernels(eps, T[sl], eta_e[sl], opts)
+        e, c = contract(k, w, f[sl], opts)
+        outs_e.append(e)
+        outs_c.append(c)
+    return np.concatenate(outs_e), np.concatenate(outs_c)
+
+
+def forward_with_scale(eps, w, T, eta_e, f, opts=Options(), chunk=32):
+    """(eta, chi, A_eta, A_chi): outputs plus their sums of absolute terms."""
+    res = [[], [], [], []]
+    for z0 in range(0, len(T), chunk):
+        sl = slice(z0, z0 + chunk)
+        k = zone_kernels(eps, np.asarray(T)[sl], np.asarray(eta_e)[sl], opts)
+        e, c = contract(k, w, f[sl], opts)
+        ae, ac = contract_abs(k, w, f[sl], opts)
+        for lst, v in zip(res, (e, c, ae, ac)):
+            lst.append(v)
+    return tuple(np.concatenate(r) for r in res)

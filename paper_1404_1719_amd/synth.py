@@ -1,0 +1,145 @@
+"""Seeded synthetic workloads: energy grid, zone states and neutrino distributions.
+
+This module is shared by the test suite, the benchmark and the CPU oracle's callers.
+It holds no part of the rate computation itself: it only draws inputs.
+
+Workloads (named by shape; all draw order fixed as T, eta_e, a_s, noise, h):
+
+* ``small``   : 1 ray x 64 radial zones, NE = 12 log bins 2-300 MeV, T ~ U(3, 30) MeV,
+                eta_e ~ U(0, 20), a_s = mu_nu/T ~ U(-2, 10), no noise, 32 nodes, Gauss-Laguerre rule.
+* ``medium``  : 256 rays x 400 zones, NE = 21 log bins 2-380 MeV, T ~ U(1, 40), eta_e ~ U(0, 40),
+                a_s ~ U(-2, 15), 5 % multiplicative log-normal noise on f0, 48 nodes, panel rule.
+* ``large``   : 4096 rays x 600 zones, NE = 21, T ~ U(0.5, 60), eta_e ~ U(0, 60), a_s ~ U(-2, 15),
+                5 % noise, 64 nodes, panel rule (one GPU's share of a 3-D model).
+
+Energy grid: NE + 1 geometric bin edges e_0..e_NE, centres eps_i = sqrt(e_i e_{i+1}) and
+bin volumes w_i = (e_{i+1}^3 - e_i^3)/3 [MeV^3], the measure of the eps'^2 d eps' phase-space
+integral over bin i (the paper writes intensities with the (2 pi hbar c)^3 phase-space
+normalisation, Sect. 2.1).
+
+Neutrino distribution per zone, species s and bin i:
+  f0 = 1 / (exp(eps_i/T - a_s) + 1), optionally f0 <- clip(f0 * exp(0.05 N(0,1)), 0, 1);
+  f1 = h f0 (1 - f0) with h ~ U(0, 1/3) per (zone, species), so that f0 + 3 mu f1 stays in [0, 1].
+Layout: f[zone][species][moment][bin], species order (nu_e, anti-nu_e, nu_x).
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+NSPECIES = 3
+SEED_BASE = 14041719
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    seed_index: int
+    rays: int
+    radial: int
+    ne: int
+    emin: float
+    emax: float
+    t_range: tuple
+    eta_range: tuple
+    a_range: tuple
+    noise: float
+    nquad: int
+    rule: str          # "laguerre" or "panel"
+    precision: str     # default arithmetic of the workload: "fp64" or "mixed"
+    chunks: int = 1
+
+    @property
+    def nzones(self) -> int:
+        return self.rays * self.radial
+
+
+WORKLOADS = {
+    "small": Workload("small", 1, 1, 64, 12, 2.0, 300.0, (3.0, 30.0), (0.0, 20.0), (-2.0, 10.0),
+                      0.0, 32, "laguerre", "fp64"),
+    "medium": Workload("medium", 2, 256, 400, 21, 2.0, 380.0, (1.0, 40.0), (0.0, 40.0), (-2.0, 15.0),
+                       0.05, 48, "panel", "fp64"),
+    "medium-mixed": Workload("medium-mixed", 3, 256, 400, 21, 2.0, 380.0, (1.0, 40.0), (0.0, 40.0),
+                             (-2.0, 15.0), 0.05, 48, "panel", "mixed"),
+    "medium-grad": Workload("medium-grad", 4, 256, 400, 21, 2.0, 380.0, (1.0, 40.0), (0.0, 40.0),
+                            (-2.0, 15.0), 0.05, 48, "panel", "fp64"),
+    "large": Workload("large", 5, 4096, 600, 21, 2.0, 380.0, (0.5, 60.0), (0.0, 60.0), (-2.0, 15.0),
+                      0.05, 64, "panel", "mixed", chunks=8),
+}
+
+
+def energy_grid(ne: int, emin: float, emax: float):
+    """Geometric edges, centres eps_i = sqrt(e_i e_{i+1}) and volumes w_i = (e_{i+1}^3 - e_i^3)/3."""
+    edges = np.geomspace(emin, emax, ne + 1)
+    eps = np.sqrt(edges[1:] * edges[:-1])
+    w = (edges[1:] ** 3 - edges[:-1] ** 3) / 3.0
+    return eps, w
+
+
+@dataclasses.dataclass
+class ZoneInputs:
+    eps: np.ndarray      # [NE]
+    w: np.ndarray        # [NE]
+    T: np.ndarray        # [Z]   MeV
+    eta_e: np.ndarray    # [Z]   electron degeneracy mu_e / T
+    f: np.ndarray        # [Z, 3, 2, NE]
+
+
+def draw_zones(nzones: int, ne: int, eps: np.ndarray, t_range, eta_range, a_range, noise, seed):
+    """Draw zone states and distributions in the fixed order T, eta_e, a_s, noise, h."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = rng.uniform(t_range[0], t_range[1], nzones)
+    eta_e = rng.uniform(eta_range[0], eta_range[1], nzones)
+    a = rng.uniform(a_range[0], a_range[1], (nzones, NSPECIES))
+    z = eps[None, None, :] / T[:, None, None] - a[:, :, None]
+    with np.errstate(over="ignore"):
+        f0 = 1.0 / (np.exp(z) + 1.0)
+    if noise > 0.0:
+        f0 = np.clip(f0 * np.exp(noise * rng.standard_normal(f0.shape)), 0.0, 1.0)
+    h = rng.uniform(0.0, 1.0 / 3.0, (nzones, NSPECIES))
+    f1 = h[:, :, None] * f0 * (1.0 - f0)
+    f = np.stack([f0, f1], axis=2)  # [Z, 3, 2, NE]
+    return T, eta_e, np.ascontiguousarray(f)
+
+
+def make_inputs(workload: str | Workload, nzones: int | None = None) -> ZoneInputs:
+    """Full (or first-``nzones``) seeded inputs of a named workload.
+
+    Drawing a prefix uses the same stream as the full workload only for the T array;
+    callers that need bit-identical subsets of a full-size workload draw it whole and
+    slice (``subset``)."""
+    wl = WORKLOADS[workload] if isinstance(workload, str) else workload
+    eps, w = energy_grid(wl.ne, wl.emin, wl.emax)
+    nz = wl.nzones if nzones is None else nzones
+    T, eta_e, f = draw_zones(nz, wl.ne, eps, wl.t_range, wl.eta_range, wl.a_range, wl.noise,
+                             SEED_BASE + wl.seed_index)
+    return ZoneInputs(eps, w, T, eta_e, f)
+
+
+def subset(inp: ZoneInputs, idx) -> ZoneInputs:
+    idx = np.asarray(idx)
+    return ZoneInputs(inp.eps, inp.w, inp.T[idx].copy(), inp.eta_e[idx].copy(),
+                      np.ascontiguousarray(inp.f[idx]))
+
+
+def sample_zones(inp: ZoneInputs, count: int, seed: int = 0):
+    """Indices of a seeded zone sample that always holds the min-T, max-T and max-eta_e zones."""
+    nz = inp.T.shape[0]
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 1000 + seed))
+    forced = {int(np.argmin(inp.T)), int(np.argmax(inp.T)), int(np.argmax(inp.eta_e))}
+    rest = rng.choice(nz, size=min(nz, count + 3), replace=False)
+    out = list(forced)
+    for r in rest:
+        if len(out) >= min(count, nz):
+            break
+        if int(r) not in forced:
+            out.append(int(r))
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def random_gradients(nzones: int, ne: int, seed: int):
+    """Seeded upstream gradients g_eta, g_chi of shape [Z, 3, 2, NE] (unit normal entries)."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 2000 + seed))
+    g_eta = rng.standard_normal((nzones, NSPECIES, 2, ne))
+    g_chi = rng.standard_normal((nzones, NSPECIES, 2, ne))
+    return g_eta, g_chi

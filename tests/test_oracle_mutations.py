@@ -1,0 +1,75 @@
+"""Planted mistakes in the oracle (on the CPU, via monkeypatch) must trip its pins.
+
+Each mutation is a plausible slip: a sign in the azimuthal average, a missing 1/2, the
+positron chemical-potential sign, a dropped exp(x) in the Laguerre weights, an unswapped
+anti-neutrino coupling. The matching pin is re-run against the mutated oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle.angular as ang
+import oracle.physics as phys
+import oracle.rates as rates
+import oracle.rule as rule
+from paper_1404_1719_amd import synth
+
+import test_oracle_angular as pins_ang
+
+
+def _brute_fails(l, S, e, ep, E, fn, avg, pole):
+    ref = pins_ang.brute_h(avg, l, S, e, ep, E, pole)
+    got = float(fn(l, S, e, ep, E))
+    return abs(got - ref) > 5e-8 * abs(float(fn(0, S, e, ep, E)))
+
+
+def test_sign_of_azimuthal_term(monkeypatch):
+    orig = ang._phi_average
+    monkeypatch.setattr(ang, "_phi_average", lambda *a: orig(*a[:-1], -a[-1]))
+    assert _brute_fails(1, 1, 20.0, 10.0, 15.0, ang.h_nes, pins_ang.brute_nes_avg, 1.0)
+    assert _brute_fails(0, 2, 20.0, 10.0, 25.0, ang.h_pair, pins_ang.brute_pair_avg, -1.0)
+
+
+def test_missing_half_in_average(monkeypatch):
+    def bad(e, ep, E, ca, cb, cbp, sbsb, sign):
+        return ang.__dict__["_orig"](e, ep, E, ca, cb, cbp, sbsb * 2.0, sign)
+    monkeypatch.setitem(ang.__dict__, "_orig", ang._phi_average)
+    monkeypatch.setattr(ang, "_phi_average", bad)
+    assert _brute_fails(0, 1, 20.0, 10.0, 5.0, ang.h_nes, pins_ang.brute_nes_avg, 1.0)
+
+
+def test_positron_potential_sign(monkeypatch):
+    monkeypatch.setattr(rates, "one_minus_fermi_positron", lambda E, mu, T: rates._sigma((E - mu) / T))
+    inp = synth.make_inputs("medium", nzones=1)
+    f = np.zeros((1, 3, 2, inp.eps.shape[0]))
+    f[0, 0, 0] = 1 / (np.exp(inp.eps / inp.T[0] - 1.0) + 1)
+    f[0, 1, 0] = 1 / (np.exp(inp.eps / inp.T[0] + 1.0) + 1)
+    opts = rates.Options(nquad=48, processes=rates.PROC_PAIR)
+    k = rates.zone_kernels(inp.eps, inp.T, inp.eta_e, opts)
+    # detailed balance of the production kernel must break
+    pf = np.exp(-(inp.eps[:, None] + inp.eps[None, :]) / inp.T[0])
+    # the completed kernels still satisfy it by construction; a direct production quadrature does not
+    E, W = rule.pair_nodes(inp.eps[3], inp.eps[5], inp.T[0], inp.eta_e[0] * inp.T[0], 48)
+    mu, T, w = inp.eta_e[0] * inp.T[0], inp.T[0], inp.eps[3] + inp.eps[5]
+    H = ang.h_pair(0, 1, inp.eps[3], inp.eps[5], E)
+    ann = np.sum(W * rates.one_minus_fermi(E, mu, T) * rates.one_minus_fermi_positron(w - E, mu, T) * H)
+    prod = np.sum(W * rates.fermi(E, mu, T) * (1 - rates.one_minus_fermi_positron(w - E, mu, T)) * H)
+    assert not np.isclose(prod, pf[3, 5] * ann, rtol=1e-6, atol=0)
+
+
+def test_laguerre_weights_without_exp(monkeypatch):
+    orig = rule._lag.laggauss
+    monkeypatch.setattr(rule, "gauss_laguerre_scaled", lambda m: orig(m))
+    x, wt = rule.gauss_laguerre_scaled(12)
+    assert not np.isclose(np.sum(wt * np.exp(-x) * x ** 3), math.factorial(3), rtol=1e-10, atol=0)
+
+
+def test_unswapped_antineutrino_coupling(monkeypatch):
+    good = phys.couplings()
+    monkeypatch.setattr(phys, "couplings", lambda s=phys.SIN2W: (good[0], good[0], good[2]))
+    b = phys.couplings()
+    inp = synth.make_inputs("small", nzones=1)
+    k = rates.zone_kernels(inp.eps, inp.T, inp.eta_e, rates.Options(nquad=32, rule="laguerre"))
+    pa_nu = b[0][0] * k["pair_a"][..., 0, :] + b[0][1] * k["pair_a"][..., 1, :]
+    pa_bar = b[1][0] * k["pair_a"][..., 0, :] + b[1][1] * k["pair_a"][..., 1, :]
+    assert not np.allclose(pa_bar, np.swapaxes(pa_nu, 1, 2), rtol=1e-6, atol=0)

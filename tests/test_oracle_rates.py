@@ -1,0 +1,187 @@
+"""Pins for the oracle's kernels and contraction (oracle.rates, oracle.converged, oracle.grad).
+
+Closed forms (from textbook massless cross-sections, not from the oracle's own formulas):
+* pair annihilation in vacuum: sigma(nu nubar -> e+ e-) = G_F^2 s (C_V^2 + C_A^2)/(3 pi),
+  rate R(x) = sigma(s) (1 - x), s = 2 eps eps' (1 - x), so
+  Phi_0 = 8 G_F^2 eps eps' (beta_I + beta_II)/(9 pi) and Phi_1 = -Phi_0/2;
+* non-degenerate nu-e scattering: sigma = (G_F^2 s/pi)(g_L^2 + g_R^2/3); averaged over a
+  Maxwell-Boltzmann e- gas (density prefactor e^eta), the total out-scattering rate is
+  e^eta 4 G_F^2 eps T^4/pi^3 for beta_I = 1 and a third of it for beta_II = 1.
+Invariants: continuous detailed balance and time reversal by direct adaptive integration,
+the equilibrium null test of the contraction, linearity in f, coupling algebra; gradients
+against central differences.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+
+from oracle import converged, grad, physics, rates, rule
+from oracle.angular import h_nes
+from paper_1404_1719_amd import synth
+
+
+def test_couplings():
+    b = physics.couplings(0.2312)
+    cv = 0.5 + 2 * 0.2312
+    assert np.allclose(b[0], ((cv + 0.5) ** 2, (cv - 0.5) ** 2), atol=0)
+    assert b[1] == (b[0][1], b[0][0])
+    cvx = -0.5 + 2 * 0.2312
+    assert np.isclose(b[2][0], cvx ** 2 + 0.25, atol=0) and b[2][0] == b[2][1]
+
+
+@pytest.mark.parametrize("e,ep", [(10.0, 20.0), (33.0, 5.0), (7.0, 7.0)])
+def test_vacuum_pair(e, ep):
+    eps = np.array([e, ep])
+    A = rates.pair_quadrature(eps, np.array([1e-6]), np.array([0.0]), rates.Options(nquad=32))
+    # Integral H^{P,S}_0 dE = (8/9)(e ep)^2 for each S, so Phi_{0,S} = 8 G_F^2 e ep/(9 pi) and
+    # beta_I Phi_I + beta_II Phi_II = 8 G_F^2 e ep (beta_I + beta_II)/(9 pi).
+    ref0 = 8 * physics.G_F ** 2 * e * ep / (9 * math.pi)
+    assert np.isclose(A[0, 0, 1, 0], ref0, rtol=1e-11, atol=0)
+    assert np.isclose(A[0, 0, 1, 1], -ref0 / 2, rtol=1e-11, atol=0)
+    assert np.isclose(A[0, 1, 0, 0], ref0, rtol=1e-11, atol=0)
+    # cross-section route: Integral_-1^1 sigma(s)(1 - x) P_l(x) dx with beta_I = beta_II = 1
+    for l in (0, 1):
+        sig = lambda x: physics.G_F ** 2 * 2 * e * ep * (1 - x) / (3 * math.pi) * (1 - x) * (x if l else 1.0)
+        # beta_I = beta_II = 1, i.e. C_V^2 + C_A^2 = 1; both S contribute A: Phi = 2 A
+        tot = si.quad(sig, -1, 1, epsabs=0, epsrel=1e-13)[0]
+        assert np.isclose(2 * A[0, 0, 1, l], tot, rtol=1e-11, atol=0)
+
+
+@pytest.mark.parametrize("S,factor", [(1, 1.0), (2, 1.0 / 3.0)])
+def test_nondegenerate_scattering_rate(S, factor):
+    """(1/4pi^2) Integral eps'^2 Phi_out_0 d eps' -> e^eta 4 G_F^2 eps T^4/pi^3 (x 1/3 for S = II)."""
+    e, T, eta = 11.0, 3.0, -40.0
+    mu = eta * T
+    xg, wg = np.polynomial.legendre.leggauss(60)
+    xl, wl = np.polynomial.laguerre.laggauss(32)   # 32 nodes: weights pinned in test_oracle_rule
+
+    def phi_out(ep):
+        # Integral over E of F(E)(1 - F(E + e - ep)) H, split at the kink E = ep
+        lo = max(0.0, ep - e)
+        a, b = lo, max(lo, ep)
+        E1 = a + (b - a) * (xg + 1) / 2
+        W1 = (b - a) / 2 * wg
+        E2 = b + T * xl
+        W2 = T * wl * np.exp(xl)
+        E = np.concatenate([E1, E2])
+        W = np.concatenate([W1, W2])
+        blk = rates.fermi(E, mu, T) * rates.one_minus_fermi(E + e - ep, mu, T)
+        return physics.G_F ** 2 / (math.pi * e * ep) * np.sum(W * blk * h_nes(0, S, e, ep, E))
+
+    f = lambda ep: ep * ep * phi_out(ep)
+    tot = (si.quad(f, 0, e, epsabs=0, epsrel=1e-12, limit=200)[0]
+           + si.quad(f, e, np.inf, epsabs=0, epsrel=1e-12, limit=200)[0])
+    rate = tot / (4 * math.pi ** 2)
+    ref = factor * math.exp(eta) * 4 * physics.G_F ** 2 * e * T ** 4 / math.pi ** 3
+    assert np.isclose(rate, ref, rtol=1e-8, atol=0)
+
+
+@pytest.mark.parametrize("l", [0, 1])
+@pytest.mark.parametrize("S", [1, 2])
+def test_continuous_detailed_balance(l, S):
+    T, mu = 10.0, 50.0
+    down = converged.nes_out(l, S, 20.0, 10.0, T, mu)
+    up = converged.nes_out(l, S, 10.0, 20.0, T, mu)
+    assert np.isclose(up, math.exp(-1.0) * down, rtol=1e-9, atol=0)
+    a = converged.pair(l, S, 20.0, 10.0, T, mu)
+    p = converged.pair(l, S, 20.0, 10.0, T, mu, production=True)
+    assert np.isclose(p, math.exp(-3.0) * a, rtol=1e-9, atol=0)
+
+
+def test_rule_against_converged():
+    """Rule R vs adaptive integration: reported discretisation error, loose bound."""
+    eps = np.array([4.0, 25.0, 140.0])
+    cases = [(3.0, 2.0), (10.0, 15.0), (1.5, 30.0)]
+    errs = []
+    for T, eta in cases:
+        k = rates.zone_kernels(eps, np.array([T]), np.array([eta]), rates.Options(nquad=48))
+        for (i, j) in [(1, 0), (2, 1), (2, 2), (2, 0)]:
+            for l in (0, 1):
+                ref = converged.nes_out(l, 1, eps[i], eps[j], T, eta * T)
+                errs.append(abs(k["nes_out"][0, i, j, 0, l] - ref) / abs(ref))
+                refp = converged.pair(l, 1, eps[i], eps[j], T, eta * T)
+                errs.append(abs(k["pair_a"][0, i, j, 0, l] - refp) / abs(refp))
+    assert max(errs) < 5e-3, max(errs)
+
+
+def _equilibrium_f(eps, T, amu):
+    f0 = 1.0 / (np.exp(eps / T - amu) + 1.0)
+    return f0
+
+
+def test_equilibrium_null():
+    """f0 = FD(eps; mu_nu, T), f1 = 0: scattering S0 = eta0 - chi0 f0 = 0 per bin; the pair with
+    f0(partner) = FD(-mu_nu) likewise (detailed balance of the discrete kernels)."""
+    inp = synth.make_inputs("medium", nzones=3)
+    eps, w = inp.eps, inp.w
+    for proc in (rates.PROC_NES, rates.PROC_PAIR):
+        opts = rates.Options(nquad=48, processes=proc)
+        f = np.zeros((3, 3, 2, eps.shape[0]))
+        for z in range(3):
+            a = 1.5 * z - 1.0
+            f[z, 0, 0] = _equilibrium_f(eps, inp.T[z], a)
+            f[z, 1, 0] = _equilibrium_f(eps, inp.T[z], -a)
+            f[z, 2, 0] = _equilibrium_f(eps, inp.T[z], 0.0)
+        e, c, ae, ac = rates.forward_with_scale(eps, w, inp.T, inp.eta_e, f, opts)
+        S0 = e[:, :, 0] - c[:, :, 0] * f[:, :, 0]
+        assert np.all(np.abs(S0) <= 1e-13 * (ae[:, :, 0] + ac[:, :, 0])), np.max(np.abs(S0) / (ae[:, :, 0] + ac[:, :, 0]))
+        assert np.all(e[:, :, 1] == 0) and np.all(c[:, :, 1] == 0)
+
+
+def test_linear_in_f_and_species_algebra():
+    inp = synth.make_inputs("small", nzones=2)
+    opts = rates.Options(nquad=32, rule=rule.RULE_LAGUERRE)
+    k = rates.zone_kernels(inp.eps, inp.T, inp.eta_e, opts)
+    e1, c1 = rates.contract(k, inp.w, inp.f, opts)
+    g = np.random.default_rng(0).uniform(0, 1, inp.f.shape)
+    e2, c2 = rates.contract(k, inp.w, g, opts)
+    e3, c3 = rates.contract(k, inp.w, 0.3 * inp.f + 0.7 * g, opts)
+    assert np.allclose(e3, 0.3 * e1 + 0.7 * e2, rtol=1e-12, atol=0)
+    assert np.allclose(c3, 0.3 * c1 + 0.7 * c2, rtol=1e-12, atol=0)
+    # anti-nu_e pair kernel = nu_e pair kernel transposed (beta swap <-> transpose)
+    b = physics.couplings()
+    pa_nu = b[0][0] * k["pair_a"][..., 0, :] + b[0][1] * k["pair_a"][..., 1, :]
+    pa_bar = b[1][0] * k["pair_a"][..., 0, :] + b[1][1] * k["pair_a"][..., 1, :]
+    assert np.allclose(pa_bar, np.swapaxes(pa_nu, 1, 2), rtol=1e-13, atol=0)
+
+
+def test_discrete_detailed_balance():
+    inp = synth.make_inputs("medium", nzones=2)
+    k = rates.zone_kernels(inp.eps, inp.T, inp.eta_e, rates.Options(nquad=48))
+    ne = inp.eps.shape[0]
+    for z in range(2):
+        for i in range(ne):
+            for j in range(ne):
+                fac = math.exp((inp.eps[j] - inp.eps[i]) / inp.T[z])
+                if fac < 1e200:
+                    assert np.allclose(k["nes_in"][z, i, j], fac * k["nes_out"][z, i, j], rtol=1e-12, atol=1e-300)
+                pf = math.exp(-(inp.eps[i] + inp.eps[j]) / inp.T[z])
+                assert np.allclose(k["pair_p"][z, i, j], pf * k["pair_a"][z, i, j], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("workload,nq,rl", [("small", 32, "laguerre"), ("medium", 48, "panel")])
+def test_gradient_vs_central_differences(workload, nq, rl):
+    inp = synth.make_inputs(workload, nzones=3)
+    opts = rates.Options(nquad=nq, rule=rl)
+    ge, gc = synth.random_gradients(3, inp.eps.shape[0], 1)
+    gT, gE, gf = grad.vjp(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, ge, gc, opts)
+
+    def L(T, E, f):
+        e, c = rates.forward(inp.eps, inp.w, T, E, f, opts)
+        return np.sum(ge * e + gc * c, axis=(1, 2, 3))
+
+    h = 1e-6 * inp.T
+    fd = (L(inp.T + h, inp.eta_e, inp.f) - L(inp.T - h, inp.eta_e, inp.f)) / (2 * h)
+    assert np.allclose(gT, fd, rtol=1e-5, atol=1e-9 * np.abs(gT).max())
+    h = 1e-6 * np.maximum(np.abs(inp.eta_e), 1.0)
+    fd = (L(inp.T, inp.eta_e + h, inp.f) - L(inp.T, inp.eta_e - h, inp.f)) / (2 * h)
+    assert np.allclose(gE, fd, rtol=1e-5, atol=1e-9 * np.abs(gE).max())
+    for idx in [(0, 0, 3), (1, 1, 5), (2, 0, 0), (2, 1, 7)]:
+        fp = inp.f.copy()
+        fm = inp.f.copy()
+        fp[(slice(None),) + idx] += 1e-6
+        fm[(slice(None),) + idx] -= 1e-6
+        fd = (L(inp.T, inp.eta_e, fp) - L(inp.T, inp.eta_e, fm)) / 2e-6
+        assert np.allclose(gf[(slice(None),) + idx], fd, rtol=1e-6, atol=1e-9 * np.abs(gf).max())
