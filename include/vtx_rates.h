@@ -1,0 +1,143 @@
+/*
+ * vtx_rates.h -- C ABI of the MI355X (gfx950) neutrino-matter interaction-rate library.
+ *
+ * What it computes (per spatial zone): the energy-coupled interaction kernels of
+ * neutrino-electron scattering and e+e- pair annihilation/production, Legendre moments
+ * l = 0, 1, each a quadrature over the electron energy of Fermi-Dirac products, for every
+ * (eps_i, eps_j) energy-bin pair, contracted at once with the neutrino distribution into
+ * emissivities eta and opacities chi. The paper (Marek, Rampp, Hanke, Janka, "Towards
+ * Petaflops Capability of the VERTEX Supernova Code") lists these rates as the model
+ * component that feeds the transport source terms (Sect. 2.1) and the Jacobian of the
+ * implicit ray-by-ray Newton-Raphson solve (Sect. 2.1, radial sweep); the moments J, H of
+ * its Eq. 1 are the f0, f1 moments used here, with the (2 pi hbar c)^3 phase-space
+ * normalisation of its intensity definition.
+ *
+ * Definitions (massless e+-, V-A couplings; G_F = 1.1663787e-11 MeV^-2,
+ * hbar c = 1.973269804e-11 MeV cm, c0 = 1/(4 pi^2 hbar c)):
+ *   Phi_out_l(i,j) = G_F^2/(pi eps_i eps_j) Int dE F(E)[1-F(E+eps_i-eps_j)] sum_S beta_S H^N_{l,S}
+ *   Phi_a_l(i,j)   = G_F^2/(pi eps_i eps_j) Int dE [1-F(E)][1-Fbar(eps_i+eps_j-E)] sum_S beta_S H^P_{l,S}
+ *   computed by quadrature for eps_i >= eps_j (scattering) and all pairs (pair), completed
+ *   by detailed balance: Phi_out(i<j) = exp(-(eps_j-eps_i)/T) Phi_out(j,i),
+ *   Phi_in(i,j) = Phi_out(j,i), Phi_p = exp(-(eps_i+eps_j)/T) Phi_a;
+ *   eta/chi for species s (partner sbar), m = 0, 1, summed over both processes:
+ *     eta0 = c0 sum_j w_j [Phi_in_0 f0(j) + Phi_p_0 (1 - f0sbar(j))]
+ *     chi0 = c0 sum_j w_j [Phi_in_0 f0 + Phi_out_0 (1 - f0) + Phi_p_0 (1 - f0sbar) + Phi_a_0 f0sbar]
+ *     eta1 = c0 sum_j w_j [Phi_in_1 f1(j) - Phi_p_1 f1sbar(j)]
+ *     chi1 = c0 sum_j w_j [(Phi_in_1 - Phi_out_1) f1 + (Phi_a_1 - Phi_p_1) f1sbar]
+ *   Quadrature rule (both rules keep n/4 nodes per group, continuous in T and eta_e):
+ *     PANEL: scattering: Gauss-Legendre panels between sorted {0, max(0, mu-Delta), max(0, mu),
+ *            min(eps_j, max(0, mu) + 10 T)} plus a Gauss-Laguerre tail of scale T;
+ *            pair: Gauss-Legendre panels between sorted {0, min, max, clip(mu, 0, w), w}.
+ *     LAGUERRE: scattering uses one n-point Gauss-Laguerre rule E = T x; pair as PANEL.
+ *
+ * Array layouts (row-major, FP64, DEVICE memory owned by the caller):
+ *   T[nz] (MeV, > 0), eta_e[nz] (mu_e/T, finite; |eta_e| <= 700),
+ *   f[nz][3][2][ne]   species (nu_e, anti-nu_e, nu_x) x moment (f0, f1) x bin,
+ *   eta, chi, g_eta, g_chi, g_f: same [nz][3][2][ne] layout; g_T, g_eta_e: [nz].
+ * The energy grid (vtx_grid) is HOST memory: ne bin centres (strictly increasing, > 0) and
+ * ne bin volumes w_j = (e_{j+1}^3 - e_j^3)/3 in MeV^3.
+ *
+ * Execution: calls enqueue kernels on hip_stream (a hipStream_t; NULL = default stream) and
+ * return without synchronising. The first call for a given (device, grid, nquad, rule,
+ * sin2w) builds zone-independent tables (quadrature nodes, angular-weight coefficients)
+ * and uploads them with synchronous copies; they live until vtx_release() or process exit.
+ * Later calls allocate nothing. Calls are thread-safe.
+ *
+ * Errors: return VTX_OK (0) or a positive code; vtx_strerror() names it. Invalid arguments
+ * are detected on the host before any launch. Values outside the input domain are not
+ * checked on the device: they produce non-finite results confined to the offending zone.
+ */
+#ifndef VTX_RATES_H
+#define VTX_RATES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VTX_ABI_VERSION 1
+
+enum vtx_status {
+  VTX_OK = 0,
+  VTX_EINVAL = 1,   /* null pointer, bad sizes/options, unsorted or non-positive grid */
+  VTX_EDEVICE = 2,  /* no HIP device, or the current device is not gfx950 */
+  VTX_EHIP = 3,     /* a HIP runtime call or kernel launch failed */
+  VTX_ENOMEM = 4    /* table allocation failed */
+};
+
+enum vtx_precision {
+  VTX_FP64 = 0,   /* every step in FP64 */
+  VTX_MIXED = 1   /* FP32 quadrature bulk (nodes, Fermi-Dirac factors, angular weights,
+                     accumulation); FP64 angular-weight contraction, detailed-balance
+                     factors, Fermi-Dirac factors of zones with eta_e > eta_fp64, and the
+                     per-zone contraction */
+};
+
+enum vtx_rule { VTX_RULE_LAGUERRE = 0, VTX_RULE_PANEL = 1 };
+
+enum vtx_process { VTX_NES = 1, VTX_PAIR = 2 };
+
+typedef struct {
+  int32_t ne;          /* number of energy bins, 1..32 */
+  const double* eps;   /* [ne] bin centres, MeV, host memory */
+  const double* w;     /* [ne] bin volumes, MeV^3, host memory */
+} vtx_grid;
+
+typedef struct {
+  int32_t precision;   /* vtx_precision */
+  int32_t nquad;       /* nodes per kernel integral: multiple of 4 in [8, 64] */
+  int32_t rule;        /* vtx_rule */
+  uint32_t processes;  /* bitmask of vtx_process, nonzero */
+  double sin2w;        /* weak mixing angle sin^2(theta_W), default 0.2312 */
+  double eta_fp64;     /* mixed precision: zones with eta_e > eta_fp64 use FP64 Fermi-Dirac factors (30) */
+} vtx_opts;
+
+/* Fill *opts with the defaults: FP64, 48 nodes, PANEL, both processes, 0.2312, 30. */
+void vtx_opts_default(vtx_opts* opts);
+
+/*
+ * Forward: eta, chi for nzones zones (nzones >= 0; 0 is a no-op).
+ * Inputs T, eta_e, f; outputs eta, chi, all device pointers as laid out above.
+ */
+int vtx_rates_forward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
+                      const double* T, const double* eta_e, const double* f,
+                      double* eta, double* chi, void* hip_stream);
+
+/*
+ * Backward (vector-Jacobian product): given upstream gradients g_eta, g_chi of a scalar L,
+ * writes g_T = dL/dT (at fixed eta_e), g_eta_e = dL/deta_e (at fixed T) and g_f = dL/df.
+ * These are the exact derivatives of the discrete rule above, including the motion of the
+ * quadrature nodes with T and mu_e = eta_e T. The kernels are recomputed; nothing is saved
+ * from the forward call. All pointers are device memory; outputs are overwritten.
+ */
+int vtx_rates_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
+                       const double* T, const double* eta_e, const double* f,
+                       const double* g_eta, const double* g_chi,
+                       double* g_T, double* g_eta_e, double* g_f, void* hip_stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* vtx_strerror(int code);
+
+/* VTX_ABI_VERSION of the built library. */
+int vtx_abi_version(void);
+
+/* Free every cached table on every device (no call may be in flight). */
+void vtx_release(void);
+
+/*
+ * Host-side inspection of the zone-independent tables (no GPU needed; for tests).
+ * vtx_gauss_rule: kind 0 = Gauss-Legendre on [0, 1] (x, w), kind 1 = Gauss-Laguerre with
+ *   weights already multiplied by exp(x) (x, w exp(x)); n in [1, 64]. Arrays of n, host.
+ * vtx_eval_hpoly: evaluates the angular weight H from the library's coefficient tables:
+ *   process VTX_NES (requires e >= ep) or VTX_PAIR, comp = 2*(S-1) + l (S = 1, 2 for I, II),
+ *   at n energies E[] (host), into out[] (host).
+ */
+int vtx_gauss_rule(int kind, int n, double* x, double* w);
+int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const double* E, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VTX_RATES_H */

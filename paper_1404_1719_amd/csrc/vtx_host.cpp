@@ -1,0 +1,471 @@
+// Host layer of the rates library: argument checks, zone-independent tables (quadrature
+// nodes, angular-weight coefficients), a per-device table cache and the C entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/vtx_rates.h"
+#include "hpoly_gen.h"
+#include "vtx_internal.h"
+
+namespace vtx {
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// Gauss rules. Nodes: eigenvalues of the symmetric tridiagonal Jacobi matrix of the
+// three-term recurrence (Golub-Welsch), found by Sturm-sequence bisection, then polished
+// by Newton steps on the orthogonal polynomial; weights from the polynomial's
+// derivative at the node, which keeps the tiny Laguerre weights accurate to full relative
+// precision.
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix (diag d, off-diagonal
+// e[k] coupling rows k-1 and k): the count of negative pivots of the LDL^T factorisation of
+// J - x I (Sylvester's law of inertia).
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int neg = 0;
+  double q = 1.0;
+  for (size_t k = 0; k < d.size(); ++k) {
+    const double off = (k > 0) ? e[k] * e[k] / q : 0.0;
+    q = d[k] - x - off;
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++neg;
+  }
+  return neg;
+}
+
+// All eigenvalues, ascending, by bisection on the Sturm count inside the Gershgorin bounds.
+bool tridiag_eigenvalues(std::vector<double>& d, const std::vector<double>& e) {
+  const int n = (int)d.size();
+  double lo = 0.0, hi = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double r = (k > 0 ? std::fabs(e[k]) : 0.0) + (k + 1 < n ? std::fabs(e[k + 1]) : 0.0);
+    lo = (k == 0) ? d[k] - r : std::fmin(lo, d[k] - r);
+    hi = (k == 0) ? d[k] + r : std::fmax(hi, d[k] + r);
+  }
+  std::vector<double> ev(n);
+  for (int m = 0; m < n; ++m) {
+    // smallest x with at least m + 1 eigenvalues below it
+    double a = lo, b = hi;
+    for (int it = 0; it < 200 && b - a > 4e-16 * std::fmax(1.0, std::fabs(a) + std::fabs(b)); ++it) {
+      const double c = 0.5 * (a + b);
+      if (sturm_count(d, e, c) > m) b = c; else a = c;
+    }
+    ev[m] = 0.5 * (a + b);
+  }
+  d = ev;
+  return true;
+}
+
+// Legendre P_n and P_{n-1} at x.
+void legendre_pn(int n, double x, double& pn, double& pn1) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    pn = 1.0;
+    pn1 = 0.0;
+    return;
+  }
+  for (int k = 1; k < n; ++k) {
+    const double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  pn1 = p0;
+}
+
+// Laguerre L_n and L_{n-1} at x.
+void laguerre_ln(int n, double x, double& ln, double& ln1) {
+  double l0 = 1.0, l1 = 1.0 - x;
+  if (n == 0) {
+    ln = 1.0;
+    ln1 = 0.0;
+    return;
+  }
+  for (int k = 1; k < n; ++k) {
+    const double l2 = ((2 * k + 1 - x) * l1 - k * l0) / (k + 1);
+    l0 = l1;
+    l1 = l2;
+  }
+  ln = l1;
+  ln1 = l0;
+}
+
+// kind 0: Gauss-Legendre on [0, 1]; kind 1: Gauss-Laguerre, weights times exp(x).
+bool gauss_rule(int kind, int n, double* x, double* w) {
+  std::vector<double> d(n), e(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    if (kind == 0) {
+      d[k] = 0.0;
+      if (k > 0) e[k] = k / std::sqrt(4.0 * k * k - 1.0);
+    } else {
+      d[k] = 2.0 * k + 1.0;
+      if (k > 0) e[k] = k;
+    }
+  }
+  if (!tridiag_eigenvalues(d, e)) return false;
+  const std::vector<double>& r = d;
+  for (int k = 0; k < n; ++k) {
+    double xx = r[k];
+    double der = 0.0;
+    for (int it = 0; it < 4; ++it) {
+      double pn, pn1;
+      if (kind == 0) {
+        legendre_pn(n, xx, pn, pn1);
+        der = n * (xx * pn - pn1) / (xx * xx - 1.0);
+      } else {
+        laguerre_ln(n, xx, pn, pn1);
+        der = n * (pn - pn1) / xx;
+      }
+      const double dx = pn / der;
+      xx -= dx;
+      if (std::fabs(dx) <= 1e-16 * std::fabs(xx)) break;
+    }
+    double pn, pn1;
+    if (kind == 0) {
+      legendre_pn(n, xx, pn, pn1);
+      der = n * (xx * pn - pn1) / (xx * xx - 1.0);
+      x[k] = 0.5 * (xx + 1.0);
+      w[k] = 1.0 / ((1.0 - xx * xx) * der * der);   // (2/((1-x^2)P'^2)) / 2
+    } else {
+      laguerre_ln(n, xx, pn, pn1);
+      der = n * (pn - pn1) / xx;
+      x[k] = xx;
+      w[k] = std::exp(xx - std::log(xx) - 2.0 * std::log(std::fabs(der)));
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// Angular-weight coefficient tables (zone independent), prefactor G_F^2/(pi e_i e_j) folded in.
+
+void nes_coefficients(double e, double ep, NesCoef& C) {
+  double lo[4][8], hi[4][3];
+  vtx_hpoly_nes(e, ep, lo, hi);
+  const double pref = kGF * kGF / (M_PI * e * ep);
+  for (int c = 0; c < 4; ++c) {
+    for (int d = 0; d < 8; ++d) C.lo[c][d] = pref * lo[c][d];
+    for (int d = 0; d < 3; ++d) C.hi[c][d] = pref * hi[c][d];
+    C.hi[c][3] = 0.0;
+  }
+}
+
+// H^{P,I}_l(e_i, e_j, .): for e_i >= e_j the generator's S = I comps, else its S = II comps
+// with the arguments swapped (H^{P,I}(a, b, E) = H^{P,II}(b, a, E)).
+void pair_coefficients(double ei, double ej, PairCoef& C) {
+  double A[4][8], B[4][3], Cc[4][8];
+  const bool ordered = ei >= ej;
+  vtx_hpoly_pair(ordered ? ei : ej, ordered ? ej : ei, A, B, Cc);
+  const double pref = kGF * kGF / (M_PI * ei * ej);
+  for (int l = 0; l < 2; ++l) {
+    const int comp = ordered ? l : 2 + l;
+    for (int d = 0; d < 8; ++d) {
+      C.piece[0][l][d] = pref * A[comp][d];
+      C.piece[1][l][d] = d < 3 ? pref * B[comp][d] : 0.0;
+      C.piece[2][l][d] = pref * Cc[comp][d];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Table cache
+
+struct Plan {
+  int device;
+  int ne, nquad, rule;
+  double sin2w;
+  std::vector<double> eps, w;
+  DevPlan dp;              // pointers into the device buffer below
+  void* dbuf = nullptr;
+};
+
+std::mutex g_mu;
+std::vector<std::unique_ptr<Plan>> g_plans;
+std::vector<int> g_dev_ok;   // per device: 0 unknown, 1 gfx950, -1 other
+
+void couplings(double s2w, double beta[3][2]) {
+  const double cve = 0.5 + 2.0 * s2w;
+  beta[0][0] = (cve + 0.5) * (cve + 0.5);
+  beta[0][1] = (cve - 0.5) * (cve - 0.5);
+  beta[1][0] = beta[0][1];
+  beta[1][1] = beta[0][0];
+  const double cvx = -0.5 + 2.0 * s2w;
+  const double avg = 0.5 * ((cvx - 0.5) * (cvx - 0.5) + (cvx + 0.5) * (cvx + 0.5));
+  beta[2][0] = beta[2][1] = avg;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
+  std::unique_ptr<Plan> p(new Plan);
+  p->device = device;
+  p->ne = g->ne;
+  p->nquad = o->nquad;
+  p->rule = o->rule;
+  p->sin2w = o->sin2w;
+  p->eps.assign(g->eps, g->eps + g->ne);
+  p->w.assign(g->w, g->w + g->ne);
+  const int ne = g->ne, ntn = ne * (ne + 1) / 2, ntp = ne * ne, m4 = o->nquad / 4;
+  const int nlag = (o->rule == VTX_RULE_LAGUERRE) ? o->nquad : m4;
+  // host images
+  std::vector<double> c0w(ne);
+  const double c0 = 1.0 / (4.0 * M_PI * M_PI * kHbarC);
+  for (int j = 0; j < ne; ++j) c0w[j] = c0 * g->w[j];
+  std::vector<int> nes_ij(ntn);
+  std::vector<NesCoef> ncoef(ntn);
+  for (int i = 0, t = 0; i < ne; ++i)
+    for (int j = 0; j <= i; ++j, ++t) {
+      nes_ij[t] = i | (j << 8);
+      nes_coefficients(g->eps[i], g->eps[j], ncoef[t]);
+    }
+  std::vector<PairCoef> pcoef(ntp);
+  for (int i = 0; i < ne; ++i)
+    for (int j = 0; j < ne; ++j) pair_coefficients(g->eps[i], g->eps[j], pcoef[i * ne + j]);
+  std::vector<double> tx(m4), tw(m4), lx(nlag), lw(nlag);
+  if (!gauss_rule(0, m4, tx.data(), tw.data()) || !gauss_rule(1, nlag, lx.data(), lw.data())) return VTX_EINVAL;
+  std::vector<double4> leg64(m4), lag64(nlag);
+  std::vector<float4> leg32(m4), lag32(nlag);
+  for (int k = 0; k < m4; ++k) {
+    leg64[k] = make_double4(tx[k], 1.0 - tx[k], tw[k], 0.0);
+    leg32[k] = make_float4((float)tx[k], (float)(1.0 - tx[k]), (float)tw[k], 0.f);
+  }
+  for (int k = 0; k < nlag; ++k) {
+    lag64[k] = make_double4(lx[k], lx[k], lw[k], 0.0);
+    lag32[k] = make_float4((float)lx[k], (float)lx[k], (float)lw[k], 0.f);
+  }
+  // one device buffer
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    const size_t o0 = off;
+    off = align256(off + bytes);
+    return o0;
+  };
+  const size_t o_eps = place(sizeof(double) * ne), o_c0w = place(sizeof(double) * ne);
+  const size_t o_ij = place(sizeof(int) * ntn), o_nc = place(sizeof(NesCoef) * ntn);
+  const size_t o_pc = place(sizeof(PairCoef) * ntp);
+  const size_t o_l64 = place(sizeof(double4) * m4), o_g64 = place(sizeof(double4) * nlag);
+  const size_t o_l32 = place(sizeof(float4) * m4), o_g32 = place(sizeof(float4) * nlag);
+  std::vector<unsigned char> img(off, 0);
+  auto put = [&](size_t o2, const void* src, size_t bytes) { std::memcpy(img.data() + o2, src, bytes); };
+  put(o_eps, g->eps, sizeof(double) * ne);
+  put(o_c0w, c0w.data(), sizeof(double) * ne);
+  put(o_ij, nes_ij.data(), sizeof(int) * ntn);
+  put(o_nc, ncoef.data(), sizeof(NesCoef) * ntn);
+  put(o_pc, pcoef.data(), sizeof(PairCoef) * ntp);
+  put(o_l64, leg64.data(), sizeof(double4) * m4);
+  put(o_g64, lag64.data(), sizeof(double4) * nlag);
+  put(o_l32, leg32.data(), sizeof(float4) * m4);
+  put(o_g32, lag32.data(), sizeof(float4) * nlag);
+  if (hipMalloc(&p->dbuf, off) != hipSuccess) return VTX_ENOMEM;
+  if (hipMemcpy(p->dbuf, img.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->dbuf);
+    return VTX_EHIP;
+  }
+  unsigned char* b = (unsigned char*)p->dbuf;
+  DevPlan& d = p->dp;
+  d.ne = ne;
+  d.ntn = ntn;
+  d.ntp = ntp;
+  d.m4 = m4;
+  d.rule = o->rule;
+  d.nlag = nlag;
+  couplings(o->sin2w, d.beta);
+  d.eps = (const double*)(b + o_eps);
+  d.c0w = (const double*)(b + o_c0w);
+  d.nes_ij = (const int*)(b + o_ij);
+  d.nes_coef = (const NesCoef*)(b + o_nc);
+  d.pair_coef = (const PairCoef*)(b + o_pc);
+  d.leg64 = (const double4*)(b + o_l64);
+  d.lag64 = (const double4*)(b + o_g64);
+  d.leg32 = (const float4*)(b + o_l32);
+  d.lag32 = (const float4*)(b + o_g32);
+  *out = p.get();
+  g_plans.push_back(std::move(p));
+  return VTX_OK;
+}
+
+int check_args(const vtx_grid* g, const vtx_opts* o, int64_t nz) {
+  if (!g || !o || nz < 0) return VTX_EINVAL;
+  if (g->ne < 1 || g->ne > kMaxNE || !g->eps || !g->w) return VTX_EINVAL;
+  for (int i = 0; i < g->ne; ++i) {
+    if (!(g->eps[i] > 0.0) || !(g->w[i] > 0.0) || !std::isfinite(g->eps[i]) || !std::isfinite(g->w[i]))
+      return VTX_EINVAL;
+    if (i > 0 && !(g->eps[i] > g->eps[i - 1])) return VTX_EINVAL;
+  }
+  if (o->precision != VTX_FP64 && o->precision != VTX_MIXED) return VTX_EINVAL;
+  if (o->nquad < 8 || o->nquad > kMaxNquad || (o->nquad % 4) != 0) return VTX_EINVAL;
+  if (o->rule != VTX_RULE_LAGUERRE && o->rule != VTX_RULE_PANEL) return VTX_EINVAL;
+  if (o->processes == 0 || (o->processes & ~3u) != 0) return VTX_EINVAL;
+  if (!std::isfinite(o->sin2w) || !std::isfinite(o->eta_fp64)) return VTX_EINVAL;
+  if (nz > 0x7fffffffLL) return VTX_EINVAL;
+  return VTX_OK;
+}
+
+// Current device must be gfx950. Returns the device ordinal or a negative status.
+int current_device(int* dev) {
+  if (getenv("VTX_FAULT_INJECT_HIP")) return -VTX_EHIP;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return -VTX_EDEVICE;
+  if (hipGetDevice(dev) != hipSuccess) return -VTX_EHIP;
+  if ((int)g_dev_ok.size() < n) g_dev_ok.resize(n, 0);
+  if (g_dev_ok[*dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return -VTX_EHIP;
+    g_dev_ok[*dev] = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+  }
+  return g_dev_ok[*dev] == 1 ? 0 : -VTX_EDEVICE;
+}
+
+int get_plan(const vtx_grid* g, const vtx_opts* o, DevPlan* out) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  const int st = current_device(&dev);
+  if (st < 0) return -st;
+  Plan* hit = nullptr;
+  for (auto& p : g_plans) {
+    if (p->device == dev && p->ne == g->ne && p->nquad == o->nquad && p->rule == o->rule && p->sin2w == o->sin2w &&
+        std::memcmp(p->eps.data(), g->eps, sizeof(double) * g->ne) == 0 &&
+        std::memcmp(p->w.data(), g->w, sizeof(double) * g->ne) == 0) {
+      hit = p.get();
+      break;
+    }
+  }
+  if (!hit) {
+    const int rc = build_plan(dev, g, o, &hit);
+    if (rc != VTX_OK) return rc;
+  }
+  *out = hit->dp;
+  out->processes = (int)o->processes;
+  out->precision = o->precision;
+  out->eta_fp64 = o->eta_fp64;
+  return VTX_OK;
+}
+
+}  // namespace
+}  // namespace vtx
+
+extern "C" {
+
+void vtx_opts_default(vtx_opts* o) {
+  if (!o) return;
+  o->precision = VTX_FP64;
+  o->nquad = 48;
+  o->rule = VTX_RULE_PANEL;
+  o->processes = VTX_NES | VTX_PAIR;
+  o->sin2w = 0.2312;
+  o->eta_fp64 = 30.0;
+}
+
+int vtx_rates_forward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
+                      const double* eta_e, const double* f, double* eta, double* chi, void* hip_stream) {
+  int rc = vtx::check_args(grid, opts, nzones);
+  if (rc != VTX_OK) return rc;
+  if (nzones == 0) return VTX_OK;
+  if (!T || !eta_e || !f || !eta || !chi) return VTX_EINVAL;
+  vtx::DevPlan P;
+  rc = vtx::get_plan(grid, opts, &P);
+  if (rc != VTX_OK) return rc;
+  const hipError_t e = vtx::launch_forward(P, nzones, T, eta_e, f, eta, chi, (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+
+int vtx_rates_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
+                       const double* eta_e, const double* f, const double* g_eta, const double* g_chi, double* g_T,
+                       double* g_eta_e, double* g_f, void* hip_stream) {
+  int rc = vtx::check_args(grid, opts, nzones);
+  if (rc != VTX_OK) return rc;
+  if (nzones == 0) return VTX_OK;
+  if (!T || !eta_e || !f || !g_eta || !g_chi || !g_T || !g_eta_e || !g_f) return VTX_EINVAL;
+  vtx::DevPlan P;
+  rc = vtx::get_plan(grid, opts, &P);
+  if (rc != VTX_OK) return rc;
+  const hipError_t e = vtx::launch_backward(P, nzones, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f,
+                                            (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+
+const char* vtx_strerror(int code) {
+  switch (code) {
+    case VTX_OK: return "ok";
+    case VTX_EINVAL: return "invalid argument";
+    case VTX_EDEVICE: return "no gfx950 HIP device";
+    case VTX_EHIP: return "HIP runtime error";
+    case VTX_ENOMEM: return "device allocation failed";
+    default: return "unknown status";
+  }
+}
+
+int vtx_abi_version(void) { return VTX_ABI_VERSION; }
+
+void vtx_release(void) {
+  std::lock_guard<std::mutex> lock(vtx::g_mu);
+  for (auto& p : vtx::g_plans)
+    if (p->dbuf) (void)hipFree(p->dbuf);
+  vtx::g_plans.clear();
+}
+
+int vtx_gauss_rule(int kind, int n, double* x, double* w) {
+  if ((kind != 0 && kind != 1) || n < 1 || n > vtx::kMaxNquad || !x || !w) return VTX_EINVAL;
+  return vtx::gauss_rule(kind, n, x, w) ? VTX_OK : VTX_EINVAL;
+}
+
+int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const double* E, double* out) {
+  if (comp < 0 || comp > 3 || !(e > 0) || !(ep > 0) || n < 0 || (n > 0 && (!E || !out))) return VTX_EINVAL;
+  if (process == VTX_NES) {
+    if (e < ep) return VTX_EINVAL;
+    double lo[4][8], hi[4][3];
+    vtx_hpoly_nes(e, ep, lo, hi);
+    for (int k = 0; k < n; ++k) {
+      const double u = E[k] / ep;
+      double s = 0.0;
+      if (u < 1.0)
+        for (int d = 7; d >= 0; --d) s = s * u + lo[comp][d];
+      else
+        for (int d = 2; d >= 0; --d) s = s * u + hi[comp][d];
+      out[k] = E[k] < 0 ? 0.0 : s;
+    }
+    return VTX_OK;
+  }
+  if (process == VTX_PAIR) {
+    // comp S = I/II, l; evaluated through the tables of the (e, ep) task for S = I and of
+    // the (ep, e) task for S = II.
+    const int S = comp >> 1, l = comp & 1;
+    vtx::PairCoef C;
+    const double a = S == 0 ? e : ep, b = S == 0 ? ep : e;
+    vtx::pair_coefficients(a, b, C);
+    const double pref = vtx::kGF * vtx::kGF / (M_PI * e * ep);
+    const double mn = std::fmin(e, ep), mx = std::fmax(e, ep), w = e + ep;
+    for (int k = 0; k < n; ++k) {
+      const double x = E[k];
+      int piece;
+      double v;
+      if (x <= 0 || x >= w) {
+        out[k] = 0.0;
+        continue;
+      }
+      if (x <= mn) {
+        piece = 0;
+        v = x / mn;
+      } else if (x <= mx) {
+        piece = 1;
+        v = x / mx;
+      } else {
+        piece = 2;
+        v = (w - x) / mn;
+      }
+      double s = 0.0;
+      for (int d = 7; d >= 0; --d) s = s * v + C.piece[piece][l][d];
+      out[k] = s / pref;
+    }
+    return VTX_OK;
+  }
+  return VTX_EINVAL;
+}
+
+}  // extern "C"

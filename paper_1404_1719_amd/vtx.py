@@ -1,0 +1,216 @@
+"""Python binding of the rates library (ctypes over include/vtx_rates.h).
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of
+``lib/libvtxrates.so``. Tensors must be CUDA (HIP) float64 and contiguous; calls are
+enqueued on the current torch stream (or the given one) and do not synchronise.
+Raises RuntimeError if the library is not built or a call fails -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libvtxrates.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vtx_rates.h")
+
+VTX_OK, VTX_EINVAL, VTX_EDEVICE, VTX_EHIP, VTX_ENOMEM = 0, 1, 2, 3, 4
+VTX_FP64, VTX_MIXED = 0, 1
+VTX_RULE_LAGUERRE, VTX_RULE_PANEL = 0, 1
+VTX_NES, VTX_PAIR = 1, 2
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ne", ctypes.c_int32), ("eps", ctypes.POINTER(ctypes.c_double)),
+                ("w", ctypes.POINTER(ctypes.c_double))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("nquad", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("processes", ctypes.c_uint32), ("sin2w", ctypes.c_double), ("eta_fp64", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library():
+    """Load (once) and return the ctypes handle; raises if the library was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run python -m paper_1404_1719_amd.build_lib)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    lib.vtx_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    lib.vtx_opts_default.restype = None
+    lib.vtx_rates_forward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp, vp, vp]
+    lib.vtx_rates_forward.restype = ctypes.c_int
+    lib.vtx_rates_backward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64,
+                                       vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.vtx_rates_backward.restype = ctypes.c_int
+    lib.vtx_strerror.argtypes = [ctypes.c_int]
+    lib.vtx_strerror.restype = ctypes.c_char_p
+    lib.vtx_abi_version.argtypes = []
+    lib.vtx_abi_version.restype = ctypes.c_int
+    lib.vtx_release.argtypes = []
+    lib.vtx_release.restype = None
+    lib.vtx_gauss_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+    lib.vtx_gauss_rule.restype = ctypes.c_int
+    lib.vtx_eval_hpoly.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+    lib.vtx_eval_hpoly.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def declared_functions():
+    """Function names declared in include/vtx_rates.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\**\s+\**(vtx_[a-z_0-9]+)\s*\(", txt, re.M)))
+
+
+def _check(rc, what):
+    if rc != VTX_OK:
+        msg = library().vtx_strerror(rc).decode()
+        raise RuntimeError(f"{what} failed: {msg} (status {rc})")
+
+
+class GridHandle:
+    """Host copy of an energy grid in the layout the ABI takes (kept alive with the arrays)."""
+
+    def __init__(self, eps, w):
+        self.eps = np.ascontiguousarray(eps, dtype=np.float64)
+        self.w = np.ascontiguousarray(w, dtype=np.float64)
+        if self.eps.shape != self.w.shape or self.eps.ndim != 1:
+            raise ValueError("eps and w must be 1-D of equal length")
+        self.c = Grid(self.eps.shape[0], self.eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      self.w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+    @property
+    def ne(self):
+        return self.eps.shape[0]
+
+
+def make_opts(precision="fp64", nquad=48, rule="panel", processes=VTX_NES | VTX_PAIR, sin2w=0.2312,
+              eta_fp64=30.0):
+    o = Opts()
+    library().vtx_opts_default(ctypes.byref(o))
+    o.precision = {"fp64": VTX_FP64, "mixed": VTX_MIXED}[precision] if isinstance(precision, str) else precision
+    o.nquad = nquad
+    o.rule = {"laguerre": VTX_RULE_LAGUERRE, "panel": VTX_RULE_PANEL}[rule] if isinstance(rule, str) else rule
+    o.processes = processes
+    o.sin2w = sin2w
+    o.eta_fp64 = eta_fp64
+    return o
+
+
+def _dev_ptr(t, name, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def forward(grid: GridHandle, opts: Opts, T, eta_e, f, eta=None, chi=None, stream=None):
+    """eta, chi [nz, 3, 2, ne] for T[nz], eta_e[nz], f[nz, 3, 2, ne] (CUDA float64)."""
+    import torch
+    nz = T.shape[0]
+    shp = (nz, 3, 2, grid.ne)
+    if eta is None:
+        eta = torch.empty(shp, dtype=torch.float64, device=T.device)
+    if chi is None:
+        chi = torch.empty(shp, dtype=torch.float64, device=T.device)
+    rc = library().vtx_rates_forward(ctypes.byref(grid.c), ctypes.byref(opts), nz, _dev_ptr(T, "T", (nz,)),
+                                     _dev_ptr(eta_e, "eta_e", (nz,)), _dev_ptr(f, "f", shp),
+                                     _dev_ptr(eta, "eta", shp), _dev_ptr(chi, "chi", shp), _stream_handle(stream))
+    _check(rc, "vtx_rates_forward")
+    return eta, chi
+
+
+def backward(grid: GridHandle, opts: Opts, T, eta_e, f, g_eta, g_chi, g_T=None, g_eta_e=None, g_f=None,
+             stream=None):
+    """(g_T, g_eta_e, g_f): vector-Jacobian product of (eta, chi) with (g_eta, g_chi)."""
+    import torch
+    nz = T.shape[0]
+    shp = (nz, 3, 2, grid.ne)
+    if g_T is None:
+        g_T = torch.empty((nz,), dtype=torch.float64, device=T.device)
+    if g_eta_e is None:
+        g_eta_e = torch.empty((nz,), dtype=torch.float64, device=T.device)
+    if g_f is None:
+        g_f = torch.empty(shp, dtype=torch.float64, device=T.device)
+    rc = library().vtx_rates_backward(
+        ctypes.byref(grid.c), ctypes.byref(opts), nz, _dev_ptr(T, "T", (nz,)), _dev_ptr(eta_e, "eta_e", (nz,)),
+        _dev_ptr(f, "f", shp), _dev_ptr(g_eta, "g_eta", shp), _dev_ptr(g_chi, "g_chi", shp),
+        _dev_ptr(g_T, "g_T", (nz,)), _dev_ptr(g_eta_e, "g_eta_e", (nz,)), _dev_ptr(g_f, "g_f", shp),
+        _stream_handle(stream))
+    _check(rc, "vtx_rates_backward")
+    return g_T, g_eta_e, g_f
+
+
+def gauss_rule(kind: int, n: int):
+    """Host-side Gauss rule of the library: kind 0 Legendre on [0, 1], 1 Laguerre (w e^x)."""
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _check(library().vtx_gauss_rule(kind, n, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "vtx_gauss_rule")
+    return x, w
+
+
+def eval_hpoly(process: int, comp: int, e: float, ep: float, E):
+    """Host-side angular weight from the library's coefficient tables."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    out = np.zeros_like(E)
+    _check(library().vtx_eval_hpoly(process, comp, e, ep, E.size,
+                                    E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "vtx_eval_hpoly")
+    return out
+
+
+def _make_function():
+    import torch
+
+    class VtxRates(torch.autograd.Function):
+        """(T, eta_e, f) -> (eta, chi) with the hand-written backward kernel."""
+
+        @staticmethod
+        def forward(ctx, T, eta_e, f, grid, opts):
+            ctx.grid, ctx.opts = grid, opts
+            ctx.save_for_backward(T, eta_e, f)
+            return forward(grid, opts, T.contiguous(), eta_e.contiguous(), f.contiguous())
+
+        @staticmethod
+        def backward(ctx, g_eta, g_chi):
+            T, eta_e, f = ctx.saved_tensors
+            if g_eta is None:
+                g_eta = torch.zeros_like(f)
+            if g_chi is None:
+                g_chi = torch.zeros_like(f)
+            gT, gE, gf = backward(ctx.grid, ctx.opts, T, eta_e, f, g_eta.contiguous(), g_chi.contiguous())
+            return gT, gE, gf, None, None
+
+    return VtxRates
+
+
+_fn = None
+
+
+def rates(T, eta_e, f, grid: GridHandle, opts: Opts):
+    """Differentiable (eta, chi) = rates(T, eta_e, f)."""
+    global _fn
+    if _fn is None:
+        _fn = _make_function()
+    return _fn.apply(T, eta_e, f, grid, opts)
