@@ -1,0 +1,272 @@
+"""Benchmark: zone x (eps, eps') kernel evaluations per second, forward + backward.
+
+One step = forward (eta, chi) + backward (g_T, g_eta_e, g_f) over every zone of the
+workload, inputs resident in HBM, in chunks issued back to back on one compute stream.
+Default workload: 4096 rays x 600 zones, NE = 21, 64-node rule, mixed precision, 8 chunks.
+Prints ONE JSON line (rank 0). Units: zones * NE^2 per second (each unit covers 3 species,
+both processes, l = 0, 1, one forward and one backward evaluation).
+
+Also reported: the same step in plain FP64 (speedup of mixed over FP64), the maximal
+relative error per output against the FP64 oracle on sampled zones, a roofline entry for
+the dominant kernel (algorithmic FLOPs per launch / measured launch time), and the oracle
+timed on the host cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1404_1719_amd import synth  # noqa: E402
+
+# Algorithmic floating-point work per quadrature node (transcendental = 1 op, fma = 2):
+#   node coordinate and Fermi-Dirac arguments 4; two exp, two adds, one product, one
+#   division and the numerator select-product: 7; weight x blocking 1; each angular-weight
+#   component a degree-7 polynomial (Horner, 7 fma = 14) plus its accumulation (2).
+#   Scattering nodes carry 4 components, pair nodes 2.  Backward adds, per node, the
+#   derivative of the blocking factor along T, eta_e and E (10), node motion (4), the
+#   adjoint-weighted polynomial and its derivative (14 + 12) and two accumulations (8).
+FLOP_FWD_NES, FLOP_FWD_PAIR = 4 + 7 + 1 + 4 * 16, 4 + 7 + 1 + 2 * 16
+FLOP_BWD_EXTRA = 10 + 4 + 26 + 8
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}   # MI355X vector peaks, FP32 / FP64
+
+
+def algorithmic_flops_per_zone(ne, nquad, backward):
+    ntn, ntp = ne * (ne + 1) // 2, ne * ne
+    f_nes = FLOP_FWD_NES + (FLOP_BWD_EXTRA if backward else 0)
+    f_pair = FLOP_FWD_PAIR + (FLOP_BWD_EXTRA if backward else 0)
+    contraction = 3 * ne * ne * (24 if backward else 20)
+    return nquad * (ntn * f_nes + ntp * f_pair) + contraction
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("vtx_kernels.hip", "vtx_internal.h"):
+        with open(os.path.join(ROOT, "paper_1404_1719_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_tag):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, budget_s=20.0):
+    """Oracle forward + backward on a bounded zone sample, spread over the host cores."""
+    from concurrent.futures import ProcessPoolExecutor
+    ncores = max(1, min(16, os.cpu_count() or 1))
+    # calibrate on one zone, then size the sample to the budget
+    t0 = time.perf_counter()
+    _oracle_chunk((wl.name, [0]))
+    per_zone = time.perf_counter() - t0
+    nz = int(max(ncores, min(256, budget_s * ncores / max(per_zone, 1e-3))))
+    nz = max(ncores, (nz // ncores) * ncores)
+    chunks = [(wl.name, list(range(k, nz, ncores))) for k in range(ncores)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=ncores) as ex:
+        list(ex.map(_oracle_chunk, chunks))
+    dt = time.perf_counter() - t0
+    units = nz * wl.ne * wl.ne
+    return {"value": units / dt, "unit": "zone*(eps,eps')/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{nz} zones of the {wl.name} workload, forward + complex-step backward, "
+                      f"{ncores} processes, {dt:.1f} s"}
+
+
+def _oracle_chunk(arg):
+    name, idx = arg
+    from oracle import grad as ograd
+    from oracle import rates as orates
+    wl = synth.WORKLOADS[name]
+    inp = synth.subset(synth.make_inputs(name, nzones=max(idx) + 1), idx)
+    opts = orates.Options(nquad=wl.nquad, rule=wl.rule)
+    orates.forward(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, opts)
+    ge, gc = synth.random_gradients(len(idx), wl.ne, 9)
+    ograd.vjp(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, ge, gc, opts)
+    return len(idx)
+
+
+def sampled_errors(inp, eta, chi, wl, count=6):
+    """Max relative error per output on sampled zones vs the FP64 oracle (same rule)."""
+    import torch
+    from oracle import rates as orates
+    idx = synth.sample_zones(inp, count, seed=11)
+    it = torch.from_numpy(idx).to(eta.device)
+    e = eta.index_select(0, it).cpu().numpy()
+    c = chi.index_select(0, it).cpu().numpy()
+    sub = synth.subset(inp, idx)
+    re, rc, ae, ac = orates.forward_with_scale(sub.eps, sub.w, sub.T, sub.eta_e, sub.f,
+                                               orates.Options(nquad=wl.nquad, rule=wl.rule))
+
+    def err(y, r, a):
+        return float(np.max(np.abs(y - r) / np.maximum(np.maximum(np.abs(r), 1e-3 * a), 1e-290)))
+
+    return {"eta0": err(e[:, :, 0], re[:, :, 0], ae[:, :, 0]), "eta1": err(e[:, :, 1], re[:, :, 1], ae[:, :, 1]),
+            "chi0": err(c[:, :, 0], rc[:, :, 0], ac[:, :, 0]), "chi1": err(c[:, :, 1], rc[:, :, 1], ac[:, :, 1]),
+            "zones": len(idx)}
+
+
+class Runner:
+    """Device-resident buffers of one workload and the chunked two-stream step."""
+
+    def __init__(self, inp, wl, precision, chunks):
+        import torch
+        from paper_1404_1719_amd import vtx
+        self.torch, self.vtx = torch, vtx
+        dev = torch.device("cuda:0")
+        self.grid = vtx.GridHandle(inp.eps, inp.w)
+        self.opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+        self.nz, self.ne = inp.T.shape[0], wl.ne
+        self.T = torch.from_numpy(inp.T).to(dev)
+        self.E = torch.from_numpy(inp.eta_e).to(dev)
+        self.f = torch.from_numpy(inp.f).to(dev)
+        shp = (self.nz, 3, 2, self.ne)
+        g = torch.Generator(device=dev)
+        g.manual_seed(synth.SEED_BASE + 3000)
+        self.g_eta = torch.randn(shp, dtype=torch.float64, device=dev, generator=g)
+        self.g_chi = torch.randn(shp, dtype=torch.float64, device=dev, generator=g)
+        self.eta = torch.empty(shp, dtype=torch.float64, device=dev)
+        self.chi = torch.empty(shp, dtype=torch.float64, device=dev)
+        self.gT = torch.empty((self.nz,), dtype=torch.float64, device=dev)
+        self.gE = torch.empty((self.nz,), dtype=torch.float64, device=dev)
+        self.gf = torch.empty(shp, dtype=torch.float64, device=dev)
+        self.streams = [torch.cuda.Stream(device=dev)]   # default priority
+        bounds = np.linspace(0, self.nz, chunks + 1).astype(np.int64)
+        self.chunks = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+
+    def step(self, events=None):
+        """One forward + backward pass over all chunks, issued on one compute stream.
+
+        With inputs resident in HBM there are no transfers to hide and every chunk fills the
+        chip (hundreds of thousands of workgroups), so chunks run back to back; events
+        bracket every launch so that launch durations come from the timed region itself."""
+        torch, vtx = self.torch, self.vtx
+        s = self.streams[0]
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for a, b in self.chunks:
+                ev = None
+                if events is not None:
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                    ev[0].record(s)
+                vtx.forward(self.grid, self.opts, self.T[a:b], self.E[a:b], self.f[a:b], self.eta[a:b],
+                            self.chi[a:b], stream=s)
+                if ev is not None:
+                    ev[1].record(s)
+                vtx.backward(self.grid, self.opts, self.T[a:b], self.E[a:b], self.f[a:b], self.g_eta[a:b],
+                             self.g_chi[a:b], self.gT[a:b], self.gE[a:b], self.gf[a:b], stream=s)
+                if ev is not None:
+                    ev[2].record(s)
+                    events.append((b - a, ev))
+        torch.cuda.current_stream().wait_stream(s)
+
+    def timed(self, steps, warmup):
+        """Seconds per step over `steps` timed steps, and the per-launch event records."""
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        events = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step(events)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(steps, 1)
+        self.events = events
+        return dt
+
+    def launch_times(self):
+        """Average forward / backward launch durations (ms) and zones per launch, from the
+        events of the timed region."""
+        fwd = [ev[0].elapsed_time(ev[1]) for _, ev in self.events]
+        bwd = [ev[1].elapsed_time(ev[2]) for _, ev in self.events]
+        zones = [n for n, _ in self.events]
+        return float(np.mean(fwd)), float(np.mean(bwd)), float(np.mean(zones))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["mixed", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=2, help="steps of the FP64 comparison run (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-errors", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; multi-GPU runs are not part of this build "
+              "(zones shard by ray blocks with no communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    wl = synth.WORKLOADS[args.workload]
+    precision = args.precision or wl.precision
+    print(f"[bench] drawing workload {wl.name}: {wl.nzones} zones, NE={wl.ne}, n={wl.nquad}", file=sys.stderr,
+          flush=True)
+    inp = synth.make_inputs(wl.name)
+    run = Runner(inp, wl, precision, wl.chunks)
+    print(f"[bench] {precision}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    t_step = run.timed(args.steps, args.warmup)
+    units = wl.nzones * wl.ne * wl.ne
+    value = units / t_step
+    t_fwd, t_bwd, zl = run.launch_times()
+    errors = None if args.no_errors else sampled_errors(inp, run.eta, run.chi, wl)
+    del run
+    torch.cuda.empty_cache()
+
+    # roofline of the dominant kernel (backward): algorithmic FLOPs per launch / launch time
+    dom_ms, dom_bwd = (t_bwd, True) if t_bwd >= t_fwd else (t_fwd, False)
+    flops = algorithmic_flops_per_zone(wl.ne, wl.nquad, dom_bwd) * zl
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    tag = f"rates_{'backward' if dom_bwd else 'forward'}_{precision}_{wl.name}"
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[precision], "traffic": traffic_from_profiles(tag),
+            "kernel": tag, "launch_ms": dom_ms, "zones_per_launch": zl,
+            "fwd_launch_ms": t_fwd, "bwd_launch_ms": t_bwd}
+
+    fp64 = None
+    if precision == "mixed" and args.fp64_steps > 0:
+        print(f"[bench] fp64 comparison: {args.fp64_steps} steps", file=sys.stderr, flush=True)
+        run64 = Runner(inp, wl, "fp64", wl.chunks)
+        t64 = run64.timed(args.fp64_steps, 1)
+        e64 = None if args.no_errors else sampled_errors(inp, run64.eta, run64.chi, wl)
+        del run64
+        torch.cuda.empty_cache()
+        fp64 = {"value": units / t64, "ms_per_step": t64 * 1e3, "speedup_mixed_over_fp64": t64 / t_step,
+                "rel_err": e64}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl)
+
+    line = {
+        "metric": "zone*(eps,eps') kernel evals/sec fwd+bwd", "value": value, "unit": "zone*(eps,eps')/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.rays} rays x {wl.radial} zones, NE={wl.ne}, {wl.nquad}-node "
+                               f"{wl.rule} rule, {precision}, fwd+bwd, {wl.chunks} chunks, inputs resident in HBM",
+                   "zones": wl.nzones, "ne": wl.ne, "nquad": wl.nquad, "precision": precision},
+        "rel_err_vs_oracle": errors, "fp64": fp64, "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

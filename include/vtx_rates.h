@@ -136,6 +136,15 @@ void vtx_release(void);
 int vtx_gauss_rule(int kind, int n, double* x, double* w);
 int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const double* E, double* out);
 
+/*
+ * Host-side copy of one task's coefficient table, prefactor G_F^2/(pi e ep) included:
+ *   VTX_NES (e >= ep): 48 doubles, lo[4 comps][8] (folded degree-7 Bernstein in u = E/ep,
+ *     E < ep) then hi[4][4] (monomials in u, E >= ep; last entry 0);
+ *   VTX_PAIR: 48 doubles, [3 pieces][2 l][8] folded degree-7 Bernstein in the piece variable
+ *     (E/m on [0, m], E/M on [m, M], (e + ep - E)/m on [M, e + ep]).
+ */
+int vtx_task_coefficients(int process, double e, double ep, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -144,13 +144,34 @@ bool gauss_rule(int kind, int n, double* x, double* w) {
 
 // ---------------------------------------------------------------------------------------
 // Angular-weight coefficient tables (zone independent), prefactor G_F^2/(pi e_i e_j) folded in.
+// Pieces on a bounded variable u in [0, 1] are stored in the degree-7 Bernstein basis,
+// p(u) = sum_k g_k u^k (1 - u)^(7-k) (binomials folded into g_k): the basis functions are
+// nonnegative, so the kernels' FP32 moment sums carry no cancellation and the sign changes
+// of the l = 1 weights are resolved in the FP64 contraction with g_k.
+
+double binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// monomial coefficients c[0..7] (in u) -> folded Bernstein coefficients g[0..7]
+void mono_to_bernstein7(const double* c, double* g) {
+  for (int k = 0; k <= 7; ++k) {
+    double b = 0.0;
+    for (int j = 0; j <= k; ++j) b += binom(k, j) / binom(7, j) * c[j];
+    g[k] = b * binom(7, k);
+  }
+}
 
 void nes_coefficients(double e, double ep, NesCoef& C) {
   double lo[4][8], hi[4][3];
   vtx_hpoly_nes(e, ep, lo, hi);
   const double pref = kGF * kGF / (M_PI * e * ep);
   for (int c = 0; c < 4; ++c) {
-    for (int d = 0; d < 8; ++d) C.lo[c][d] = pref * lo[c][d];
+    double m[8];
+    for (int d = 0; d < 8; ++d) m[d] = pref * lo[c][d];
+    mono_to_bernstein7(m, C.lo[c]);
     for (int d = 0; d < 3; ++d) C.hi[c][d] = pref * hi[c][d];
     C.hi[c][3] = 0.0;
   }
@@ -165,12 +186,23 @@ void pair_coefficients(double ei, double ej, PairCoef& C) {
   const double pref = kGF * kGF / (M_PI * ei * ej);
   for (int l = 0; l < 2; ++l) {
     const int comp = ordered ? l : 2 + l;
+    double a[8], b[8], c[8];
     for (int d = 0; d < 8; ++d) {
-      C.piece[0][l][d] = pref * A[comp][d];
-      C.piece[1][l][d] = d < 3 ? pref * B[comp][d] : 0.0;
-      C.piece[2][l][d] = pref * Cc[comp][d];
+      a[d] = pref * A[comp][d];
+      b[d] = d < 3 ? pref * B[comp][d] : 0.0;
+      c[d] = pref * Cc[comp][d];
     }
+    mono_to_bernstein7(a, C.piece[0][l]);
+    mono_to_bernstein7(b, C.piece[1][l]);
+    mono_to_bernstein7(c, C.piece[2][l]);
   }
+}
+
+double bernstein7(const double* g, double u) {
+  const double v = 1.0 - u;
+  double s = 0.0;
+  for (int k = 0; k <= 7; ++k) s += g[k] * std::pow(u, k) * std::pow(v, 7 - k);
+  return s;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -415,20 +447,39 @@ int vtx_gauss_rule(int kind, int n, double* x, double* w) {
   return vtx::gauss_rule(kind, n, x, w) ? VTX_OK : VTX_EINVAL;
 }
 
+int vtx_task_coefficients(int process, double e, double ep, double* out) {
+  if (!out || !(e > 0) || !(ep > 0)) return VTX_EINVAL;
+  if (process == VTX_NES) {
+    if (e < ep) return VTX_EINVAL;
+    vtx::NesCoef C;
+    vtx::nes_coefficients(e, ep, C);
+    std::memcpy(out, &C, sizeof(C));
+    return VTX_OK;
+  }
+  if (process == VTX_PAIR) {
+    vtx::PairCoef C;
+    vtx::pair_coefficients(e, ep, C);
+    std::memcpy(out, &C, sizeof(C));
+    return VTX_OK;
+  }
+  return VTX_EINVAL;
+}
+
 int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const double* E, double* out) {
   if (comp < 0 || comp > 3 || !(e > 0) || !(ep > 0) || n < 0 || (n > 0 && (!E || !out))) return VTX_EINVAL;
   if (process == VTX_NES) {
     if (e < ep) return VTX_EINVAL;
-    double lo[4][8], hi[4][3];
-    vtx_hpoly_nes(e, ep, lo, hi);
+    vtx::NesCoef C;
+    vtx::nes_coefficients(e, ep, C);
+    const double pref = vtx::kGF * vtx::kGF / (M_PI * e * ep);
     for (int k = 0; k < n; ++k) {
       const double u = E[k] / ep;
       double s = 0.0;
       if (u < 1.0)
-        for (int d = 7; d >= 0; --d) s = s * u + lo[comp][d];
+        s = vtx::bernstein7(C.lo[comp], u);
       else
-        for (int d = 2; d >= 0; --d) s = s * u + hi[comp][d];
-      out[k] = E[k] < 0 ? 0.0 : s;
+        for (int d = 2; d >= 0; --d) s = s * u + C.hi[comp][d];
+      out[k] = E[k] < 0 ? 0.0 : s / pref;
     }
     return VTX_OK;
   }
@@ -459,9 +510,7 @@ int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const doub
         piece = 2;
         v = (w - x) / mn;
       }
-      double s = 0.0;
-      for (int d = 7; d >= 0; --d) s = s * v + C.piece[piece][l][d];
-      out[k] = s / pref;
+      out[k] = vtx::bernstein7(C.piece[piece][l], v) / pref;
     }
     return VTX_OK;
   }

@@ -17,15 +17,16 @@ constexpr double kHbarC = 1.973269804e-11;   // MeV cm
 
 // Angular-weight coefficients of one scattering task (eps_i >= eps_j), comps
 // (S, l) = (I,0), (I,1), (II,0), (II,1); variable u = E / eps_j; lo: E < eps_j, hi: E >= eps_j.
-// The task prefactor G_F^2 / (pi eps_i eps_j) is folded in.
+// lo: degree-7 Bernstein, H = sum_k lo[k] u^k (1-u)^(7-k) (binomials folded in);
+// hi: monomials, H = sum_k hi[k] u^k. The task prefactor G_F^2 / (pi eps_i eps_j) is folded in.
 struct NesCoef {
   double lo[4][8];
   double hi[4][4];   // [3] unused
 };
 
 // Pair task (i, j): H^{P,I}_l(eps_i, eps_j, .) on the three pieces
-// A: [0, m] var E/m,  B: [m, M] var E/M,  C: [M, w] var (w - E)/m  (m, M = min, max).
-// Prefactor folded in.
+// A: [0, m] var E/m,  B: [m, M] var E/M,  C: [M, w] var (w - E)/m  (m, M = min, max),
+// each in the folded degree-7 Bernstein basis of its variable. Prefactor folded in.
 struct PairCoef {
   double piece[3][2][8];
 };

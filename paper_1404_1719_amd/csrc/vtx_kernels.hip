@@ -204,8 +204,25 @@ __device__ __forceinline__ RF blocking(RF z1, RF z2, RF e1, RF e2) {
   return num * recip((RF(1) + e1) * (RF(1) + e2));
 }
 
-// Forward node loop of one group: moments M[c] = sum W B var^c (low piece, c = 0..7) and
-// Hm[c] (high piece, c = 0..2). R: bulk precision; RF: Fermi-Dirac precision.
+// Degree-7 Bernstein basis without binomials: b[k] = u^k (1 - u)^(7 - k).
+template <typename R>
+__device__ __forceinline__ void bernstein7(R u, R b[8]) {
+  const R v = R(1) - u;
+  const R u2 = u * u, u3 = u2 * u, u4 = u2 * u2, u5 = u4 * u, u6 = u3 * u3;
+  const R v2 = v * v, v3 = v2 * v, v4 = v2 * v2, v5 = v4 * v, v6 = v3 * v3;
+  b[0] = v6 * v;
+  b[1] = u * v6;
+  b[2] = u2 * v5;
+  b[3] = u3 * v4;
+  b[4] = u4 * v3;
+  b[5] = u5 * v2;
+  b[6] = u6 * v;
+  b[7] = u6 * u;
+}
+
+// Forward node loop of one group: moments M[c] = sum W B u^c (1-u)^(7-c) of the low piece
+// (nonnegative basis: positive sums, no cancellation in FP32) and Hm[c] = sum W B u^c of
+// the high piece (c = 0..2). R: bulk precision; RF: Fermi-Dirac precision.
 template <typename R, typename RF>
 __device__ __forceinline__ void node_moments(const Group& G, int m4, const Tables& tb, R M[8], R Hm[3]) {
   const auto* tR = G.lag ? lag_tab<R>(tb) + G.toff : leg_tab<R>(tb);
@@ -223,21 +240,18 @@ __device__ __forceinline__ void node_moments(const Group& G, int m4, const Table
     const RF z2 = b0 + b1 * (br ? nF.y : nF.x);
     const RF B = blocking<RF>(z1, z2, exp_neg_abs(z1), exp_neg_abs(z2));
     const R wb = ws * nR.z * R(B);
-    const R wl = (var < split) ? wb : R(0);
-    const R wh = wb - wl;
-    const R v2 = var * var, v3 = v2 * var, v4 = v2 * v2;
-    const R v5 = v4 * var, v6 = v3 * v3, v7 = v6 * var;
-    M[0] += wl;
-    M[1] += wl * var;
-    M[2] += wl * v2;
-    M[3] += wl * v3;
-    M[4] += wl * v4;
-    M[5] += wl * v5;
-    M[6] += wl * v6;
-    M[7] += wl * v7;
+    // select, never subtract: wb - wl would be contracted into fma(ws w, B, -wl), which
+    // leaves the product's rounding residue in the other piece instead of zero
+    const bool lo = var < split;
+    const R wl = lo ? wb : R(0);
+    const R wh = lo ? R(0) : wb;
+    R b[8];
+    bernstein7<R>(var, b);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) M[c] += wl * b[c];
     Hm[0] += wh;
     Hm[1] += wh * var;
-    Hm[2] += wh * v2;
+    Hm[2] += wh * (var * var);
   }
 }
 
@@ -473,7 +487,7 @@ __device__ double pair_gw(const DevPlan& P, const Adj& A, int S, int l, int a, i
 
 template <typename R, typename RF>
 __device__ __forceinline__ void node_loop_bwd(const Group& G, int m4, const Tables& tb, double T, double eta,
-                                              const R hl[8], const R hh[3], const R dl[7], const R dh[2],
+                                              const R hl[8], const R hh[3], const R dl[8], const R dh[2],
                                               R M[8], R Hm[3], R& accT, R& accE) {
   const auto* tR = G.lag ? lag_tab<R>(tb) + G.toff : leg_tab<R>(tb);
   const auto* tF = G.lag ? lag_tab<RF>(tb) + G.toff : leg_tab<RF>(tb);
@@ -499,21 +513,21 @@ __device__ __forceinline__ void node_loop_bwd(const Group& G, int m4, const Tabl
     const R wt = nR.z;
     const R wb = ws * wt * B;
     // value moments
-    const R wl = (var < split) ? wb : R(0);
-    const R wh = wb - wl;
-    const R v2 = var * var, v3 = v2 * var, v4 = v2 * v2;
-    const R v5 = v4 * var, v6 = v3 * v3, v7 = v6 * var;
-    M[0] += wl;
-    M[1] += wl * var;
-    M[2] += wl * v2;
-    M[3] += wl * v3;
-    M[4] += wl * v4;
-    M[5] += wl * v5;
-    M[6] += wl * v6;
-    M[7] += wl * v7;
+    const bool lo = var < split;
+    const R wl = lo ? wb : R(0);
+    const R wh = lo ? R(0) : wb;   // select, never subtract (see node_moments)
+    R b[8];
+    bernstein7<R>(var, b);
+    R Hlo = R(0), Dlo = R(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      M[c] += wl * b[c];
+      Hlo += hl[c] * b[c];
+      Dlo += dl[c] * b[c];
+    }
     Hm[0] += wh;
     Hm[1] += wh * var;
-    Hm[2] += wh * v2;
+    Hm[2] += wh * (var * var);
     // derivatives of log B at fixed E, and along E
     const R rr1 = R(r1), rr2 = R(r2);
     const R dlE = s1 * rr1 + s2 * rr2;                                    // d/deta
@@ -522,11 +536,8 @@ __device__ __forceinline__ void node_loop_bwd(const Group& G, int m4, const Tabl
     // node motion
     const R tau = nR.x;
     const R dET = dE0T + dEsT * tau, dEE = dE0E + dEsE * tau;
-    // adjoint-weighted angular weight and its E-derivative
-    const bool lo = var < split;
-    const R Hlo = ((((((hl[7] * var + hl[6]) * var + hl[5]) * var + hl[4]) * var + hl[3]) * var + hl[2]) * var + hl[1]) * var + hl[0];
+    // adjoint-weighted angular weight and its E-derivative (low piece: Bernstein above)
     const R Hhi = (hh[2] * var + hh[1]) * var + hh[0];
-    const R Dlo = (((((dl[6] * var + dl[5]) * var + dl[4]) * var + dl[3]) * var + dl[2]) * var + dl[1]) * var + dl[0];
     const R Dhi = dh[1] * var + dh[0];
     const R H = lo ? Hlo : Hhi;
     const R D = lo ? Dlo : Dhi;
@@ -564,14 +575,28 @@ __device__ void items_backward(const DevPlan& P, const Tables& tb, double T, dou
       j = task % P.ne;
       pair_group(P.eps[i], P.eps[j], g, T, eta, G);
       const PairCoef& C = P.pair_coef[task];
-      const double* a = s_adj + 4 * ntn_used + 2 * task;
+      const double* a = s_adj + 4 * P.ntn + 2 * task;
       for (int c = 0; c < 8; ++c) hl64[c] = a[0] * C.piece[G.piece][0][c] + a[1] * C.piece[G.piece][1][c];
       for (int c = 0; c < 3; ++c) hh64[c] = 0.0;
     }
-    R hl[8], hh[3], dl[7], dh[2];
-    for (int c = 0; c < 8; ++c) hl[c] = R(hl64[c]);
+    // d/dE of the low piece, in the same folded degree-7 Bernstein basis: with beta_k =
+    // g_k / C(7,k), dH/du has degree-6 coefficients d_k = 7 (beta_{k+1} - beta_k); degree
+    // elevation gives D_k = (k/7) d_{k-1} + (1 - k/7) d_k; fold C(7,k) back and scale by du/dE.
+    constexpr double kBin7[8] = {1.0, 7.0, 21.0, 35.0, 35.0, 21.0, 7.0, 1.0};
+    double d6[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) d6[c] = 7.0 * (hl64[c + 1] / kBin7[c + 1] - hl64[c] / kBin7[c]);
+    R hl[8], hh[3], dl[8], dh[2];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double lower = (c > 0) ? (c / 7.0) * d6[c - 1] : 0.0;
+      const double upper = (c < 7) ? (1.0 - c / 7.0) * d6[c] : 0.0;
+      hl[c] = R(hl64[c]);
+      dl[c] = R((lower + upper) * kBin7[c] * G.dvar);
+    }
+#pragma unroll
     for (int c = 0; c < 3; ++c) hh[c] = R(hh64[c]);
-    for (int c = 0; c < 7; ++c) dl[c] = R(hl64[c + 1] * (c + 1) * G.dvar);
+#pragma unroll
     for (int c = 0; c < 2; ++c) dh[c] = R(hh64[c + 1] * (c + 1) * G.dvar);
     R M[8] = {0, 0, 0, 0, 0, 0, 0, 0}, Hm[3] = {0, 0, 0};
     R accT = 0, accE = 0;
@@ -587,17 +612,18 @@ __device__ void items_backward(const DevPlan& P, const Tables& tb, double T, dou
       if (nes) {
         const double* u = s_uadj + 4 * task;
         const double de = (P.eps[i] - P.eps[j]) / (T * T);
-        double* q = s_qn + 4 * task;
+        gT += (o.x * u[0] + o.y * u[1] + o.z * u[2] + o.w * u[3]) * de;
+        double* q = s_qn + 4 * task;   // same slot: read above, overwritten now
         q[0] = o.x;
         q[1] = o.y;
         q[2] = o.z;
         q[3] = o.w;
-        gT += (o.x * u[0] + o.y * u[1] + o.z * u[2] + o.w * u[3]) * de;
       } else {
-        const double* u = s_uadj + 4 * ntn_used + 2 * task;
+        const double* u = s_uadj + 4 * P.ntn + 2 * task;
+        const double u0 = u[0], u1 = u[1];
         s_pa[2 * task] = o.x;
         s_pa[2 * task + 1] = o.y;
-        gT += o.x * u[0] + o.y * u[1];
+        gT += o.x * u0 + o.y * u1;
       }
     }
   }
@@ -626,13 +652,17 @@ __global__ __launch_bounds__(kBlock) void rates_backward_kernel(
   const int64_t z = blockIdx.x;
   const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
   const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntp : 0;
+  // Task slots: [4 ntn] scattering comps, then [2 ntp] pair comps (full-size offsets
+  // whatever the process mask). s_uadj holds each task's completion-factor weight until the
+  // lane that owns the task has read it; the same lane then stores the task's kernel values
+  // in that slot (s_qn / s_pa alias s_uadj).
   double* s_f = smem;
   double* s_ge = s_f + 6 * ne;
   double* s_gc = s_ge + 6 * ne;
-  double* s_qn = s_gc + 6 * ne;         // [4 ntn]
-  double* s_pa = s_qn + 4 * P.ntn;      // [2 ntp]
-  double* s_adj = s_pa + 2 * P.ntp;     // [4 ntn + 2 ntp] adjoint weights of task comps
+  double* s_adj = s_gc + 6 * ne;                    // adjoint weights of task comps
   double* s_uadj = s_adj + 4 * P.ntn + 2 * P.ntp;   // completion-factor T-derivative weights
+  double* s_qn = s_uadj;
+  double* s_pa = s_uadj + 4 * P.ntn;
   double* s_d = s_uadj + 4 * P.ntn + 2 * P.ntp;
   double* s_p = s_d + ne * ne;
   const double T = Tz[z], eta = etaz[z];
@@ -662,8 +692,8 @@ __global__ __launch_bounds__(kBlock) void rates_backward_kernel(
       const double pf = s_p[i * ne + j];
       const double dpf = pf * (P.eps[i] + P.eps[j]) / (T * T);
       for (int l = 0; l < 2; ++l) {
-        s_adj[4 * ntn + 2 * p + l] = pair_gw(P, A, 0, l, i, j, pf, false) + pair_gw(P, A, 1, l, j, i, pf, false);
-        s_uadj[4 * ntn + 2 * p + l] = (pair_gw(P, A, 0, l, i, j, pf, true) + pair_gw(P, A, 1, l, j, i, pf, true)) * dpf;
+        s_adj[4 * P.ntn + 2 * p + l] = pair_gw(P, A, 0, l, i, j, pf, false) + pair_gw(P, A, 1, l, j, i, pf, false);
+        s_uadj[4 * P.ntn + 2 * p + l] = (pair_gw(P, A, 0, l, i, j, pf, true) + pair_gw(P, A, 1, l, j, i, pf, true)) * dpf;
       }
     }
   }
@@ -673,7 +703,6 @@ __global__ __launch_bounds__(kBlock) void rates_backward_kernel(
     items_backward<float, double>(P, tb, T, eta, ntn, ntp, s_adj, s_uadj, s_qn, s_pa, gT, gE);
   else
     items_backward<R, R>(P, tb, T, eta, ntn, ntp, s_adj, s_uadj, s_qn, s_pa, gT, gE);
-  // the pair tables are indexed from the start of s_pa whatever ntn is
   const double sT = block_sum(gT, red);
   const double sE = block_sum(gE, red + 4);
   if (threadIdx.x == 0) {
@@ -723,7 +752,15 @@ size_t fwd_smem(const DevPlan& P) {
   return sizeof(double) * (6 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne);
 }
 size_t bwd_smem(const DevPlan& P) {
-  return sizeof(double) * (18 * P.ne + 3 * (4 * P.ntn + 2 * P.ntp) + 2 * P.ne * P.ne);
+  return sizeof(double) * (18 * P.ne + 2 * (4 * P.ntn + 2 * P.ntp) + 2 * P.ne * P.ne);
+}
+
+// Dynamic LDS beyond the 64 KiB default must be requested per kernel.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
 }
 
 }  // namespace
@@ -732,10 +769,15 @@ hipError_t launch_forward(const DevPlan& P, int64_t nz, const double* T, const d
                           double* eta, double* chi, hipStream_t s) {
   if (nz <= 0) return hipSuccess;
   const dim3 grid((unsigned)nz), block(kBlock);
-  if (P.precision == VTX_MIXED)
-    hipLaunchKernelGGL(rates_forward_kernel<float>, grid, block, fwd_smem(P), s, P, T, eta_e, f, eta, chi);
-  else
-    hipLaunchKernelGGL(rates_forward_kernel<double>, grid, block, fwd_smem(P), s, P, T, eta_e, f, eta, chi);
+  const size_t lds = fwd_smem(P);
+  hipError_t e;
+  if (P.precision == VTX_MIXED) {
+    if ((e = allow_lds(rates_forward_kernel<float>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_forward_kernel<float>, grid, block, lds, s, P, T, eta_e, f, eta, chi);
+  } else {
+    if ((e = allow_lds(rates_forward_kernel<double>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_forward_kernel<double>, grid, block, lds, s, P, T, eta_e, f, eta, chi);
+  }
   return hipGetLastError();
 }
 
@@ -744,12 +786,17 @@ hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const 
                            hipStream_t s) {
   if (nz <= 0) return hipSuccess;
   const dim3 grid((unsigned)nz), block(kBlock);
-  if (P.precision == VTX_MIXED)
-    hipLaunchKernelGGL(rates_backward_kernel<float>, grid, block, bwd_smem(P), s, P, T, eta_e, f, g_eta, g_chi,
-                       g_T, g_eta_e, g_f);
-  else
-    hipLaunchKernelGGL(rates_backward_kernel<double>, grid, block, bwd_smem(P), s, P, T, eta_e, f, g_eta, g_chi,
-                       g_T, g_eta_e, g_f);
+  const size_t lds = bwd_smem(P);
+  hipError_t e;
+  if (P.precision == VTX_MIXED) {
+    if ((e = allow_lds(rates_backward_kernel<float>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_backward_kernel<float>, grid, block, lds, s, P, T, eta_e, f, g_eta, g_chi, g_T,
+                       g_eta_e, g_f);
+  } else {
+    if ((e = allow_lds(rates_backward_kernel<double>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_backward_kernel<double>, grid, block, lds, s, P, T, eta_e, f, g_eta, g_chi, g_T,
+                       g_eta_e, g_f);
+  }
   return hipGetLastError();
 }
 

@@ -62,6 +62,8 @@ def library():
     lib.vtx_gauss_rule.restype = ctypes.c_int
     lib.vtx_eval_hpoly.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
     lib.vtx_eval_hpoly.restype = ctypes.c_int
+    lib.vtx_task_coefficients.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+    lib.vtx_task_coefficients.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -177,6 +179,14 @@ def eval_hpoly(process: int, comp: int, e: float, ep: float, E):
     _check(library().vtx_eval_hpoly(process, comp, e, ep, E.size,
                                     E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "vtx_eval_hpoly")
+    return out
+
+
+def task_coefficients(process: int, e: float, ep: float):
+    """Host copy of one task's coefficient table (48 doubles, layout in include/vtx_rates.h)."""
+    out = np.zeros(48)
+    _check(library().vtx_task_coefficients(process, e, ep, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "vtx_task_coefficients")
     return out
 
 

@@ -1,0 +1,258 @@
+"""GPU parity of the HIP rates library against the FP64 CPU oracle (needs a gfx950 GPU).
+
+Relative error of an output y against the oracle value y_ref (same rule, same inputs):
+  err = |y - y_ref| / max(|y_ref|, 1e-3 A, 1e-290),
+A being the sum of the absolute values of the terms that make up y (computed by the
+oracle): it keeps outputs that cancel to near zero (eta1, chi1) or underflow from being
+compared on rounding noise. Bars: FP64 path 1e-6 (met with ~1e-12), mixed path 1e-4.
+
+Full-size workloads run in one launch over every zone, exactly as the benchmark runs
+them, and sampled zones (always including the min-T, max-T and max-eta_e zones) are
+compared with the oracle zone by zone.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import grad as ograd
+from oracle import rates as orates
+from paper_1404_1719_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1404_1719_amd import vtx  # noqa: E402
+
+DEV = "cuda:0"
+FP64_TOL = 1e-6
+MIXED_TOL = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def gpu_forward(inp, precision, nquad, rule, processes=3, eta_fp64=30.0):
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, nquad, rule, processes, eta_fp64=eta_fp64)
+    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
+    eta, chi = vtx.forward(grid, opts, T, E, f)
+    torch.cuda.synchronize()
+    return eta.cpu().numpy(), chi.cpu().numpy()
+
+
+def rel_err(y, ref, A):
+    den = np.maximum(np.maximum(np.abs(ref), 1e-3 * A), 1e-290)
+    return np.abs(y - ref) / den
+
+
+def oracle_forward(inp, nquad, rule, processes=3):
+    opts = orates.Options(nquad=nquad, rule=rule, processes=processes)
+    return orates.forward_with_scale(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, opts)
+
+
+def check_forward(inp, precision, nquad, rule, tol, processes=3, label=""):
+    say(f"[gpu] forward {label} precision={precision} nquad={nquad} rule={rule} nz={inp.T.shape[0]} "
+        f"ne={inp.eps.shape[0]} processes={processes}")
+    e, c = gpu_forward(inp, precision, nquad, rule, processes)
+    re, rc, ae, ac = oracle_forward(inp, nquad, rule, processes)
+    err_e, err_c = rel_err(e, re, ae), rel_err(c, rc, ac)
+    worst = max(err_e.max(), err_c.max())
+    say(f"    max rel err eta0 {err_e[:, :, 0].max():.2e} eta1 {err_e[:, :, 1].max():.2e} "
+        f"chi0 {err_c[:, :, 0].max():.2e} chi1 {err_c[:, :, 1].max():.2e}")
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(c))
+    assert worst <= tol, worst
+    return worst
+
+
+# ---------------------------------------------------------------------------- forward
+
+def test_small_fp64_laguerre_all_zones():
+    inp = synth.make_inputs("small")
+    check_forward(inp, "fp64", 32, "laguerre", FP64_TOL, label="small")
+
+
+def test_small_fp64_panel_and_mixed():
+    inp = synth.make_inputs("small")
+    check_forward(inp, "fp64", 32, "panel", FP64_TOL, label="small/panel")
+    check_forward(inp, "mixed", 32, "panel", MIXED_TOL, label="small/panel")
+
+
+@pytest.mark.parametrize("processes", [1, 2])
+def test_single_process(processes):
+    inp = synth.make_inputs("medium", nzones=8)
+    check_forward(inp, "fp64", 48, "panel", FP64_TOL, processes, label="medium-8")
+    check_forward(inp, "mixed", 48, "panel", MIXED_TOL, processes, label="medium-8")
+
+
+def _full_then_sample(name, count, precision):
+    wl = synth.WORKLOADS[name]
+    say(f"[gpu] full-size {name}: drawing {wl.nzones} zones")
+    inp = synth.make_inputs(name)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
+    say(f"[gpu] full-size {name} {precision}: one launch over {wl.nzones} zones")
+    eta, chi = vtx.forward(grid, opts, T, E, f)
+    torch.cuda.synchronize()
+    idx = synth.sample_zones(inp, count)
+    it = torch.from_numpy(idx).to(DEV)
+    e = eta.index_select(0, it).cpu().numpy()
+    c = chi.index_select(0, it).cpu().numpy()
+    del eta, chi, T, E, f
+    torch.cuda.empty_cache()
+    sub = synth.subset(inp, idx)
+    re, rc, ae, ac = oracle_forward(sub, wl.nquad, wl.rule)
+    err = max(rel_err(e, re, ae).max(), rel_err(c, rc, ac).max())
+    say(f"    {name} {precision}: sampled {len(idx)} zones, max rel err {err:.2e}")
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(c))
+    return err
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_medium_full_size_sampled(precision, tol):
+    assert _full_then_sample("medium", 40, precision) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_large_full_size_sampled(precision, tol):
+    assert _full_then_sample("large", 24, precision) <= tol
+
+
+def test_edge_cases():
+    # ragged batch, one bin, the 32-bin maximum, node counts 8 and 64, eta_e at 0 and below
+    inp = synth.make_inputs("medium", nzones=37)
+    check_forward(inp, "fp64", 8, "panel", FP64_TOL, label="ragged-37/n8")
+    eps, w = synth.energy_grid(1, 5.0, 9.0)
+    T, eta_e, f = synth.draw_zones(5, 1, eps, (1, 20), (-3, 25), (-2, 5), 0.0, 77)
+    check_forward(synth.ZoneInputs(eps, w, T, eta_e, f), "fp64", 16, "panel", FP64_TOL, label="ne=1")
+    eps, w = synth.energy_grid(32, 1.0, 400.0)
+    T, eta_e, f = synth.draw_zones(3, 32, eps, (0.5, 60), (0, 60), (-2, 15), 0.05, 78)
+    check_forward(synth.ZoneInputs(eps, w, T, eta_e, f), "fp64", 64, "panel", FP64_TOL, label="ne=32/n64")
+    check_forward(synth.ZoneInputs(eps, w, T, eta_e, f), "mixed", 64, "panel", MIXED_TOL, label="ne=32/n64")
+    inp = synth.make_inputs("medium", nzones=4)
+    inp.eta_e[:] = [0.0, -5.0, 35.0, 60.0]
+    inp.T[:] = [0.5, 60.0, 3.0, 1.0]
+    check_forward(inp, "fp64", 48, "panel", FP64_TOL, label="extremes")
+    check_forward(inp, "mixed", 48, "panel", MIXED_TOL, label="extremes")
+
+
+def test_empty_batch_and_stream():
+    inp = synth.make_inputs("small", nzones=6)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts("fp64", 32, "laguerre")
+    z = torch.zeros(0, dtype=torch.float64, device=DEV)
+    e0, c0 = vtx.forward(grid, opts, z, z, torch.zeros((0, 3, 2, inp.eps.shape[0]), dtype=torch.float64,
+                                                       device=DEV))
+    assert e0.shape[0] == 0
+    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
+    e1, c1 = vtx.forward(grid, opts, T, E, f)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        e2, c2 = vtx.forward(grid, opts, T, E, f)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(e1, e2) and torch.equal(c1, c2)
+
+
+def test_deterministic_and_batch_independent():
+    inp = synth.make_inputs("medium", nzones=20)
+    for prec in ("fp64", "mixed"):
+        a = gpu_forward(inp, prec, 48, "panel")
+        b = gpu_forward(inp, prec, 48, "panel")
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        one = gpu_forward(synth.subset(inp, [7]), prec, 48, "panel")
+        assert np.array_equal(one[0][0], a[0][7]) and np.array_equal(one[1][0], a[1][7])
+
+
+# ---------------------------------------------------------------------------- backward
+
+def gpu_backward(inp, ge, gc, precision, nquad, rule):
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, nquad, rule)
+    out = vtx.backward(grid, opts, to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f), to_dev(ge), to_dev(gc))
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out]
+
+
+def grad_err(g, ref):
+    """|g - ref| / max(|ref|, 1e-3 mean|ref|) over one field."""
+    floor = 1e-3 * np.mean(np.abs(ref)) + 1e-300
+    return np.abs(g - ref) / np.maximum(np.abs(ref), floor)
+
+
+@pytest.mark.parametrize("name,nq,rule,nz", [("small", 32, "laguerre", 6), ("medium", 48, "panel", 6),
+                                             ("large", 64, "panel", 4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 1e-3)])
+def test_backward_vs_oracle(name, nq, rule, nz, precision, tol):
+    inp = synth.make_inputs(name, nzones=nz)
+    ge, gc = synth.random_gradients(nz, inp.eps.shape[0], 3)
+    say(f"[gpu] backward {name} {precision} nz={nz}")
+    gT, gE, gf = gpu_backward(inp, ge, gc, precision, nq, rule)
+    rT, rE, rf = ograd.vjp(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, ge, gc, orates.Options(nquad=nq, rule=rule))
+    eT, eE, ef = grad_err(gT, rT).max(), grad_err(gE, rE).max(), grad_err(gf, rf).max()
+    say(f"    rel err g_T {eT:.2e} g_eta_e {eE:.2e} g_f {ef:.2e}")
+    assert max(eT, eE, ef) <= tol
+
+
+def test_backward_vs_central_differences():
+    """FP64 kernels: backward against central differences of the forward kernel itself."""
+    inp = synth.make_inputs("medium", nzones=5)
+    ge, gc = synth.random_gradients(5, inp.eps.shape[0], 4)
+    gT, gE, gf = gpu_backward(inp, ge, gc, "fp64", 48, "panel")
+
+    def L(T, E, f):
+        x = synth.ZoneInputs(inp.eps, inp.w, T, E, f)
+        e, c = gpu_forward(x, "fp64", 48, "panel")
+        return np.sum(ge * e + gc * c, axis=(1, 2, 3))
+
+    h = 1e-6 * inp.T
+    fd = (L(inp.T + h, inp.eta_e, inp.f) - L(inp.T - h, inp.eta_e, inp.f)) / (2 * h)
+    assert np.all(np.abs(gT - fd) <= 1e-5 * np.abs(gT) + 1e-9 * np.abs(gT).max())
+    h = 1e-6 * np.maximum(np.abs(inp.eta_e), 1.0)
+    fd = (L(inp.T, inp.eta_e + h, inp.f) - L(inp.T, inp.eta_e - h, inp.f)) / (2 * h)
+    assert np.all(np.abs(gE - fd) <= 1e-5 * np.abs(gE) + 1e-9 * np.abs(gE).max())
+    for idx in [(0, 0, 2), (1, 1, 9), (2, 0, 20)]:
+        fp, fm = inp.f.copy(), inp.f.copy()
+        fp[(slice(None),) + idx] += 1e-6
+        fm[(slice(None),) + idx] -= 1e-6
+        fd = (L(inp.T, inp.eta_e, fp) - L(inp.T, inp.eta_e, fm)) / 2e-6
+        g = gf[(slice(None),) + idx]
+        assert np.all(np.abs(g - fd) <= 1e-5 * np.abs(g) + 1e-8 * np.abs(gf).max())
+
+
+def test_autograd_function():
+    inp = synth.make_inputs("small", nzones=4)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts("fp64", 32, "laguerre")
+    T = to_dev(inp.T).requires_grad_(True)
+    E = to_dev(inp.eta_e).requires_grad_(True)
+    f = to_dev(inp.f).requires_grad_(True)
+    ge, gc = synth.random_gradients(4, inp.eps.shape[0], 5)
+    eta, chi = vtx.rates(T, E, f, grid, opts)
+    (eta * to_dev(ge) + chi * to_dev(gc)).sum().backward()
+    gT, gE, gf = gpu_backward(inp, ge, gc, "fp64", 32, "laguerre")
+    assert np.array_equal(T.grad.cpu().numpy(), gT)
+    assert np.array_equal(E.grad.cpu().numpy(), gE)
+    assert np.array_equal(f.grad.cpu().numpy(), gf)
+
+
+def test_backward_largest_grid():
+    """32 bins: the backward kernel's LDS exceeds 64 KiB and is requested explicitly."""
+    eps, w = synth.energy_grid(32, 1.0, 400.0)
+    T, eta_e, f = synth.draw_zones(2, 32, eps, (2, 30), (0, 20), (-2, 10), 0.05, 79)
+    inp = synth.ZoneInputs(eps, w, T, eta_e, f)
+    ge, gc = synth.random_gradients(2, 32, 6)
+    say("[gpu] backward ne=32")
+    gT, gE, gf = gpu_backward(inp, ge, gc, "fp64", 32, "panel")
+    rT, rE, rf = ograd.vjp(eps, w, T, eta_e, f, ge, gc, orates.Options(nquad=32, rule="panel"))
+    assert max(grad_err(gT, rT).max(), grad_err(gE, rE).max(), grad_err(gf, rf).max()) <= FP64_TOL
