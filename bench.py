@@ -65,7 +65,7 @@ def traffic_from_profiles(kernel_tag):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s=20.0):
+def cpu_baseline(wl, budget_s=15.0):
     """Oracle forward + backward on a bounded zone sample, spread over the host cores."""
     from concurrent.futures import ProcessPoolExecutor
     ncores = max(1, min(16, os.cpu_count() or 1))
@@ -207,10 +207,12 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2, help="steps of the FP64 comparison run (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="also run one device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU; multi-GPU runs are not part of this build "
-              "(zones shard by ray blocks with no communication).", file=sys.stderr)
+        print("bench.py measures a single GPU: run it with --gpus 1. The rates need no communication; "
+              "more GPUs would each take a block of rays.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -219,6 +221,14 @@ def main():
     print(f"[bench] drawing workload {wl.name}: {wl.nzones} zones, NE={wl.ne}, n={wl.nquad}", file=sys.stderr,
           flush=True)
     inp = synth.make_inputs(wl.name)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 8
+        src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     run = Runner(inp, wl, precision, wl.chunks)
     print(f"[bench] {precision}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     t_step = run.timed(args.steps, args.warmup)
