@@ -68,10 +68,12 @@ enum vtx_status {
 
 enum vtx_precision {
   VTX_FP64 = 0,   /* every step in FP64 */
-  VTX_MIXED = 1   /* FP32 quadrature bulk (nodes, Fermi-Dirac factors, angular weights,
-                     accumulation); FP64 angular-weight contraction, detailed-balance
-                     factors, Fermi-Dirac factors of zones with eta_e > eta_fp64, and the
-                     per-zone contraction */
+  VTX_MIXED = 1   /* FP32 quadrature bulk (nodes, Fermi-Dirac factors, angular-weight
+                     moments and their accumulation); FP64 angular-weight contraction,
+                     detailed-balance factors and the per-zone contraction. Zones with
+                     |eta_e| > eta_fp64 are computed entirely in FP64 (a second, sparse
+                     pass), since their blocking factors reach exp(-|eta_e|) and FP32 ends
+                     near exp(-87) */
 };
 
 enum vtx_rule { VTX_RULE_LAGUERRE = 0, VTX_RULE_PANEL = 1 };
@@ -90,10 +92,10 @@ typedef struct {
   int32_t rule;        /* vtx_rule */
   uint32_t processes;  /* bitmask of vtx_process, nonzero */
   double sin2w;        /* weak mixing angle sin^2(theta_W), default 0.2312 */
-  double eta_fp64;     /* mixed precision: zones with eta_e > eta_fp64 use FP64 Fermi-Dirac factors (30) */
+  double eta_fp64;     /* mixed precision: zones with |eta_e| > eta_fp64 run in FP64 (default 64) */
 } vtx_opts;
 
-/* Fill *opts with the defaults: FP64, 48 nodes, PANEL, both processes, 0.2312, 30. */
+/* Fill *opts with the defaults: FP64, 48 nodes, PANEL, both processes, 0.2312, 64. */
 void vtx_opts_default(vtx_opts* opts);
 
 /*
@@ -138,10 +140,12 @@ int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const doub
 
 /*
  * Host-side copy of one task's coefficient table, prefactor G_F^2/(pi e ep) included:
- *   VTX_NES (e >= ep): 48 doubles, lo[4 comps][8] (folded degree-7 Bernstein in u = E/ep,
- *     E < ep) then hi[4][4] (monomials in u, E >= ep; last entry 0);
- *   VTX_PAIR: 48 doubles, [3 pieces][2 l][8] folded degree-7 Bernstein in the piece variable
- *     (E/m on [0, m], E/M on [m, M], (e + ep - E)/m on [M, e + ep]).
+ *   VTX_NES (e >= ep): 32 doubles, lo[4 comps][5] then hi[4][3]; H = sum_{k=3..7} lo[k-3]
+ *     u^k (1-u)^(7-k) for u = E/ep < 1 (folded Bernstein form; its k < 3 terms vanish) and
+ *     H = sum_{k<3} hi[k] u^k for u >= 1;
+ *   VTX_PAIR: 26 doubles, A[2 l][5], B[2][3], C[2][5]: folded Bernstein k = 3..7 in E/m on
+ *     [0, m], monomials in E/M on [m, M], folded Bernstein in (e + ep - E)/m on [M, e + ep].
+ * out must hold 32 doubles.
  */
 int vtx_task_coefficients(int process, double e, double ep, double* out);
 

@@ -164,44 +164,56 @@ void mono_to_bernstein7(const double* c, double* g) {
   }
 }
 
-void nes_coefficients(double e, double ep, NesCoef& C) {
+// Bernstein form of a low piece (exact E^3 factor): its k = 0..2 coefficients vanish
+// exactly, and only k = 3..7 are stored.
+bool low_piece(const double* mono, double* out5) {
+  double g[8];
+  mono_to_bernstein7(mono, g);
+  if (g[0] != 0.0 || g[1] != 0.0 || g[2] != 0.0) return false;
+  for (int k = 0; k < 5; ++k) out5[k] = g[k + 3];
+  return true;
+}
+
+bool nes_coefficients(double e, double ep, NesCoef& C) {
   double lo[4][8], hi[4][3];
   vtx_hpoly_nes(e, ep, lo, hi);
   const double pref = kGF * kGF / (M_PI * e * ep);
+  bool ok = true;
   for (int c = 0; c < 4; ++c) {
     double m[8];
     for (int d = 0; d < 8; ++d) m[d] = pref * lo[c][d];
-    mono_to_bernstein7(m, C.lo[c]);
+    ok = low_piece(m, C.lo[c]) && ok;
     for (int d = 0; d < 3; ++d) C.hi[c][d] = pref * hi[c][d];
-    C.hi[c][3] = 0.0;
   }
+  return ok;
 }
 
 // H^{P,I}_l(e_i, e_j, .): for e_i >= e_j the generator's S = I comps, else its S = II comps
 // with the arguments swapped (H^{P,I}(a, b, E) = H^{P,II}(b, a, E)).
-void pair_coefficients(double ei, double ej, PairCoef& C) {
+bool pair_coefficients(double ei, double ej, PairCoef& C) {
   double A[4][8], B[4][3], Cc[4][8];
   const bool ordered = ei >= ej;
   vtx_hpoly_pair(ordered ? ei : ej, ordered ? ej : ei, A, B, Cc);
   const double pref = kGF * kGF / (M_PI * ei * ej);
+  bool ok = true;
   for (int l = 0; l < 2; ++l) {
     const int comp = ordered ? l : 2 + l;
-    double a[8], b[8], c[8];
+    double a[8], c[8];
     for (int d = 0; d < 8; ++d) {
       a[d] = pref * A[comp][d];
-      b[d] = d < 3 ? pref * B[comp][d] : 0.0;
       c[d] = pref * Cc[comp][d];
     }
-    mono_to_bernstein7(a, C.piece[0][l]);
-    mono_to_bernstein7(b, C.piece[1][l]);
-    mono_to_bernstein7(c, C.piece[2][l]);
+    ok = low_piece(a, C.A[l]) && ok;
+    ok = low_piece(c, C.C[l]) && ok;
+    for (int d = 0; d < 3; ++d) C.B[l][d] = pref * B[comp][d];
   }
+  return ok;
 }
 
-double bernstein7(const double* g, double u) {
+double bernstein_low(const double* g5, double u) {
   const double v = 1.0 - u;
   double s = 0.0;
-  for (int k = 0; k <= 7; ++k) s += g[k] * std::pow(u, k) * std::pow(v, 7 - k);
+  for (int k = 3; k <= 7; ++k) s += g5[k - 3] * std::pow(u, k) * std::pow(v, 7 - k);
   return s;
 }
 
@@ -249,16 +261,20 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   std::vector<double> c0w(ne);
   const double c0 = 1.0 / (4.0 * M_PI * M_PI * kHbarC);
   for (int j = 0; j < ne; ++j) c0w[j] = c0 * g->w[j];
+  std::vector<double> inv_eps(ne);
+  for (int j = 0; j < ne; ++j) inv_eps[j] = 1.0 / g->eps[j];
   std::vector<int> nes_ij(ntn);
   std::vector<NesCoef> ncoef(ntn);
+  bool ok = true;
   for (int i = 0, t = 0; i < ne; ++i)
     for (int j = 0; j <= i; ++j, ++t) {
       nes_ij[t] = i | (j << 8);
-      nes_coefficients(g->eps[i], g->eps[j], ncoef[t]);
+      ok = nes_coefficients(g->eps[i], g->eps[j], ncoef[t]) && ok;
     }
   std::vector<PairCoef> pcoef(ntp);
   for (int i = 0; i < ne; ++i)
-    for (int j = 0; j < ne; ++j) pair_coefficients(g->eps[i], g->eps[j], pcoef[i * ne + j]);
+    for (int j = 0; j < ne; ++j) ok = pair_coefficients(g->eps[i], g->eps[j], pcoef[i * ne + j]) && ok;
+  if (!ok) return VTX_EINVAL;
   std::vector<double> tx(m4), tw(m4), lx(nlag), lw(nlag);
   if (!gauss_rule(0, m4, tx.data(), tw.data()) || !gauss_rule(1, nlag, lx.data(), lw.data())) return VTX_EINVAL;
   std::vector<double4> leg64(m4), lag64(nlag);
@@ -279,6 +295,7 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
     return o0;
   };
   const size_t o_eps = place(sizeof(double) * ne), o_c0w = place(sizeof(double) * ne);
+  const size_t o_ie = place(sizeof(double) * ne);
   const size_t o_ij = place(sizeof(int) * ntn), o_nc = place(sizeof(NesCoef) * ntn);
   const size_t o_pc = place(sizeof(PairCoef) * ntp);
   const size_t o_l64 = place(sizeof(double4) * m4), o_g64 = place(sizeof(double4) * nlag);
@@ -287,6 +304,7 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   auto put = [&](size_t o2, const void* src, size_t bytes) { std::memcpy(img.data() + o2, src, bytes); };
   put(o_eps, g->eps, sizeof(double) * ne);
   put(o_c0w, c0w.data(), sizeof(double) * ne);
+  put(o_ie, inv_eps.data(), sizeof(double) * ne);
   put(o_ij, nes_ij.data(), sizeof(int) * ntn);
   put(o_nc, ncoef.data(), sizeof(NesCoef) * ntn);
   put(o_pc, pcoef.data(), sizeof(PairCoef) * ntp);
@@ -310,6 +328,7 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   couplings(o->sin2w, d.beta);
   d.eps = (const double*)(b + o_eps);
   d.c0w = (const double*)(b + o_c0w);
+  d.inv_eps = (const double*)(b + o_ie);
   d.nes_ij = (const int*)(b + o_ij);
   d.nes_coef = (const NesCoef*)(b + o_nc);
   d.pair_coef = (const PairCoef*)(b + o_pc);
@@ -391,7 +410,7 @@ void vtx_opts_default(vtx_opts* o) {
   o->rule = VTX_RULE_PANEL;
   o->processes = VTX_NES | VTX_PAIR;
   o->sin2w = 0.2312;
-  o->eta_fp64 = 30.0;
+  o->eta_fp64 = 64.0;
 }
 
 int vtx_rates_forward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
@@ -452,13 +471,13 @@ int vtx_task_coefficients(int process, double e, double ep, double* out) {
   if (process == VTX_NES) {
     if (e < ep) return VTX_EINVAL;
     vtx::NesCoef C;
-    vtx::nes_coefficients(e, ep, C);
+    if (!vtx::nes_coefficients(e, ep, C)) return VTX_EINVAL;
     std::memcpy(out, &C, sizeof(C));
     return VTX_OK;
   }
   if (process == VTX_PAIR) {
     vtx::PairCoef C;
-    vtx::pair_coefficients(e, ep, C);
+    if (!vtx::pair_coefficients(e, ep, C)) return VTX_EINVAL;
     std::memcpy(out, &C, sizeof(C));
     return VTX_OK;
   }
@@ -470,13 +489,13 @@ int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const doub
   if (process == VTX_NES) {
     if (e < ep) return VTX_EINVAL;
     vtx::NesCoef C;
-    vtx::nes_coefficients(e, ep, C);
+    if (!vtx::nes_coefficients(e, ep, C)) return VTX_EINVAL;
     const double pref = vtx::kGF * vtx::kGF / (M_PI * e * ep);
     for (int k = 0; k < n; ++k) {
       const double u = E[k] / ep;
       double s = 0.0;
       if (u < 1.0)
-        s = vtx::bernstein7(C.lo[comp], u);
+        s = vtx::bernstein_low(C.lo[comp], u);
       else
         for (int d = 2; d >= 0; --d) s = s * u + C.hi[comp][d];
       out[k] = E[k] < 0 ? 0.0 : s / pref;
@@ -489,28 +508,25 @@ int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const doub
     const int S = comp >> 1, l = comp & 1;
     vtx::PairCoef C;
     const double a = S == 0 ? e : ep, b = S == 0 ? ep : e;
-    vtx::pair_coefficients(a, b, C);
+    if (!vtx::pair_coefficients(a, b, C)) return VTX_EINVAL;
     const double pref = vtx::kGF * vtx::kGF / (M_PI * e * ep);
     const double mn = std::fmin(e, ep), mx = std::fmax(e, ep), w = e + ep;
     for (int k = 0; k < n; ++k) {
       const double x = E[k];
-      int piece;
-      double v;
       if (x <= 0 || x >= w) {
         out[k] = 0.0;
         continue;
       }
+      double s;
       if (x <= mn) {
-        piece = 0;
-        v = x / mn;
+        s = vtx::bernstein_low(C.A[l], x / mn);
       } else if (x <= mx) {
-        piece = 1;
-        v = x / mx;
+        const double u = x / mx;
+        s = (C.B[l][2] * u + C.B[l][1]) * u + C.B[l][0];
       } else {
-        piece = 2;
-        v = (w - x) / mn;
+        s = vtx::bernstein_low(C.C[l], (w - x) / mn);
       }
-      out[k] = vtx::bernstein7(C.piece[piece][l], v) / pref;
+      out[k] = s / pref;
     }
     return VTX_OK;
   }

@@ -9,26 +9,32 @@ namespace vtx {
 
 constexpr int kMaxNE = 32;
 constexpr int kMaxNquad = 64;
-constexpr int kBlock = 256;
 // Decay panel above mu_e is capped at KAPPA * T; the rest of the decay goes to the tail.
 constexpr double kKappa = 10.0;
 constexpr double kGF = 1.1663787e-11;        // MeV^-2
 constexpr double kHbarC = 1.973269804e-11;   // MeV cm
 
 // Angular-weight coefficients of one scattering task (eps_i >= eps_j), comps
-// (S, l) = (I,0), (I,1), (II,0), (II,1); variable u = E / eps_j; lo: E < eps_j, hi: E >= eps_j.
-// lo: degree-7 Bernstein, H = sum_k lo[k] u^k (1-u)^(7-k) (binomials folded in);
-// hi: monomials, H = sum_k hi[k] u^k. The task prefactor G_F^2 / (pi eps_i eps_j) is folded in.
+// (S, l) = (I,0), (I,1), (II,0), (II,1); variable u = E / eps_j.
+// lo (E < eps_j): H = sum_{k=3..7} lo[k-3] u^k (1-u)^(7-k), the degree-7 Bernstein form with
+//   binomials folded in; its k = 0..2 coefficients vanish exactly (H ~ E^3 near E = 0).
+// hi (E >= eps_j): H = sum_{k=0..2} hi[k] u^k.
+// The task prefactor G_F^2 / (pi eps_i eps_j) is folded in.
 struct NesCoef {
-  double lo[4][8];
-  double hi[4][4];   // [3] unused
+  double lo[4][5];
+  double hi[4][3];
 };
 
-// Pair task (i, j): H^{P,I}_l(eps_i, eps_j, .) on the three pieces
-// A: [0, m] var E/m,  B: [m, M] var E/M,  C: [M, w] var (w - E)/m  (m, M = min, max),
-// each in the folded degree-7 Bernstein basis of its variable. Prefactor folded in.
+// Pair task (i, j): H^{P,I}_l(eps_i, eps_j, .), l = 0, 1, on its three pieces (m, M = min,
+// max of eps_i, eps_j; w = eps_i + eps_j):
+//   A on [0, m], u = E/m:        folded Bernstein k = 3..7 (factor E^3);
+//   B on [m, M], u = E/M:        monomials k = 0..2;
+//   C on [M, w], u = (w - E)/m:  folded Bernstein k = 3..7 (factor (w - E)^3).
+// Prefactor folded in.
 struct PairCoef {
-  double piece[3][2][8];
+  double A[2][5];
+  double B[2][3];
+  double C[2][5];
 };
 
 // Everything a kernel needs about the zone-independent tables; passed by value.
@@ -44,6 +50,7 @@ struct DevPlan {
   double eta_fp64;
   double beta[3][2];
   const double* eps;        // [ne]
+  const double* inv_eps;    // [ne] 1 / eps
   const double* c0w;        // [ne] c0 w_j
   const int* nes_ij;        // [ntn] i | (j << 8)
   const NesCoef* nes_coef;  // [ntn]

@@ -1,16 +1,21 @@
 // HIP kernels for gfx950: energy-coupled neutrino-matter interaction rates.
 //
-// One zone per workgroup (256 lanes = 4 wave64). The zone's work is split into items
-// (task, group): a task is one (eps_i, eps_j) kernel integral -- scattering for
-// eps_i >= eps_j, pair for every (i, j) -- and a group is one quarter of its quadrature
-// rule (a Gauss-Legendre panel or a Gauss-Laguerre tail). The four groups of a task sit in
-// four neighbouring lanes and are summed with two lane swaps. Per node a lane evaluates
-// the two Fermi-Dirac blocking factors (two exp and one reciprocal) and accumulates the
-// moments sum_k W_k B_k var_k^c of the piece variable; the moments are contracted with
-// the zone-independent angular-weight coefficients in FP64 at the end of the group. Task
-// results live in LDS only: detailed-balance completion, species combination and the
-// contraction with f run from LDS, and the only HBM writes are eta/chi (or the gradients).
-// The workload is VALU/transcendental bound (no dense contraction: no MFMA).
+// A workgroup takes one zone and gives each lane whole (eps_i, eps_j) tasks: the
+// scattering kernel integral for eps_i >= eps_j or the pair kernel integral for any (i, j).
+// Tasks go to waves in units of 64 of one kind, so a wave never mixes the two kinds and
+// each kind compiles to its own code path. A task's quadrature rule has four groups of nodes (Gauss-Legendre panels and,
+// for scattering, a Gauss-Laguerre tail); every group is an affine image of one node table
+// held in LDS. Per node a lane forms the piece variable u and the two Fermi-Dirac arguments
+// from the table, evaluates the blocking factor with two exp and one reciprocal, and
+// accumulates the moments sum_k w_k B_k b(u_k) of a nonnegative basis of the angular-weight
+// piece. The moments are contracted in FP64 with the zone-independent angular-weight
+// coefficients once per task. Task values stay in LDS: detailed-balance completion, species
+// combination and the contraction with f run from LDS, and the only HBM writes are eta/chi
+// (or the gradients). The work is VALU bound with no dense contraction, so MFMA has no role.
+//
+// Mixed precision runs the bulk in FP32; zones with |eta_e| above a threshold (where
+// exp(-|eta_e|)-sized blocking factors approach the end of the FP32 range) are computed
+// entirely in FP64 by a second, sparse pass that scans the zones and takes only those.
 #include <hip/hip_runtime.h>
 
 #include "../../include/vtx_rates.h"
@@ -18,6 +23,21 @@
 
 namespace vtx {
 namespace {
+
+constexpr double kLog2e = 1.4426950408889634;
+constexpr int kM4 = kMaxNquad / 4;
+// Node table in LDS (entries of the bulk type): Gauss-Legendre x | 1 - x | w on [0, 1], then
+// Gauss-Laguerre x | w e^x. A map reads its node coordinate through a per-lane offset.
+constexpr int kOffX = 0, kOffY = kM4, kOffW = 2 * kM4, kOffGX = 3 * kM4, kOffGW = 3 * kM4 + kMaxNquad;
+constexpr int kTabLen = 3 * kM4 + 2 * kMaxNquad;
+
+// Workgroup size: four waves. The task units of a zone spread over them, and they cover the
+// per-zone contraction's 3 ne lanes up to 32 bins.
+constexpr int kBlock = 256;
+
+// Lane modes of a group: every node in the low piece, every node in the high piece, or
+// decided per node (u < split).
+constexpr int kLow = 0, kHigh = 1, kGen = 2;
 
 // Pair partner of species s: nu_e <-> anti-nu_e, nu_x <-> nu_x.
 __device__ __forceinline__ int partner(int s) { return s == 2 ? 2 : 1 - s; }
@@ -30,371 +50,501 @@ __device__ __forceinline__ double beta_of(const DevPlan& P, int s, int S) {
   return s == 0 ? b0 : (s == 1 ? b1 : b2);
 }
 
-template <typename R> struct V4;
-template <> struct V4<double> { using T = double4; };
-template <> struct V4<float> { using T = float4; };
-
-__device__ __forceinline__ double exp_neg_abs(double z) { return exp(-fabs(z)); }
-__device__ __forceinline__ float exp_neg_abs(float z) { return __expf(-fabsf(z)); }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+// Arithmetic of the bulk type. The FP32 path carries the Fermi-Dirac arguments pre-scaled
+// by log2(e), so exp(-z) is one hardware exp2.
+template <typename R> struct Num;
+template <> struct Num<double> {
+  static constexpr double zscale = 1.0;
+  static constexpr double zmin = -700.0;   // keeps exp(-z) finite where a ratio needs it
+  __device__ static __forceinline__ double exp_neg(double z) { return exp(-z); }
+  __device__ static __forceinline__ double recip(double x) { return 1.0 / x; }
+  __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+  __device__ static __forceinline__ double max(double a, double b) { return fmax(a, b); }
+};
+template <> struct Num<float> {
+  static constexpr double zscale = kLog2e;
+  static constexpr float zmin = -126.0f;
+  __device__ static __forceinline__ float exp_neg(float z) { return __builtin_amdgcn_exp2f(-z); }
+  __device__ static __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+  __device__ static __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+  __device__ static __forceinline__ float max(float a, float b) { return fmaxf(a, b); }
+};
 
 // A breakpoint: value and its derivatives along T (eta_e fixed) and along eta_e (T fixed).
 struct Tri {
   double v, dT, dE;
 };
 
-__device__ __forceinline__ void cswap(Tri& a, Tri& b) {
-  if (a.v > b.v) {
-    Tri t = a;
-    a = b;
-    b = t;
-  }
+// Component-wise select (a struct select would become an address select into scratch).
+__device__ __forceinline__ Tri sel(bool c, const Tri& a, const Tri& b) {
+  return {c ? a.v : b.v, c ? a.dT : b.dT, c ? a.dE : b.dE};
+}
+__device__ __forceinline__ Tri pick4(int g, const Tri& a, const Tri& b, const Tri& c, const Tri& d) {
+  return sel(g == 0, a, sel(g == 1, b, sel(g == 2, c, d)));
 }
 
-// value_k = c0 + c1 * (rev ? 1 - tau_k : tau_k)
-struct Aff {
-  double c0, c1;
-  bool rev;
+// Per-zone state shared by the lanes of a workgroup.
+struct Zone {
+  double T, eta, invT, mu;
+  int64_t z;   // zone index, or -1 for an empty slot
+  int valid;
 };
 
-// Anchor an affine function of the node at the end of the group where it is smaller in
-// magnitude, so that FP32 evaluation never subtracts two large numbers. Breakpoints sit on
-// the zeros of the Fermi-Dirac arguments, so inside a group each argument keeps its sign.
-__device__ __forceinline__ Aff anchor(double zA, double zB, bool lag, double slope_lag) {
-  if (lag) return {zA, slope_lag, false};
-  if (fabs(zA) <= fabs(zB)) return {zA, zB - zA, false};
-  return {zB, zA - zB, true};
-}
-
-struct Group {
-  bool lag;        // Laguerre table
-  int toff;        // offset into the Laguerre table
-  double Es;       // E = E0 + Es * tau; weight W = Es * w_table
-  Aff var, z1, z2; // piece variable and the two Fermi-Dirac arguments
-  double split;    // nodes with var < split go to the low piece
-  Tri E0;          // group start (and its derivatives)
-  double dEsT, dEsE;
-  double s1, s2;   // d z / d eta_e
-  double dvar;     // d var / dE
-  int piece;       // pair: 0, 1, 2
-};
-
-// Scattering task eps_i >= eps_j, group g in 0..3.
-//   z1 = (mu - E)/T  [F(E) = sigma(z1)],  z2 = (E + Delta - mu)/T  [1 - F(E + Delta) = sigma(z2)].
-__device__ void nes_group(const DevPlan& P, double e, double ep, int g, double T, double eta, Group& G) {
-  const double mu = eta * T, delta = e - ep;
-  if (P.rule == VTX_RULE_LAGUERRE) {
-    G.lag = true;
-    G.toff = g * P.m4;
-    G.E0 = {0.0, 0.0, 0.0};
-    G.Es = T;
-    G.dEsT = 1.0;
-    G.dEsE = 0.0;
-  } else {
-    Tri b0 = {0.0, 0.0, 0.0};
-    Tri bm = (mu - delta > 0.0) ? Tri{mu - delta, eta, T} : Tri{0.0, 0.0, 0.0};
-    Tri bu = (mu > 0.0) ? Tri{mu, eta, T} : Tri{0.0, 0.0, 0.0};
-    const double cap = bu.v + kKappa * T;
-    Tri bp = (ep <= cap) ? Tri{ep, 0.0, 0.0} : Tri{cap, bu.dT + kKappa, bu.dE};
-    cswap(b0, bm);
-    cswap(bu, bp);
-    cswap(b0, bu);
-    cswap(bm, bp);
-    cswap(bm, bu);
-    // sorted breakpoints b0 <= bm <= bu <= bp; group g spans [b_g, b_{g+1}] (g = 3: tail)
-    const Tri lo = (g == 0) ? b0 : (g == 1) ? bm : (g == 2) ? bu : bp;
-    const Tri hi = (g == 0) ? bm : (g == 1) ? bu : bp;
-    G.lag = (g == 3);
-    G.toff = 0;
-    G.E0 = lo;
-    if (g < 3) {
-      G.Es = hi.v - lo.v;
-      G.dEsT = hi.dT - lo.dT;
-      G.dEsE = hi.dE - lo.dE;
-    } else {
-      G.Es = T;
-      G.dEsT = 1.0;
-      G.dEsE = 0.0;
-    }
-  }
-  const double Ea = G.E0.v, Eb = G.E0.v + G.Es;
-  G.var = anchor(Ea / ep, Eb / ep, G.lag, T / ep);
-  G.z1 = anchor((mu - Ea) / T, (mu - Eb) / T, G.lag, -1.0);
-  G.z2 = anchor((Ea + delta - mu) / T, (Eb + delta - mu) / T, G.lag, 1.0);
-  G.split = 1.0;
-  G.s1 = 1.0;
-  G.s2 = -1.0;
-  G.dvar = 1.0 / ep;
-  G.piece = 0;
-}
-
-// Pair task (e, ep), group g in 0..3: Gauss-Legendre panels between sorted {0, m, M, c, w}.
-//   z1 = (E - mu)/T  [1 - F(E)],  z2 = (w - E + mu)/T  [1 - Fbar(w - E)].
-__device__ void pair_group(double e, double ep, int g, double T, double eta, Group& G) {
-  const double mu = eta * T, w = e + ep;
-  const double mn = fmin(e, ep), mx = fmax(e, ep);
-  Tri c = (mu > 0.0) ? (mu <= w ? Tri{mu, eta, T} : Tri{w, 0.0, 0.0}) : Tri{0.0, 0.0, 0.0};
-  // sorted {0, m, M, c, w}: c goes after every one of {0, m, M} not above it (stable order)
-  const int pos = 1 + (mn <= c.v ? 1 : 0) + (mx <= c.v ? 1 : 0);
-  const Tri t0 = {0.0, 0.0, 0.0}, tm = {mn, 0.0, 0.0}, tM = {mx, 0.0, 0.0}, tw = {w, 0.0, 0.0};
-  // element q of the sorted list: base element q for q < pos, c at pos, base element q-1 after
-  auto elem = [&](int q) -> Tri {
-    if (q == pos) return c;
-    const int k = (q < pos) ? q : q - 1;
-    return (k == 0) ? t0 : (k == 1) ? tm : (k == 2) ? tM : tw;
-  };
-  const Tri blo = elem(g), bhi = elem(g + 1);
-  G.lag = false;
-  G.toff = 0;
-  G.E0 = blo;
-  G.Es = bhi.v - blo.v;
-  G.dEsT = bhi.dT - blo.dT;
-  G.dEsE = bhi.dE - blo.dE;
-  const double Ea = G.E0.v, Eb = Ea + G.Es;
-  const double mid = Ea + 0.5 * G.Es;
-  G.piece = (mid <= mn) ? 0 : ((mid <= mx) ? 1 : 2);
-  if (G.piece == 0) {
-    G.var = anchor(Ea / mn, Eb / mn, false, 0.0);
-    G.dvar = 1.0 / mn;
-  } else if (G.piece == 1) {
-    G.var = anchor(Ea / mx, Eb / mx, false, 0.0);
-    G.dvar = 1.0 / mx;
-  } else {
-    G.var = anchor((w - Ea) / mn, (w - Eb) / mn, false, 0.0);
-    G.dvar = -1.0 / mn;
-  }
-  G.z1 = anchor((Ea - mu) / T, (Eb - mu) / T, false, 0.0);
-  G.z2 = anchor((w - Ea + mu) / T, (w - Eb + mu) / T, false, 0.0);
-  G.split = 1e30;
-  G.s1 = -1.0;
-  G.s2 = 1.0;
-}
-
-// LDS-staged node tables of one block.
-struct Tables {
-  double4 leg64[kMaxNquad / 4];
-  double4 lag64[kMaxNquad];
-  float4 leg32[kMaxNquad / 4];
-  float4 lag32[kMaxNquad];
-};
-
-__device__ void stage_tables(const DevPlan& P, Tables& tb) {
+template <typename R> __device__ void stage_tab(const DevPlan& P, R* tab);
+template <> __device__ void stage_tab<double>(const DevPlan& P, double* tab) {
   for (int k = threadIdx.x; k < P.m4; k += blockDim.x) {
-    tb.leg64[k] = P.leg64[k];
-    tb.leg32[k] = P.leg32[k];
+    const double4 n = P.leg64[k];
+    tab[kOffX + k] = n.x;
+    tab[kOffY + k] = n.y;
+    tab[kOffW + k] = n.z;
   }
   for (int k = threadIdx.x; k < P.nlag; k += blockDim.x) {
-    tb.lag64[k] = P.lag64[k];
-    tb.lag32[k] = P.lag32[k];
+    const double4 n = P.lag64[k];
+    tab[kOffGX + k] = n.x;
+    tab[kOffGW + k] = n.z;
   }
 }
-
-template <typename R> __device__ __forceinline__ const typename V4<R>::T* leg_tab(const Tables& tb);
-template <> __device__ __forceinline__ const double4* leg_tab<double>(const Tables& tb) { return tb.leg64; }
-template <> __device__ __forceinline__ const float4* leg_tab<float>(const Tables& tb) { return tb.leg32; }
-template <typename R> __device__ __forceinline__ const typename V4<R>::T* lag_tab(const Tables& tb);
-template <> __device__ __forceinline__ const double4* lag_tab<double>(const Tables& tb) { return tb.lag64; }
-template <> __device__ __forceinline__ const float4* lag_tab<float>(const Tables& tb) { return tb.lag32; }
-
-// Blocking factor sigma(z1) sigma(z2) from e_k = exp(-|z_k|).
-template <typename RF>
-__device__ __forceinline__ RF blocking(RF z1, RF z2, RF e1, RF e2) {
-  const RF num = (z1 >= RF(0) ? RF(1) : e1) * (z2 >= RF(0) ? RF(1) : e2);
-  return num * recip((RF(1) + e1) * (RF(1) + e2));
-}
-
-// Degree-7 Bernstein basis without binomials: b[k] = u^k (1 - u)^(7 - k).
-template <typename R>
-__device__ __forceinline__ void bernstein7(R u, R b[8]) {
-  const R v = R(1) - u;
-  const R u2 = u * u, u3 = u2 * u, u4 = u2 * u2, u5 = u4 * u, u6 = u3 * u3;
-  const R v2 = v * v, v3 = v2 * v, v4 = v2 * v2, v5 = v4 * v, v6 = v3 * v3;
-  b[0] = v6 * v;
-  b[1] = u * v6;
-  b[2] = u2 * v5;
-  b[3] = u3 * v4;
-  b[4] = u4 * v3;
-  b[5] = u5 * v2;
-  b[6] = u6 * v;
-  b[7] = u6 * u;
-}
-
-// Forward node loop of one group: moments M[c] = sum W B u^c (1-u)^(7-c) of the low piece
-// (nonnegative basis: positive sums, no cancellation in FP32) and Hm[c] = sum W B u^c of
-// the high piece (c = 0..2). R: bulk precision; RF: Fermi-Dirac precision.
-template <typename R, typename RF>
-__device__ __forceinline__ void node_moments(const Group& G, int m4, const Tables& tb, R M[8], R Hm[3]) {
-  const auto* tR = G.lag ? lag_tab<R>(tb) + G.toff : leg_tab<R>(tb);
-  const auto* tF = G.lag ? lag_tab<RF>(tb) + G.toff : leg_tab<RF>(tb);
-  const R v0 = R(G.var.c0), v1 = R(G.var.c1);
-  const RF a0 = RF(G.z1.c0), a1 = RF(G.z1.c1), b0 = RF(G.z2.c0), b1 = RF(G.z2.c1);
-  const R ws = R(G.Es), split = R(G.split);
-  const bool vr = G.var.rev, ar = G.z1.rev, br = G.z2.rev;
-#pragma unroll 4
-  for (int k = 0; k < m4; ++k) {
-    const auto nR = tR[k];
-    const auto nF = tF[k];
-    const R var = v0 + v1 * (vr ? nR.y : nR.x);
-    const RF z1 = a0 + a1 * (ar ? nF.y : nF.x);
-    const RF z2 = b0 + b1 * (br ? nF.y : nF.x);
-    const RF B = blocking<RF>(z1, z2, exp_neg_abs(z1), exp_neg_abs(z2));
-    const R wb = ws * nR.z * R(B);
-    // select, never subtract: wb - wl would be contracted into fma(ws w, B, -wl), which
-    // leaves the product's rounding residue in the other piece instead of zero
-    const bool lo = var < split;
-    const R wl = lo ? wb : R(0);
-    const R wh = lo ? R(0) : wb;
-    R b[8];
-    bernstein7<R>(var, b);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) M[c] += wl * b[c];
-    Hm[0] += wh;
-    Hm[1] += wh * var;
-    Hm[2] += wh * (var * var);
+template <> __device__ void stage_tab<float>(const DevPlan& P, float* tab) {
+  for (int k = threadIdx.x; k < P.m4; k += blockDim.x) {
+    const float4 n = P.leg32[k];
+    tab[kOffX + k] = n.x;
+    tab[kOffY + k] = n.y;
+    tab[kOffW + k] = n.z;
   }
-}
-
-struct Q4 {
-  double x, y, z, w;
-};
-
-// Task results (4 comps for scattering, 2 for pair) from the moments, in FP64.
-template <typename R>
-__device__ __forceinline__ Q4 contract_moments(const DevPlan& P, bool nes, int task, const Group& G,
-                                               const R M[8], const R Hm[3]) {
-  double m[8], h[3];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) m[c] = double(M[c]);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) h[c] = double(Hm[c]);
-  Q4 out = {0.0, 0.0, 0.0, 0.0};
-  if (nes) {
-    const NesCoef& C = P.nes_coef[task];
-    double s[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double a = 0.0;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) a = fma(C.lo[q][c], m[c], a);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) a = fma(C.hi[q][c], h[c], a);
-      s[q] = a;
-    }
-    out = {s[0], s[1], s[2], s[3]};
-  } else {
-    const double* c0 = P.pair_coef[task].piece[G.piece][0];
-    const double* c1 = P.pair_coef[task].piece[G.piece][1];
-    double a = 0.0, b = 0.0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      a = fma(c0[c], m[c], a);
-      b = fma(c1[c], m[c], b);
-    }
-    out.x = a;
-    out.y = b;
+  for (int k = threadIdx.x; k < P.nlag; k += blockDim.x) {
+    const float4 n = P.lag32[k];
+    tab[kOffGX + k] = n.x;
+    tab[kOffGW + k] = n.z;
   }
-  return out;
-}
-
-__device__ __forceinline__ double quad_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  return v;
 }
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// Detailed-balance factors exp(-|eps_i - eps_j|/T) and exp(-(eps_i + eps_j)/T), FP64.
-__device__ void stage_factors(const DevPlan& P, double T, double* s_d, double* s_p) {
-  const int ne = P.ne;
-  for (int k = threadIdx.x; k < ne * ne; k += blockDim.x) {
-    const int i = k / ne, j = k % ne;
-    const double ei = P.eps[i], ej = P.eps[j];
-    s_d[k] = exp(-fabs(ei - ej) / T);
-    s_p[k] = exp(-(ei + ej) / T);
+// ----------------------------------------------------------------------------------------
+// Tasks and their quadrature groups.
+//
+// Scattering (eps_i >= eps_j): z1 = (mu - E)/T [F(E)], z2 = (E + Delta - mu)/T
+// [1 - F(E + Delta)], Delta = eps_i - eps_j. Pair: z1 = (E - mu)/T [1 - F(E)],
+// z2 = (w - E + mu)/T [1 - Fbar(w - E)], w = eps_i + eps_j. Both read
+// z1 = sg (mu - E)/T and z2 = (D - sg (mu - E))/T with (sg, D) = (1, Delta) or (-1, w).
+// The blocking factor is B = sigma(z1) sigma(z2), sigma(z) = 1 / (1 + exp(-z)).
+
+struct Task {
+  bool pair;
+  int i, j;
+  double e, ep, sg, D;
+};
+
+template <bool PAIR>
+__device__ __forceinline__ Task make_task(const DevPlan& P, int t) {
+  Task K;
+  const bool pair = PAIR;
+  K.pair = pair;
+  if (pair) {
+    K.i = t / P.ne;
+    K.j = t - K.i * P.ne;
+  } else {
+    const int ij = P.nes_ij[t];
+    K.i = ij & 0xff;
+    K.j = ij >> 8;
+  }
+  K.e = P.eps[K.i];
+  K.ep = P.eps[K.j];
+  K.sg = pair ? -1.0 : 1.0;
+  K.D = pair ? K.e + K.ep : K.e - K.ep;
+  return K;
+}
+
+// One group: a Gauss-Legendre panel E = lo + (hi - lo) x, or the Gauss-Laguerre tail
+// E = lo + T x (table entries toff ...). The piece variable is u = E ub, or (w - E) ub for
+// the pair's upper piece (c). mode: see kLow/kHigh/kGen; slot: moment slot of the piece.
+struct GroupDesc {
+  Tri lo, hi;
+  bool lag, c;
+  int toff, mode, slot, piece;
+  double ub, w;
+};
+
+// Scattering breakpoints {0, (mu - Delta)+, mu+, min(eps_j, mu+ + KAPPA T)} in increasing
+// order s1 <= s2 <= s3 (the first is 0). (mu - Delta)+ <= mu+ always, so only the cap is
+// inserted.
+__device__ __forceinline__ void nes_breakpoints(double ep, double delta, const Zone& Z, Tri& s1, Tri& s2,
+                                                Tri& s3) {
+  const double mu = Z.mu, T = Z.T, eta = Z.eta;
+  const bool pm = mu - delta > 0.0, pu = mu > 0.0;
+  const Tri b1 = {pm ? mu - delta : 0.0, pm ? eta : 0.0, pm ? T : 0.0};
+  const Tri b2 = {pu ? mu : 0.0, pu ? eta : 0.0, pu ? T : 0.0};
+  const double cap = b2.v + kKappa * T;
+  const bool pp = ep <= cap;
+  const Tri b3 = {pp ? ep : cap, pp ? 0.0 : b2.dT + kKappa, pp ? 0.0 : b2.dE};
+  const bool c2 = b3.v < b2.v, c1 = b3.v < b1.v;
+  s1 = sel(c1, b3, b1);
+  s2 = sel(c1, b1, sel(c2, b3, b2));
+  s3 = sel(c2, b2, b3);
+}
+
+// Pair breakpoints {0, b1, b2, b3, w}: {m, M} with c = clip(mu, 0, w) inserted after every
+// one of {0, m, M} not above it.
+__device__ __forceinline__ void pair_breakpoints(double mn, double mx, double w, const Zone& Z, Tri& b1, Tri& b2,
+                                                 Tri& b3) {
+  const double mu = Z.mu, T = Z.T, eta = Z.eta;
+  const bool in = (mu > 0.0) && (mu <= w);
+  const double cv = (mu > 0.0) ? fmin(mu, w) : 0.0, cT = in ? eta : 0.0, cE = in ? T : 0.0;
+  const bool below_m = cv < mn, below_M = cv < mx;
+  b1 = {below_m ? cv : mn, below_m ? cT : 0.0, below_m ? cE : 0.0};
+  b2 = {below_m ? mn : (below_M ? cv : mx), (!below_m && below_M) ? cT : 0.0, (!below_m && below_M) ? cE : 0.0};
+  b3 = {below_M ? mx : cv, below_M ? 0.0 : cT, below_M ? 0.0 : cE};
+}
+
+// Group g of a task. Scattering panels lie wholly below or wholly above eps_j (eps_j is a
+// breakpoint whenever a panel could cross it), so only the tail can straddle u = 1. Each
+// pair group lies in one piece: [0, m] (A), [m, M] (B), [M, w] (C).
+template <bool PAIR>
+__device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, const Zone& Z, int g) {
+  GroupDesc G;
+  const Tri zero = {0.0, 0.0, 0.0};
+  G.w = 0.0;
+  G.c = false;
+  G.slot = 0;
+  G.piece = 0;
+  if (!PAIR) {
+    G.ub = P.inv_eps[K.j];
+    if (P.rule == VTX_RULE_LAGUERRE) {
+      G.lo = zero;
+      G.hi = zero;
+      G.lag = true;
+      G.toff = g * P.m4;
+      G.mode = kGen;
+    } else {
+      Tri s1, s2, s3;
+      nes_breakpoints(K.ep, K.D, Z, s1, s2, s3);
+      G.lo = pick4(g, zero, s1, s2, s3);
+      G.hi = pick4(g, s1, s2, s3, s3);
+      G.lag = (g == 3);
+      G.toff = 0;
+      G.mode = G.lag ? (s3.v >= K.ep ? kHigh : kGen) : (G.hi.v <= K.ep ? kLow : kHigh);
+    }
+  } else {
+    const bool le = K.e <= K.ep;
+    const double mn = le ? K.e : K.ep, mx = le ? K.ep : K.e, w = K.D;
+    Tri b1, b2, b3;
+    pair_breakpoints(mn, mx, w, Z, b1, b2, b3);
+    const Tri b4 = {w, 0.0, 0.0};
+    G.lo = pick4(g, zero, b1, b2, b3);
+    G.hi = pick4(g, b1, b2, b3, b4);
+    G.lag = false;
+    G.toff = 0;
+    const double mid = 0.5 * (G.lo.v + G.hi.v);
+    const double imn = P.inv_eps[le ? K.i : K.j], imx = P.inv_eps[le ? K.j : K.i];
+    G.piece = (mid <= mn) ? 0 : ((mid <= mx) ? 1 : 2);
+    G.ub = (G.piece == 1) ? imx : imn;
+    G.c = (G.piece == 2);
+    G.w = w;
+    G.mode = (G.piece == 1) ? kHigh : kLow;
+    G.slot = (G.piece == 2) ? 1 : 0;
+  }
+  return G;
+}
+
+// Values of the three maps at energy E.
+struct EndV {
+  double u, z1, z2;
+};
+__device__ __forceinline__ EndV end_values(const Task& K, const GroupDesc& G, const Zone& Z, double E) {
+  const double d = Z.mu - E;
+  return {G.c ? (G.w - E) * G.ub : E * G.ub, K.sg * d * Z.invT, (K.D - K.sg * d) * Z.invT};
+}
+
+// Node-loop parameters: value_k = c0 + c1 tab[off + k] per map; tab[ow + k] is the weight.
+// A Legendre map is anchored at the end where it is smaller in magnitude (reading x or
+// 1 - x), so that FP32 evaluation never subtracts two large numbers. Breakpoints sit on the
+// zeros of the Fermi-Dirac arguments, so inside a group each argument keeps its sign.
+template <typename R>
+struct Loop {
+  R u0, u1, a0, a1, b0, b1, split;
+  int ou, o1, o2, ow;
+};
+
+// Returns the group's weight scale Es (nodes weigh Es w_k).
+template <typename R>
+__device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, const Zone& Z, Loop<R>& L) {
+  const double zs = Num<R>::zscale;
+  const EndV A = end_values(K, G, Z, G.lo.v);
+  double Es;
+  if (G.lag) {
+    Es = Z.T;
+    L.u0 = R(A.u);
+    L.u1 = R((G.c ? -G.ub : G.ub) * Z.T);
+    L.a0 = R(A.z1 * zs);
+    L.a1 = R(-K.sg * zs);
+    L.b0 = R(A.z2 * zs);
+    L.b1 = R(K.sg * zs);
+    L.ou = L.o1 = L.o2 = kOffGX + G.toff;
+    L.ow = kOffGW + G.toff;
+  } else {
+    Es = G.hi.v - G.lo.v;
+    const EndV B = end_values(K, G, Z, G.hi.v);
+    const bool ru = fabs(A.u) > fabs(B.u), r1 = fabs(A.z1) > fabs(B.z1), r2 = fabs(A.z2) > fabs(B.z2);
+    L.u0 = R(ru ? B.u : A.u);
+    L.u1 = R(ru ? A.u - B.u : B.u - A.u);
+    L.a0 = R((r1 ? B.z1 : A.z1) * zs);
+    L.a1 = R((r1 ? A.z1 - B.z1 : B.z1 - A.z1) * zs);
+    L.b0 = R((r2 ? B.z2 : A.z2) * zs);
+    L.b1 = R((r2 ? A.z2 - B.z2 : B.z2 - A.z2) * zs);
+    L.ou = ru ? kOffY : kOffX;
+    L.o1 = r1 ? kOffY : kOffX;
+    L.o2 = r2 ? kOffY : kOffX;
+    L.ow = kOffW;
+  }
+  L.split = G.mode == kLow ? R(INFINITY) : (G.mode == kHigh ? R(-INFINITY) : R(1));
+  return Es;
+}
+
+// The variant a wave runs for a group: the lanes' common mode, else the general one. The
+// general loop reproduces the low and high loops bit for bit on lanes of those modes
+// (explicit fma, exact zeros), so results never depend on which lanes share a wave.
+__device__ __forceinline__ int wave_mode(int m) {
+  const bool gen = __any(m == kGen), lo = __any(m == kLow), hi = __any(m == kHigh);
+  const int wm = (gen || (lo && hi)) ? kGen : (lo ? kLow : kHigh);
+  return __builtin_amdgcn_readfirstlane(wm);
+}
+
+// ----------------------------------------------------------------------------------------
+// Node loops.
+//
+// Low piece (degree-7 angular weight with a triple zero at u = 0): moments
+//   M_j += w B u^3 q_j(u), q = (v^4, u v^3, u^2 v^2, u^3 v, u^4), v = 1 - u,
+// i.e. the folded Bernstein basis u^k v^(7-k), k = 3..7. High piece: H_k += w B u^k,
+// k = 0..2. Both bases are nonnegative on their ranges, so the FP32 sums are free of
+// cancellation; sign changes of the l = 1 weights resolve in the FP64 contraction.
+
+template <typename R, int MODE>
+__device__ __forceinline__ void node_fwd(const Loop<R>& L, R xu, R x1, R x2, R w, R M[5], R H[3]) {
+  using N = Num<R>;
+  const R u = N::fma(L.u1, xu, L.u0);
+  const R z1 = N::fma(L.a1, x1, L.a0), z2 = N::fma(L.b1, x2, L.b0);
+  const R a = N::exp_neg(z1), b = N::exp_neg(z2);
+  const R wB = w * N::recip((R(1) + a) * (R(1) + b));
+  R ul = u, wh = wB;
+  if (MODE == kGen) {
+    const bool lo = u < L.split;
+    ul = lo ? u : R(0);
+    wh = lo ? R(0) : wB;
+  }
+  if (MODE != kHigh) {
+    const R v = R(1) - ul, u2 = ul * ul, v2 = v * v, uv = ul * v;
+    const R p = wB * (u2 * ul);
+    M[0] = N::fma(p, v2 * v2, M[0]);
+    M[1] = N::fma(p, uv * v2, M[1]);
+    M[2] = N::fma(p, uv * uv, M[2]);
+    M[3] = N::fma(p, uv * u2, M[3]);
+    M[4] = N::fma(p, u2 * u2, M[4]);
+  }
+  if (MODE != kLow) {
+    H[0] = H[0] + wh;
+    H[1] = N::fma(wh, u, H[1]);
+    H[2] = N::fma(wh, u * u, H[2]);
   }
 }
 
-// Item loop shared by forward and backward value passes: tasks' kernel integrals into LDS.
-template <typename R, typename RF>
-__device__ void items_forward(const DevPlan& P, const Tables& tb, double T, double eta, int ntn_used,
-                              int ntp_used, double* s_qn, double* s_pa) {
-  const int nitems = 4 * (ntn_used + ntp_used);
-  for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
-    const int task_any = it >> 2, g = it & 3;
-    const bool nes = task_any < ntn_used;
-    const int task = nes ? task_any : task_any - ntn_used;
-    Group G;
-    int i, j;
-    if (nes) {
-      const int ij = P.nes_ij[task];
-      i = ij & 0xff;
-      j = ij >> 8;
-      nes_group(P, P.eps[i], P.eps[j], g, T, eta, G);
-    } else {
-      i = task / P.ne;
-      j = task % P.ne;
-      pair_group(P.eps[i], P.eps[j], g, T, eta, G);
+template <typename R, int MODE>
+__device__ __forceinline__ void nodes_fwd(const Loop<R>& L, int m, const R* tab, R M[5], R H[3]) {
+#pragma unroll 4
+  for (int k = 0; k < m; ++k)
+    node_fwd<R, MODE>(L, tab[L.ou + k], tab[L.o1 + k], tab[L.o2 + k], tab[L.ow + k], M, H);
+}
+
+template <typename R>
+__device__ __forceinline__ void run_nodes_fwd(int mode, const Loop<R>& L, int m, const R* tab, R M[5], R H[3]) {
+  const int wm = wave_mode(mode);
+  if (wm == kLow)
+    nodes_fwd<R, kLow>(L, m, tab, M, H);
+  else if (wm == kHigh)
+    nodes_fwd<R, kHigh>(L, m, tab, M, H);
+  else
+    nodes_fwd<R, kGen>(L, m, tab, M, H);
+}
+
+// Moment slots of a task: slot 0 low (scattering; pair piece A), high (scattering; pair
+// piece B), slot 1 low (pair piece C). Groups add Es times their moments.
+template <typename R>
+struct Slots {
+  R lo0[5], hi[3], lo1[5];
+};
+
+template <typename R>
+__device__ __forceinline__ void add_group(const GroupDesc& G, double Es, const R M[5], const R H[3], Slots<R>& S) {
+  const R es = R(Es);
+  const R e0 = G.slot == 0 ? es : R(0), e1 = G.slot == 1 ? es : R(0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    S.lo0[k] = Num<R>::fma(e0, M[k], S.lo0[k]);
+    S.lo1[k] = Num<R>::fma(e1, M[k], S.lo1[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S.hi[k] = Num<R>::fma(es, H[k], S.hi[k]);
+}
+
+// Task values (a struct, so that no array of them ever lives in scratch memory).
+struct Q4 {
+  double a, b, c, d;
+};
+
+// Task values from the slots (FP64 contraction with the coefficient tables): scattering
+// (a, b, c, d) = (S, l) = (I,0), (I,1), (II,0), (II,1); pair (a, b) = l = 0, 1 of
+// Phi_a,I(i, j).
+// Coefficient tables are read through an opaque pointer at each use, so that the compiler
+// reloads them (from cache) instead of keeping 26-32 doubles live across the node loops.
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
+template <typename R, bool PAIR>
+__device__ __forceinline__ Q4 contract_task(const DevPlan& P, int t, const Slots<R>& S) {
+  double q[4];
+  if (!PAIR) {
+    const NesCoef& C = *opaque(P.nes_coef + t);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) a = fma(C.lo[c][k], double(S.lo0[k]), a);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a = fma(C.hi[c][k], double(S.hi[k]), a);
+      q[c] = a;
     }
-    R M[8] = {0, 0, 0, 0, 0, 0, 0, 0}, Hm[3] = {0, 0, 0};
-    node_moments<R, RF>(G, P.m4, tb, M, Hm);
-    Q4 o = contract_moments<R>(P, nes, task, G, M, Hm);
-    o.x = quad_sum(o.x);
-    o.y = quad_sum(o.y);
-    o.z = quad_sum(o.z);
-    o.w = quad_sum(o.w);
-    if (g == 0) {
-      if (nes) {
-        double* q = s_qn + 4 * task;
-        q[0] = o.x;
-        q[1] = o.y;
-        q[2] = o.z;
-        q[3] = o.w;
-      } else {
-        s_pa[2 * task] = o.x;
-        s_pa[2 * task + 1] = o.y;
+  } else {
+    const PairCoef& C = *opaque(P.pair_coef + t);
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) a = fma(C.A[l][k], double(S.lo0[k]), a);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a = fma(C.B[l][k], double(S.hi[k]), a);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) a = fma(C.C[l][k], double(S.lo1[k]), a);
+      q[l] = a;
+    }
+    q[2] = q[3] = 0.0;
+  }
+  return {q[0], q[1], q[2], q[3]};
+}
+
+template <typename R, bool PAIR>
+__device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const Zone& Z, int t) {
+  const Task K = make_task<PAIR>(P, t);
+  Slots<R> S = {};
+  for (int g = 0; g < 4; ++g) {
+    const GroupDesc G = describe<PAIR>(P, K, Z, g);
+    Loop<R> L;
+    const double Es = make_loop<R>(K, G, Z, L);
+    R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0};
+    run_nodes_fwd<R>(G.mode, L, P.m4, tab, M, H);
+    add_group<R>(G, Es, M, H, S);
+  }
+  return contract_task<R, PAIR>(P, t, S);
+}
+
+// ----------------------------------------------------------------------------------------
+// Workgroup layout: one zone per workgroup; in LDS (doubles): f [6 ne] | scattering task
+// values [4 ntn] | pair task values [2 ntp] | exp(-|eps_i - eps_j|/T) [ne^2] |
+// exp(-(eps_i + eps_j)/T) [ne^2]; the backward also holds g_eta, g_chi [12 ne] after f.
+
+// Zone selection of a pass: every zone, or the zones the FP32 pass takes (|eta_e| not above
+// the threshold, which includes values that do not compare).
+constexpr int kSelAll = 0, kSelBulk = 1;
+
+__device__ void stage_zone_state(const DevPlan& P, int64_t z, int selm, const double* Tz, const double* etaz,
+                                 Zone* zs) {
+  if (threadIdx.x == 0) {
+    Zone Z;
+    Z.z = z;
+    Z.valid = z >= 0;
+    Z.T = Z.valid ? Tz[z] : 1.0;
+    Z.eta = Z.valid ? etaz[z] : 0.0;
+    if (selm == kSelBulk && fabs(Z.eta) > P.eta_fp64) Z.valid = 0;
+    Z.invT = 1.0 / Z.T;
+    Z.mu = Z.eta * Z.T;
+    *zs = Z;
+  }
+}
+
+// Detailed-balance factors exp(-|eps_i - eps_j|/T) and exp(-(eps_i + eps_j)/T), FP64.
+__device__ void stage_factors(const DevPlan& P, const Zone& Z, double* s_d) {
+  const int ne = P.ne, n2 = ne * ne;
+  for (int r = threadIdx.x; r < n2; r += blockDim.x) {
+    const int i = r / ne, j = r % ne;
+    const double ei = P.eps[i], ej = P.eps[j];
+    s_d[r] = exp(-fabs(ei - ej) * Z.invT);
+    s_d[n2 + r] = exp(-(ei + ej) * Z.invT);
+  }
+}
+
+// Task units: units 0 .. nN-1 hold 64 scattering tasks each, the rest 64 pair tasks. Wave w
+// of workgroup b takes units (w + b) mod W, + W, ...; the rotation spreads the wave that
+// holds one unit fewer over the SIMDs.
+struct Units {
+  int nN, nU, first, step;
+};
+__device__ __forceinline__ Units task_units(int ntn, int ntp) {
+  Units U;
+  U.nN = (ntn + 63) >> 6;
+  U.nU = U.nN + ((ntp + 63) >> 6);
+  U.step = blockDim.x >> 6;
+  U.first = __builtin_amdgcn_readfirstlane((int)(((threadIdx.x >> 6) + blockIdx.x) % U.step));
+  return U;
+}
+
+template <typename R>
+__device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* smem, int64_t z, int selm,
+                             const double* __restrict__ Tz, const double* __restrict__ etaz,
+                             const double* __restrict__ f, double* __restrict__ eta_out,
+                             double* __restrict__ chi_out) {
+  const int ne = P.ne;
+  const int off_q = 6 * ne, off_p = off_q + 4 * P.ntn, off_d = off_p + 2 * P.ntp, n2 = ne * ne;
+  const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
+  const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntp : 0;
+  stage_zone_state(P, z, selm, Tz, etaz, zs);
+  __syncthreads();
+  const Zone& Z = *zs;
+  if (!Z.valid) return;   // uniform: every lane reads the same zone state
+  for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
+  stage_factors(P, Z, smem + off_d);
+  const Units U = task_units(ntn, ntp);
+  const int lane = threadIdx.x & 63;
+  for (int u = U.first; u < U.nU; u += U.step) {
+    if (u < U.nN) {
+      const int t = (u << 6) + lane;
+      if (t < ntn) {
+        const Q4 q = task_forward<R, false>(P, tab, Z, t);
+        double* o = smem + off_q + 4 * t;
+        o[0] = q.a;
+        o[1] = q.b;
+        o[2] = q.c;
+        o[3] = q.d;
+      }
+    } else {
+      const int t = ((u - U.nN) << 6) + lane;
+      if (t < ntp) {
+        const Q4 q = task_forward<R, true>(P, tab, Z, t);
+        double* o = smem + off_p + 2 * t;
+        o[0] = q.a;
+        o[1] = q.b;
       }
     }
   }
-}
-
-template <typename R>
-__device__ void items_forward_dispatch(const DevPlan& P, const Tables& tb, double T, double eta, int ntn_used,
-                                       int ntp_used, double* s_qn, double* s_pa) {
-  if (sizeof(R) == sizeof(float) && eta > P.eta_fp64)
-    items_forward<float, double>(P, tb, T, eta, ntn_used, ntp_used, s_qn, s_pa);
-  else
-    items_forward<R, R>(P, tb, T, eta, ntn_used, ntp_used, s_qn, s_pa);
-}
-
-template <typename R>
-__global__ __launch_bounds__(kBlock) void rates_forward_kernel(DevPlan P, const double* __restrict__ Tz,
-                                                               const double* __restrict__ etaz,
-                                                               const double* __restrict__ f,
-                                                               double* __restrict__ eta_out,
-                                                               double* __restrict__ chi_out) {
-  __shared__ Tables tb;
-  extern __shared__ double smem[];
-  const int ne = P.ne;
-  const int64_t z = blockIdx.x;
-  const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
-  double* s_f = smem;                 // [6 ne]
-  double* s_qn = s_f + 6 * ne;        // [4 ntn]
-  double* s_pa = s_qn + 4 * P.ntn;    // [2 ntp]
-  double* s_d = s_pa + 2 * P.ntp;     // [ne ne]
-  double* s_p = s_d + ne * ne;        // [ne ne]
-  const double T = Tz[z], eta = etaz[z];
-  const double* fz = f + z * 6 * ne;
-  for (int k = threadIdx.x; k < 6 * ne; k += blockDim.x) s_f[k] = fz[k];
-  stage_tables(P, tb);
-  stage_factors(P, T, s_d, s_p);
   __syncthreads();
-  items_forward_dispatch<R>(P, tb, T, eta, do_nes ? P.ntn : 0, do_pair ? P.ntp : 0, s_qn, s_pa);
-  __syncthreads();
-  const int tid = threadIdx.x;
-  if (tid < 3 * ne) {
-    const int s = tid / ne, i = tid % ne, sb = partner(s);
+  // completion, species combination and contraction: one lane per (species, bin)
+  for (int r = threadIdx.x; r < 3 * ne; r += blockDim.x) {
+    const int s = r / ne, i = r % ne, sb = partner(s);
+    const double* s_f = smem;
+    const double* s_qn = smem + off_q;
+    const double* s_pa = smem + off_p;
+    const double* s_d = smem + off_d;
+    const double* s_p = s_d + n2;
     const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
     double e0 = 0.0, c0 = 0.0, e1 = 0.0, c1 = 0.0;
     for (int j = 0; j < ne; ++j) {
@@ -427,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void rates_forward_kernel(DevPlan P, const 
         c1 += t1 - t1 * pf;
       }
     }
-    const int64_t o = z * 6 * ne + (2 * s) * ne + i;
+    const int64_t o = Z.z * 6 * ne + (2 * s) * ne + i;
     eta_out[o] = e0;
     chi_out[o] = c0;
     eta_out[o + ne] = e1;
@@ -435,10 +585,65 @@ __global__ __launch_bounds__(kBlock) void rates_forward_kernel(DevPlan P, const 
   }
 }
 
+// Dense pass: workgroup b takes zone b (if selected).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void rates_forward_kernel(DevPlan P, int64_t nz, int selm,
+                                                                  const double* __restrict__ Tz,
+                                                                  const double* __restrict__ etaz,
+                                                                  const double* __restrict__ f,
+                                                                  double* __restrict__ eta_out,
+                                                                  double* __restrict__ chi_out) {
+  __shared__ R tab[kTabLen];
+  __shared__ Zone zs;
+  extern __shared__ double smem[];
+  stage_tab<R>(P, tab);
+  const int64_t z = blockIdx.x;
+  zone_forward<R>(P, tab, &zs, smem, z < nz ? z : -1, selm, Tz, etaz, f, eta_out, chi_out);
+}
+
+// Sparse FP64 pass: workgroups scan windows of blockDim zones and run the zones with
+// |eta_e| above the threshold, one at a time. The scan order does not change any result.
+__global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_t nz,
+                                                                  const double* __restrict__ Tz,
+                                                                  const double* __restrict__ etaz,
+                                                                  const double* __restrict__ f,
+                                                                  double* __restrict__ eta_out,
+                                                                  double* __restrict__ chi_out) {
+  __shared__ double tab[kTabLen];
+  __shared__ Zone zs;
+  __shared__ int list[kBlock];
+  __shared__ int count;
+  extern __shared__ double smem[];
+  stage_tab<double>(P, tab);
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nz; base += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    const int64_t z = base + threadIdx.x;
+    if (z < nz && fabs(etaz[z]) > P.eta_fp64) list[atomicAdd(&count, 1)] = (int)threadIdx.x;
+    __syncthreads();
+    const int n = count;
+    for (int c = 0; c < n; ++c) {
+      zone_forward<double>(P, tab, &zs, smem, base + list[c], kSelAll, Tz, etaz, f, eta_out, chi_out);
+      __syncthreads();
+    }
+    __syncthreads();   // every lane has read count before the next window resets it
+  }
+}
+
+
 // ---------------------------------------------------------------------------------------
 // Backward (vector-Jacobian product). Recomputes every task's kernel values and, in the
 // same node loop, the derivative of the adjoint-weighted kernel sum_c A_c q_c along T and
-// eta_e (node motion included). A_c are the upstream weights of each task component.
+// eta_e, node motion included. A_c are the upstream weights of each task component.
+//
+// With the node maps value = c0 + c1 x for the three maps m (x the node coordinate the map
+// reads) and the group weight Es w_k, the derivative of Es sum_k w_k B_k H(u_k) along
+// theta is
+//   dEs/dtheta sum w B H + Es sum_m [dc0_m/dtheta S_m + dc1_m/dtheta S_mx],
+// S_z = sum w B H r_z, S_zx = sum w B H r_z x (r_z = d log sigma / dz = 1 - sigma(z)) for
+// the two Fermi-Dirac arguments and S_u = sum w B dH/du, S_ux = sum w B dH/du x. The node
+// loop accumulates these sums; the group end applies the FP64 derivatives of the anchored
+// map coefficients, which depend only on the group's end points.
 
 struct Adj {
   const double* f;
@@ -485,234 +690,324 @@ __device__ double pair_gw(const DevPlan& P, const Adj& A, int S, int l, int a, i
   return P.c0w[b] * acc;
 }
 
-template <typename R, typename RF>
-__device__ __forceinline__ void node_loop_bwd(const Group& G, int m4, const Tables& tb, double T, double eta,
-                                              const R hl[8], const R hh[3], const R dl[8], const R dh[2],
-                                              R M[8], R Hm[3], R& accT, R& accE) {
-  const auto* tR = G.lag ? lag_tab<R>(tb) + G.toff : leg_tab<R>(tb);
-  const auto* tF = G.lag ? lag_tab<RF>(tb) + G.toff : leg_tab<RF>(tb);
-  const R v0 = R(G.var.c0), v1 = R(G.var.c1);
-  const RF a0 = RF(G.z1.c0), a1 = RF(G.z1.c1), b0 = RF(G.z2.c0), b1 = RF(G.z2.c1);
-  const R ws = R(G.Es), split = R(G.split);
-  const bool vr = G.var.rev, ar = G.z1.rev, br = G.z2.rev;
-  const R s1 = R(G.s1), s2 = R(G.s2);
-  const R invT = R(1.0 / T), etaR = R(eta);
-  const R dE0T = R(G.E0.dT), dEsT = R(G.dEsT), dE0E = R(G.E0.dE), dEsE = R(G.dEsE);
-#pragma unroll 2
-  for (int k = 0; k < m4; ++k) {
-    const auto nR = tR[k];
-    const auto nF = tF[k];
-    const R var = v0 + v1 * (vr ? nR.y : nR.x);
-    const RF z1 = a0 + a1 * (ar ? nF.y : nF.x);
-    const RF z2 = b0 + b1 * (br ? nF.y : nF.x);
-    const RF e1 = exp_neg_abs(z1), e2 = exp_neg_abs(z2);
-    const RF i1 = recip(RF(1) + e1), i2 = recip(RF(1) + e2);
-    const RF sg1 = (z1 >= RF(0) ? RF(1) : e1) * i1, sg2 = (z2 >= RF(0) ? RF(1) : e2) * i2;
-    const RF r1 = (z1 >= RF(0) ? e1 : RF(1)) * i1, r2 = (z2 >= RF(0) ? e2 : RF(1)) * i2;
-    const R B = R(sg1 * sg2);
-    const R wt = nR.z;
-    const R wb = ws * wt * B;
-    // value moments
-    const bool lo = var < split;
-    const R wl = lo ? wb : R(0);
-    const R wh = lo ? R(0) : wb;   // select, never subtract (see node_moments)
-    R b[8];
-    bernstein7<R>(var, b);
-    R Hlo = R(0), Dlo = R(0);
+// Adjoint-weighted angular weight of a piece and its u-derivative:
+//   low:  H = u^3 sum_j hl_j q_j(u), dH/du = u^2 sum_j dl_j q_j(u);
+//   high: H = hh0 + hh1 u + hh2 u^2, dH/du = dh0 + dh1 u.
+template <typename R>
+struct AdjPoly {
+  R hl[5], dl[5], hh[3], dh[2];
+};
+
+// From folded Bernstein coefficients g_3..g_7 (g_k of u^k v^(7-k)), differentiating term by
+// term: dH/du = sum_m D_m u^m v^(6-m), D_m = (m + 1) g_(m+1) - (7 - m) g_m, m = 2..6.
+template <typename R>
+__device__ __forceinline__ void make_adj_poly(const double lo[5], const double hi[3], AdjPoly<R>& Q) {
+  Q.dl[0] = R(3.0 * lo[0]);
+  Q.dl[1] = R(4.0 * lo[1] - 4.0 * lo[0]);
+  Q.dl[2] = R(5.0 * lo[2] - 3.0 * lo[1]);
+  Q.dl[3] = R(6.0 * lo[3] - 2.0 * lo[2]);
+  Q.dl[4] = R(7.0 * lo[4] - lo[3]);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      M[c] += wl * b[c];
-      Hlo += hl[c] * b[c];
-      Dlo += dl[c] * b[c];
-    }
-    Hm[0] += wh;
-    Hm[1] += wh * var;
-    Hm[2] += wh * (var * var);
-    // derivatives of log B at fixed E, and along E
-    const R rr1 = R(r1), rr2 = R(r2);
-    const R dlE = s1 * rr1 + s2 * rr2;                                    // d/deta
-    const R dlT = -(rr1 * R(z1) + rr2 * R(z2) - etaR * dlE) * invT;       // d/dT
-    const R dlX = -dlE * invT;                                            // d/dE
-    // node motion
-    const R tau = nR.x;
-    const R dET = dE0T + dEsT * tau, dEE = dE0E + dEsE * tau;
-    // adjoint-weighted angular weight and its E-derivative (low piece: Bernstein above)
-    const R Hhi = (hh[2] * var + hh[1]) * var + hh[0];
-    const R Dhi = dh[1] * var + dh[0];
-    const R H = lo ? Hlo : Hhi;
-    const R D = lo ? Dlo : Dhi;
-    const R wtB = wt * B;
-    const R aT = dEsT * wtB + wb * (dlT + dlX * dET);
-    const R aE = dEsE * wtB + wb * (dlE + dlX * dEE);
-    accT += aT * H + wb * dET * D;
-    accE += aE * H + wb * dEE * D;
-  }
+  for (int k = 0; k < 5; ++k) Q.hl[k] = R(lo[k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Q.hh[k] = R(hi[k]);
+  Q.dh[0] = R(hi[1]);
+  Q.dh[1] = R(2.0 * hi[2]);
 }
 
-template <typename R, typename RF>
-__device__ void items_backward(const DevPlan& P, const Tables& tb, double T, double eta, int ntn_used,
-                               int ntp_used, const double* s_adj, const double* s_uadj, double* s_qn,
-                               double* s_pa, double& gT, double& gE) {
-  const int nitems = 4 * (ntn_used + ntp_used);
-  for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
-    const int task_any = it >> 2, g = it & 3;
-    const bool nes = task_any < ntn_used;
-    const int task = nes ? task_any : task_any - ntn_used;
-    Group G;
-    int i, j;
-    double hl64[8], hh64[3];
-    if (nes) {
-      const int ij = P.nes_ij[task];
-      i = ij & 0xff;
-      j = ij >> 8;
-      nes_group(P, P.eps[i], P.eps[j], g, T, eta, G);
-      const NesCoef& C = P.nes_coef[task];
-      const double* a = s_adj + 4 * task;
-      for (int c = 0; c < 8; ++c) hl64[c] = a[0] * C.lo[0][c] + a[1] * C.lo[1][c] + a[2] * C.lo[2][c] + a[3] * C.lo[3][c];
-      for (int c = 0; c < 3; ++c) hh64[c] = a[0] * C.hi[0][c] + a[1] * C.hi[1][c] + a[2] * C.hi[2][c] + a[3] * C.hi[3][c];
+template <typename R, int MODE>
+__device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, R xu, R x1, R x2, R w, R M[5],
+                                         R H[3], R S[7]) {
+  using N = Num<R>;
+  const R u = N::fma(L.u1, xu, L.u0);
+  const R z1 = N::fma(L.a1, x1, L.a0), z2 = N::fma(L.b1, x2, L.b0);
+  const R a = N::exp_neg(N::max(z1, R(N::zmin))), b = N::exp_neg(N::max(z2, R(N::zmin)));
+  const R i1 = N::recip(R(1) + a), i2 = N::recip(R(1) + b);
+  const R wB = w * (i1 * i2);
+  const R r1 = a * i1, r2 = b * i2;
+  R ul = u, wh = wB;
+  if (MODE == kGen) {
+    const bool lo = u < L.split;
+    ul = lo ? u : R(0);
+    wh = lo ? R(0) : wB;
+  }
+  R x0 = R(0), yu = R(0);
+  if (MODE != kHigh) {
+    const R v = R(1) - ul, u2 = ul * ul, v2 = v * v, uv = ul * v;
+    const R q0 = v2 * v2, q1 = uv * v2, q2 = uv * uv, q3 = uv * u2, q4 = u2 * u2;
+    const R p = wB * (u2 * ul);
+    M[0] = N::fma(p, q0, M[0]);
+    M[1] = N::fma(p, q1, M[1]);
+    M[2] = N::fma(p, q2, M[2]);
+    M[3] = N::fma(p, q3, M[3]);
+    M[4] = N::fma(p, q4, M[4]);
+    const R hq = N::fma(Q.hl[4], q4, N::fma(Q.hl[3], q3, N::fma(Q.hl[2], q2, N::fma(Q.hl[1], q1, Q.hl[0] * q0))));
+    const R dq = N::fma(Q.dl[4], q4, N::fma(Q.dl[3], q3, N::fma(Q.dl[2], q2, N::fma(Q.dl[1], q1, Q.dl[0] * q0))));
+    x0 = p * hq;
+    yu = (wB * u2) * dq;
+  }
+  if (MODE != kLow) {
+    H[0] = H[0] + wh;
+    H[1] = N::fma(wh, u, H[1]);
+    H[2] = N::fma(wh, u * u, H[2]);
+    const R hh = N::fma(N::fma(Q.hh[2], u, Q.hh[1]), u, Q.hh[0]);
+    const R dh = N::fma(Q.dh[1], u, Q.dh[0]);
+    if (MODE == kHigh) {
+      x0 = wh * hh;
+      yu = wh * dh;
     } else {
-      i = task / P.ne;
-      j = task % P.ne;
-      pair_group(P.eps[i], P.eps[j], g, T, eta, G);
-      const PairCoef& C = P.pair_coef[task];
-      const double* a = s_adj + 4 * P.ntn + 2 * task;
-      for (int c = 0; c < 8; ++c) hl64[c] = a[0] * C.piece[G.piece][0][c] + a[1] * C.piece[G.piece][1][c];
-      for (int c = 0; c < 3; ++c) hh64[c] = 0.0;
-    }
-    // d/dE of the low piece, in the same folded degree-7 Bernstein basis: with beta_k =
-    // g_k / C(7,k), dH/du has degree-6 coefficients d_k = 7 (beta_{k+1} - beta_k); degree
-    // elevation gives D_k = (k/7) d_{k-1} + (1 - k/7) d_k; fold C(7,k) back and scale by du/dE.
-    constexpr double kBin7[8] = {1.0, 7.0, 21.0, 35.0, 35.0, 21.0, 7.0, 1.0};
-    double d6[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) d6[c] = 7.0 * (hl64[c + 1] / kBin7[c + 1] - hl64[c] / kBin7[c]);
-    R hl[8], hh[3], dl[8], dh[2];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const double lower = (c > 0) ? (c / 7.0) * d6[c - 1] : 0.0;
-      const double upper = (c < 7) ? (1.0 - c / 7.0) * d6[c] : 0.0;
-      hl[c] = R(hl64[c]);
-      dl[c] = R((lower + upper) * kBin7[c] * G.dvar);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) hh[c] = R(hh64[c]);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) dh[c] = R(hh64[c + 1] * (c + 1) * G.dvar);
-    R M[8] = {0, 0, 0, 0, 0, 0, 0, 0}, Hm[3] = {0, 0, 0};
-    R accT = 0, accE = 0;
-    node_loop_bwd<R, RF>(G, P.m4, tb, T, eta, hl, hh, dl, dh, M, Hm, accT, accE);
-    gT += double(accT);
-    gE += double(accE);
-    Q4 o = contract_moments<R>(P, nes, task, G, M, Hm);
-    o.x = quad_sum(o.x);
-    o.y = quad_sum(o.y);
-    o.z = quad_sum(o.z);
-    o.w = quad_sum(o.w);
-    if (g == 0) {
-      if (nes) {
-        const double* u = s_uadj + 4 * task;
-        const double de = (P.eps[i] - P.eps[j]) / (T * T);
-        gT += (o.x * u[0] + o.y * u[1] + o.z * u[2] + o.w * u[3]) * de;
-        double* q = s_qn + 4 * task;   // same slot: read above, overwritten now
-        q[0] = o.x;
-        q[1] = o.y;
-        q[2] = o.z;
-        q[3] = o.w;
-      } else {
-        const double* u = s_uadj + 4 * P.ntn + 2 * task;
-        const double u0 = u[0], u1 = u[1];
-        s_pa[2 * task] = o.x;
-        s_pa[2 * task + 1] = o.y;
-        gT += o.x * u0 + o.y * u1;
-      }
+      x0 = N::fma(wh, hh, x0);
+      yu = N::fma(wh, dh, yu);
     }
   }
+  S[0] = S[0] + x0;
+  const R y1 = x0 * r1, y2 = x0 * r2;
+  S[1] = S[1] + y1;
+  S[2] = N::fma(y1, x1, S[2]);
+  S[3] = S[3] + y2;
+  S[4] = N::fma(y2, x2, S[4]);
+  S[5] = S[5] + yu;
+  S[6] = N::fma(yu, xu, S[6]);
 }
 
-__device__ double block_sum(double v, double* scratch) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) scratch[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += scratch[k];
-  return t;
+template <typename R, int MODE>
+__device__ __forceinline__ void nodes_bwd(const Loop<R>& L, const AdjPoly<R>& Q, int m, const R* tab, R M[5],
+                                          R H[3], R S[7]) {
+#pragma unroll 2
+  for (int k = 0; k < m; ++k)
+    node_bwd<R, MODE>(L, Q, tab[L.ou + k], tab[L.o1 + k], tab[L.o2 + k], tab[L.ow + k], M, H, S);
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void rates_backward_kernel(
-    DevPlan P, const double* __restrict__ Tz, const double* __restrict__ etaz, const double* __restrict__ f,
-    const double* __restrict__ g_eta, const double* __restrict__ g_chi, double* __restrict__ gT_out,
-    double* __restrict__ gE_out, double* __restrict__ gf_out) {
-  __shared__ Tables tb;
-  __shared__ double red[8];
-  extern __shared__ double smem[];
-  const int ne = P.ne;
-  const int64_t z = blockIdx.x;
+__device__ __forceinline__ void run_nodes_bwd(int mode, const Loop<R>& L, const AdjPoly<R>& Q, int m, const R* tab,
+                                              R M[5], R H[3], R S[7]) {
+  const int wm = wave_mode(mode);
+  if (wm == kLow)
+    nodes_bwd<R, kLow>(L, Q, m, tab, M, H, S);
+  else if (wm == kHigh)
+    nodes_bwd<R, kHigh>(L, Q, m, tab, M, H, S);
+  else
+    nodes_bwd<R, kGen>(L, Q, m, tab, M, H, S);
+}
+
+// Derivatives of the map values at a group end E (a breakpoint with its derivatives):
+// z1 = sg (mu - E)/T gives dz1/dT = sg (eta - E_T)/T - z1/T, dz1/deta = sg (1 - E_eta/T);
+// z2 = D/T - z1 - ... gives dz2/dT = -sg (eta - E_T)/T - z2/T, dz2/deta = -dz1/deta;
+// u = E ub (or (w - E) ub) gives du = +-ub dE.
+struct EndD {
+  double uT, uE, z1T, z1E, z2T, z2E;
+};
+__device__ __forceinline__ EndD end_derivs(const Task& K, const GroupDesc& G, const Zone& Z, const Tri& E,
+                                           const EndV& v) {
+  const double gT = K.sg * (Z.eta - E.dT) * Z.invT, gE = K.sg * (1.0 - E.dE * Z.invT);
+  const double dudE = G.c ? -G.ub : G.ub;
+  return {dudE * E.dT, dudE * E.dE, gT - v.z1 * Z.invT, gE, -gT - v.z2 * Z.invT, -gE};
+}
+
+// Group end of the backward: adds the group's d/dT and d/deta_e of the adjoint-weighted
+// kernel. The anchoring choices repeat those of make_loop (same inputs, same decisions).
+template <typename R>
+__device__ __forceinline__ void group_grad(const Task& K, const GroupDesc& G, const Zone& Z, double Es, const R S[7],
+                                           double& gT, double& gE) {
+  const EndV A = end_values(K, G, Z, G.lo.v);
+  const EndD dA = end_derivs(K, G, Z, G.lo, A);
+  double u0T, u0E, u1T, u1E, a0T, a0E, a1T, a1E, b0T, b0E, b1T, b1E, EsT, EsE;
+  if (G.lag) {
+    u0T = dA.uT;
+    u0E = dA.uE;
+    u1T = G.c ? -G.ub : G.ub;
+    u1E = 0.0;
+    a0T = dA.z1T;
+    a0E = dA.z1E;
+    b0T = dA.z2T;
+    b0E = dA.z2E;
+    a1T = a1E = b1T = b1E = 0.0;
+    EsT = 1.0;
+    EsE = 0.0;
+  } else {
+    const EndV B = end_values(K, G, Z, G.hi.v);
+    const EndD dB = end_derivs(K, G, Z, G.hi, B);
+    const bool ru = fabs(A.u) > fabs(B.u), r1 = fabs(A.z1) > fabs(B.z1), r2 = fabs(A.z2) > fabs(B.z2);
+    u0T = ru ? dB.uT : dA.uT;
+    u0E = ru ? dB.uE : dA.uE;
+    u1T = ru ? dA.uT - dB.uT : dB.uT - dA.uT;
+    u1E = ru ? dA.uE - dB.uE : dB.uE - dA.uE;
+    a0T = r1 ? dB.z1T : dA.z1T;
+    a0E = r1 ? dB.z1E : dA.z1E;
+    a1T = r1 ? dA.z1T - dB.z1T : dB.z1T - dA.z1T;
+    a1E = r1 ? dA.z1E - dB.z1E : dB.z1E - dA.z1E;
+    b0T = r2 ? dB.z2T : dA.z2T;
+    b0E = r2 ? dB.z2E : dA.z2E;
+    b1T = r2 ? dA.z2T - dB.z2T : dB.z2T - dA.z2T;
+    b1E = r2 ? dA.z2E - dB.z2E : dB.z2E - dA.z2E;
+    EsT = G.hi.dT - G.lo.dT;
+    EsE = G.hi.dE - G.lo.dE;
+  }
+  const double s0 = double(S[0]), s1 = double(S[1]), s2 = double(S[2]), s3 = double(S[3]), s4 = double(S[4]),
+               s5 = double(S[5]), s6 = double(S[6]);
+  gT += Es * (u0T * s5 + u1T * s6 + a0T * s1 + a1T * s2 + b0T * s3 + b1T * s4) + EsT * s0;
+  gE += Es * (u0E * s5 + u1E * s6 + a0E * s1 + a1E * s2 + b0E * s3 + b1E * s4) + EsE * s0;
+}
+
+// Recompute one task with derivatives. adj: upstream weights of the task components
+// (scattering: 4; pair: 2). Returns the task values q and adds d/dT, d/deta_e to gT, gE.
+template <typename R, bool PAIR>
+__device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, const Zone& Z, int t, const Q4& adj,
+                                            double& gT, double& gE) {
+  const Task K = make_task<PAIR>(P, t);
+  Slots<R> Sl = {};
+  AdjPoly<R> Q;
+  if (!PAIR) {
+    const NesCoef& C = *opaque(P.nes_coef + t);
+    double lo[5], hi[3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      lo[k] = adj.a * C.lo[0][k] + adj.b * C.lo[1][k] + adj.c * C.lo[2][k] + adj.d * C.lo[3][k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      hi[k] = adj.a * C.hi[0][k] + adj.b * C.hi[1][k] + adj.c * C.hi[2][k] + adj.d * C.hi[3][k];
+    make_adj_poly<R>(lo, hi, Q);
+  }
+  for (int g = 0; g < 4; ++g) {
+    const GroupDesc G = describe<PAIR>(P, K, Z, g);
+    Loop<R> L;
+    const double Es = make_loop<R>(K, G, Z, L);
+    if (PAIR) {
+      const PairCoef& C = *opaque(P.pair_coef + t);
+      double lo[5], hi[3];
+      const bool pc = G.piece == 2;
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        lo[k] = G.piece == 1 ? 0.0 : adj.a * (pc ? C.C[0][k] : C.A[0][k]) + adj.b * (pc ? C.C[1][k] : C.A[1][k]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) hi[k] = G.piece == 1 ? adj.a * C.B[0][k] + adj.b * C.B[1][k] : 0.0;
+      make_adj_poly<R>(lo, hi, Q);
+    }
+    R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0}, S[7] = {0, 0, 0, 0, 0, 0, 0};
+    run_nodes_bwd<R>(G.mode, L, Q, P.m4, tab, M, H, S);
+    add_group<R>(G, Es, M, H, Sl);
+    group_grad<R>(K, G, Z, Es, S, gT, gE);
+  }
+  return contract_task<R, PAIR>(P, t, Sl);
+}
+
+// Sum over the 64 lanes of a wave (lane 0's value is the one used: its summation order
+// depends only on lane positions).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Scattering task t in the backward: upstream weights of its components, recomputation with
+// derivatives, and the T-derivative of its detailed-balance completion. The task's LDS slot
+// holds the completion weights until the task values replace them.
+template <typename R>
+__device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
+                                             const double* s_d, double* s_u, int t, double& dT, double& dE) {
+  const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
+  const double d = s_d[i * ne + j];
+  double* o = s_u + 4 * t;
+  double w[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int S = c >> 1, l = c & 1;
+    const double up = (i > j) ? d * nes_ghat(P, A, S, l, j, i) : 0.0;
+    w[c] = nes_ghat(P, A, S, l, i, j) + up;
+    o[c] = up;
+  }
+  const Q4 q = task_backward<R, false>(P, tab, Z, t, Q4{w[0], w[1], w[2], w[3]}, dT, dE);
+  // completion: Phi_out(j, i) = exp(-(eps_i - eps_j)/T) q, d/dT = (eps_i - eps_j)/T^2 times it
+  dT += (q.a * o[0] + q.b * o[1] + q.c * o[2] + q.d * o[3]) * (P.eps[i] - P.eps[j]) * (Z.invT * Z.invT);
+  o[0] = q.a;
+  o[1] = q.b;
+  o[2] = q.c;
+  o[3] = q.d;
+}
+
+// Pair task t = i ne + j in the backward; the production factor's weights wait in the
+// task's LDS slot.
+template <typename R>
+__device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
+                                              const double* s_p, double* s_u, int t, double& dT, double& dE) {
+  const int ne = P.ne, i = t / ne, j = t - i * ne;
+  const double pf = s_p[t];
+  double* o = s_u + 4 * P.ntn + 2 * t;
+  const double w0 = pair_gw(P, A, 0, 0, i, j, pf, false) + pair_gw(P, A, 1, 0, j, i, pf, false);
+  const double w1 = pair_gw(P, A, 0, 1, i, j, pf, false) + pair_gw(P, A, 1, 1, j, i, pf, false);
+  o[0] = pair_gw(P, A, 0, 0, i, j, pf, true) + pair_gw(P, A, 1, 0, j, i, pf, true);
+  o[1] = pair_gw(P, A, 0, 1, i, j, pf, true) + pair_gw(P, A, 1, 1, j, i, pf, true);
+  const Q4 q = task_backward<R, true>(P, tab, Z, t, Q4{w0, w1, 0.0, 0.0}, dT, dE);
+  // production factor p = exp(-(eps_i + eps_j)/T): d/dT = (eps_i + eps_j)/T^2 p
+  dT += (q.a * o[0] + q.b * o[1]) * pf * (P.eps[i] + P.eps[j]) * (Z.invT * Z.invT);
+  o[0] = q.a;
+  o[1] = q.b;
+}
+
+// Task units of one zone, at most: scattering ceil(528/64) + pair 1024/64 at 32 bins.
+constexpr int kMaxUnits = 32;
+
+template <typename R>
+__device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* red, double* smem, int64_t z,
+                              int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
+                              const double* __restrict__ f, const double* __restrict__ g_eta,
+                              const double* __restrict__ g_chi, double* __restrict__ gT_out,
+                              double* __restrict__ gE_out, double* __restrict__ gf_out) {
+  const int ne = P.ne, n2 = ne * ne;
   const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
   const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntp : 0;
-  // Task slots: [4 ntn] scattering comps, then [2 ntp] pair comps (full-size offsets
-  // whatever the process mask). s_uadj holds each task's completion-factor weight until the
-  // lane that owns the task has read it; the same lane then stores the task's kernel values
-  // in that slot (s_qn / s_pa alias s_uadj).
-  double* s_f = smem;
-  double* s_ge = s_f + 6 * ne;
-  double* s_gc = s_ge + 6 * ne;
-  double* s_adj = s_gc + 6 * ne;                    // adjoint weights of task comps
-  double* s_uadj = s_adj + 4 * P.ntn + 2 * P.ntp;   // completion-factor T-derivative weights
-  double* s_qn = s_uadj;
-  double* s_pa = s_uadj + 4 * P.ntn;
-  double* s_d = s_uadj + 4 * P.ntn + 2 * P.ntp;
-  double* s_p = s_d + ne * ne;
-  const double T = Tz[z], eta = etaz[z];
-  const int64_t zo = z * 6 * ne;
-  for (int k = threadIdx.x; k < 6 * ne; k += blockDim.x) {
-    s_f[k] = f[zo + k];
-    s_ge[k] = g_eta[zo + k];
-    s_gc[k] = g_chi[zo + k];
-  }
-  stage_tables(P, tb);
-  stage_factors(P, T, s_d, s_p);
+  // f | g_eta | g_chi [6 ne each] | task values [4 ntn + 2 ntp] (full-size offsets whatever
+  // the process mask) | detailed-balance factors [2 ne^2]
+  const int off_ge = 6 * ne, off_gc = 12 * ne, off_u = 18 * ne, off_d = off_u + 4 * P.ntn + 2 * P.ntp;
+  stage_zone_state(P, z, selm, Tz, etaz, zs);
   __syncthreads();
-  const Adj A{s_f, s_ge, s_gc, ne};
-  // adjoint weights per task component
-  for (int t = threadIdx.x; t < ntn + ntp; t += blockDim.x) {
-    if (t < ntn) {
-      const int ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
-      const double d = s_d[i * ne + j];
-      for (int c = 0; c < 4; ++c) {
-        const int S = c >> 1, l = c & 1;
-        const double up = (i > j) ? d * nes_ghat(P, A, S, l, j, i) : 0.0;
-        s_adj[4 * t + c] = nes_ghat(P, A, S, l, i, j) + up;
-        s_uadj[4 * t + c] = up;
-      }
+  const Zone& Z = *zs;
+  if (!Z.valid) return;   // uniform: every lane reads the same zone state
+  for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) {
+    const int64_t g = Z.z * 6 * ne + r;
+    smem[r] = f[g];
+    smem[off_ge + r] = g_eta[g];
+    smem[off_gc + r] = g_chi[g];
+  }
+  stage_factors(P, Z, smem + off_d);
+  __syncthreads();
+  const Adj A{smem, smem + off_ge, smem + off_gc, ne};
+  const Units U = task_units(ntn, ntp);
+  const int lane = threadIdx.x & 63;
+  // d/dT and d/deta_e: summed per unit in the unit's wave, then over units in unit order, so
+  // the result does not depend on which wave ran which unit
+  for (int u = U.first; u < U.nU; u += U.step) {
+    double dT = 0.0, dE = 0.0;
+    if (u < U.nN) {
+      const int t = (u << 6) + lane;
+      if (t < ntn) nes_task_bwd<R>(P, tab, Z, A, smem + off_d, smem + off_u, t, dT, dE);
     } else {
-      const int p = t - ntn, i = p / ne, j = p % ne;
-      const double pf = s_p[i * ne + j];
-      const double dpf = pf * (P.eps[i] + P.eps[j]) / (T * T);
-      for (int l = 0; l < 2; ++l) {
-        s_adj[4 * P.ntn + 2 * p + l] = pair_gw(P, A, 0, l, i, j, pf, false) + pair_gw(P, A, 1, l, j, i, pf, false);
-        s_uadj[4 * P.ntn + 2 * p + l] = (pair_gw(P, A, 0, l, i, j, pf, true) + pair_gw(P, A, 1, l, j, i, pf, true)) * dpf;
-      }
+      const int t = ((u - U.nN) << 6) + lane;
+      if (t < ntp) pair_task_bwd<R>(P, tab, Z, A, smem + off_d + n2, smem + off_u, t, dT, dE);
+    }
+    dT = wave_sum(dT);
+    dE = wave_sum(dE);
+    if (lane == 0) {
+      red[2 * u] = dT;
+      red[2 * u + 1] = dE;
     }
   }
   __syncthreads();
-  double gT = 0.0, gE = 0.0;
-  if (sizeof(R) == sizeof(float) && eta > P.eta_fp64)
-    items_backward<float, double>(P, tb, T, eta, ntn, ntp, s_adj, s_uadj, s_qn, s_pa, gT, gE);
-  else
-    items_backward<R, R>(P, tb, T, eta, ntn, ntp, s_adj, s_uadj, s_qn, s_pa, gT, gE);
-  const double sT = block_sum(gT, red);
-  const double sE = block_sum(gE, red + 4);
   if (threadIdx.x == 0) {
-    gT_out[z] = sT;
-    gE_out[z] = sE;
+    double sT = 0.0, sE = 0.0;
+    for (int u = 0; u < U.nU; ++u) {
+      sT += red[2 * u];
+      sE += red[2 * u + 1];
+    }
+    gT_out[Z.z] = sT;
+    gE_out[Z.z] = sE;
   }
-  __syncthreads();
-  const int tid = threadIdx.x;
-  if (tid < 3 * ne) {
-    const int sg = tid / ne, j = tid % ne;
+  // g_f: column contractions of the kernels from LDS, one lane per (species, bin)
+  for (int r = threadIdx.x; r < 3 * ne; r += blockDim.x) {
+    const int sg = r / ne, j = r % ne;
+    const double* s_qn = smem + off_u;
+    const double* s_pa = smem + off_u + 4 * P.ntn;
+    const double* s_d = smem + off_d;
+    const double* s_p = s_d + n2;
     const double cw = P.c0w[j];
     double a0 = 0.0, a1 = 0.0;
     if (do_nes) {
@@ -743,16 +1038,59 @@ __global__ __launch_bounds__(kBlock) void rates_backward_kernel(
         a1 += -(ge1 * ka1) * pf + gc1 * ka1 - (gc1 * ka1) * pf;
       }
     }
+    const int64_t zo = Z.z * 6 * ne;
     gf_out[zo + (2 * sg) * ne + j] = a0;
     gf_out[zo + (2 * sg + 1) * ne + j] = a1;
   }
 }
 
-size_t fwd_smem(const DevPlan& P) {
+template <typename R>
+__global__ __launch_bounds__(kBlock) void rates_backward_kernel(
+    DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
+    const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
+    double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out) {
+  __shared__ R tab[kTabLen];
+  __shared__ Zone zs;
+  __shared__ double red[2 * kMaxUnits];
+  extern __shared__ double smem[];
+  stage_tab<R>(P, tab);
+  const int64_t z = blockIdx.x;
+  zone_backward<R>(P, tab, &zs, red, smem, z < nz ? z : -1, selm, Tz, etaz, f, g_eta, g_chi, gT_out, gE_out,
+                   gf_out);
+}
+
+__global__ __launch_bounds__(kBlock) void rates_backward_sparse(
+    DevPlan P, int64_t nz, const double* __restrict__ Tz, const double* __restrict__ etaz,
+    const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
+    double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out) {
+  __shared__ double tab[kTabLen];
+  __shared__ Zone zs;
+  __shared__ double red[2 * kMaxUnits];
+  __shared__ int list[kBlock];
+  __shared__ int count;
+  extern __shared__ double smem[];
+  stage_tab<double>(P, tab);
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nz; base += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    const int64_t z = base + threadIdx.x;
+    if (z < nz && fabs(etaz[z]) > P.eta_fp64) list[atomicAdd(&count, 1)] = (int)threadIdx.x;
+    __syncthreads();
+    const int n = count;
+    for (int c = 0; c < n; ++c) {
+      zone_backward<double>(P, tab, &zs, red, smem, base + list[c], kSelAll, Tz, etaz, f, g_eta, g_chi, gT_out,
+                            gE_out, gf_out);
+      __syncthreads();
+    }
+    __syncthreads();   // every lane has read count before the next window resets it
+  }
+}
+
+size_t zone_lds_fwd(const DevPlan& P) {
   return sizeof(double) * (6 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne);
 }
-size_t bwd_smem(const DevPlan& P) {
-  return sizeof(double) * (18 * P.ne + 2 * (4 * P.ntn + 2 * P.ntp) + 2 * P.ne * P.ne);
+size_t zone_lds_bwd(const DevPlan& P) {
+  return sizeof(double) * (18 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne);
 }
 
 // Dynamic LDS beyond the 64 KiB default must be requested per kernel.
@@ -763,20 +1101,29 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
+// Workgroups of the sparse FP64 pass: enough to scan every zone in a few windows.
+unsigned sparse_grid(int64_t nz) {
+  const int64_t windows = (nz + kBlock - 1) / kBlock;
+  return (unsigned)(windows < 1024 ? windows : 1024);
+}
+
 }  // namespace
 
 hipError_t launch_forward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
                           double* eta, double* chi, hipStream_t s) {
   if (nz <= 0) return hipSuccess;
+  const size_t lds = zone_lds_fwd(P);
   const dim3 grid((unsigned)nz), block(kBlock);
-  const size_t lds = fwd_smem(P);
   hipError_t e;
   if (P.precision == VTX_MIXED) {
     if ((e = allow_lds(rates_forward_kernel<float>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_forward_kernel<float>, grid, block, lds, s, P, T, eta_e, f, eta, chi);
+    hipLaunchKernelGGL(rates_forward_kernel<float>, grid, block, lds, s, P, nz, kSelBulk, T, eta_e, f, eta, chi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = allow_lds(rates_forward_sparse, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_forward_sparse, dim3(sparse_grid(nz)), block, lds, s, P, nz, T, eta_e, f, eta, chi);
   } else {
     if ((e = allow_lds(rates_forward_kernel<double>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_forward_kernel<double>, grid, block, lds, s, P, T, eta_e, f, eta, chi);
+    hipLaunchKernelGGL(rates_forward_kernel<double>, grid, block, lds, s, P, nz, kSelAll, T, eta_e, f, eta, chi);
   }
   return hipGetLastError();
 }
@@ -785,17 +1132,21 @@ hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const 
                            const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
                            hipStream_t s) {
   if (nz <= 0) return hipSuccess;
+  const size_t lds = zone_lds_bwd(P);
   const dim3 grid((unsigned)nz), block(kBlock);
-  const size_t lds = bwd_smem(P);
   hipError_t e;
   if (P.precision == VTX_MIXED) {
     if ((e = allow_lds(rates_backward_kernel<float>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_backward_kernel<float>, grid, block, lds, s, P, T, eta_e, f, g_eta, g_chi, g_T,
-                       g_eta_e, g_f);
+    hipLaunchKernelGGL(rates_backward_kernel<float>, grid, block, lds, s, P, nz, kSelBulk, T, eta_e, f, g_eta, g_chi,
+                       g_T, g_eta_e, g_f);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = allow_lds(rates_backward_sparse, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_backward_sparse, dim3(sparse_grid(nz)), block, lds, s, P, nz, T, eta_e, f, g_eta, g_chi,
+                       g_T, g_eta_e, g_f);
   } else {
     if ((e = allow_lds(rates_backward_kernel<double>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_backward_kernel<double>, grid, block, lds, s, P, T, eta_e, f, g_eta, g_chi, g_T,
-                       g_eta_e, g_f);
+    hipLaunchKernelGGL(rates_backward_kernel<double>, grid, block, lds, s, P, nz, kSelAll, T, eta_e, f, g_eta, g_chi,
+                       g_T, g_eta_e, g_f);
   }
   return hipGetLastError();
 }

@@ -97,7 +97,7 @@ class GridHandle:
 
 
 def make_opts(precision="fp64", nquad=48, rule="panel", processes=VTX_NES | VTX_PAIR, sin2w=0.2312,
-              eta_fp64=30.0):
+              eta_fp64=64.0):
     o = Opts()
     library().vtx_opts_default(ctypes.byref(o))
     o.precision = {"fp64": VTX_FP64, "mixed": VTX_MIXED}[precision] if isinstance(precision, str) else precision
@@ -183,11 +183,11 @@ def eval_hpoly(process: int, comp: int, e: float, ep: float, E):
 
 
 def task_coefficients(process: int, e: float, ep: float):
-    """Host copy of one task's coefficient table (48 doubles, layout in include/vtx_rates.h)."""
-    out = np.zeros(48)
+    """Host copy of one task's coefficient table (32 / 26 doubles, layout in include/vtx_rates.h)."""
+    out = np.zeros(32)
     _check(library().vtx_task_coefficients(process, e, ep, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
            "vtx_task_coefficients")
-    return out
+    return out if process == VTX_NES else out[:26]
 
 
 def _make_function():

@@ -41,7 +41,7 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-def gpu_forward(inp, precision, nquad, rule, processes=3, eta_fp64=30.0):
+def gpu_forward(inp, precision, nquad, rule, processes=3, eta_fp64=64.0):
     grid = vtx.GridHandle(inp.eps, inp.w)
     opts = vtx.make_opts(precision, nquad, rule, processes, eta_fp64=eta_fp64)
     T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
@@ -176,9 +176,9 @@ def test_deterministic_and_batch_independent():
 
 # ---------------------------------------------------------------------------- backward
 
-def gpu_backward(inp, ge, gc, precision, nquad, rule):
+def gpu_backward(inp, ge, gc, precision, nquad, rule, eta_fp64=64.0):
     grid = vtx.GridHandle(inp.eps, inp.w)
-    opts = vtx.make_opts(precision, nquad, rule)
+    opts = vtx.make_opts(precision, nquad, rule, eta_fp64=eta_fp64)
     out = vtx.backward(grid, opts, to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f), to_dev(ge), to_dev(gc))
     torch.cuda.synchronize()
     return [t.cpu().numpy() for t in out]
@@ -247,7 +247,7 @@ def test_autograd_function():
 
 
 def test_backward_largest_grid():
-    """32 bins: the backward kernel's LDS exceeds 64 KiB and is requested explicitly."""
+    """32 bins, the largest grid: 25 task units per zone over the four waves."""
     eps, w = synth.energy_grid(32, 1.0, 400.0)
     T, eta_e, f = synth.draw_zones(2, 32, eps, (2, 30), (0, 20), (-2, 10), 0.05, 79)
     inp = synth.ZoneInputs(eps, w, T, eta_e, f)
@@ -256,3 +256,40 @@ def test_backward_largest_grid():
     gT, gE, gf = gpu_backward(inp, ge, gc, "fp64", 32, "panel")
     rT, rE, rf = ograd.vjp(eps, w, T, eta_e, f, ge, gc, orates.Options(nquad=32, rule="panel"))
     assert max(grad_err(gT, rT).max(), grad_err(gE, rE).max(), grad_err(gf, rf).max()) <= FP64_TOL
+
+
+def test_mixed_fp64_pass():
+    """Mixed precision sends zones with |eta_e| above the threshold to a second, FP64 pass:
+    those zones match the FP64 path bit for bit (forward and backward), the rest stay within
+    the mixed bars."""
+    inp = synth.make_inputs("medium", nzones=24)
+    inp.eta_e[:6] = [-30.0, -12.0, 25.0, 39.0, 16.0, -16.0]
+    thr = 15.0
+    big = np.abs(inp.eta_e) > thr
+    assert big.sum() >= 6 and (~big).sum() >= 6
+    say(f"[gpu] mixed with FP64 pass: {int(big.sum())} of {big.size} zones above |eta_e| = {thr}")
+    e64, c64 = gpu_forward(inp, "fp64", 48, "panel")
+    em, cm = gpu_forward(inp, "mixed", 48, "panel", eta_fp64=thr)
+    assert np.array_equal(em[big], e64[big]) and np.array_equal(cm[big], c64[big])
+    re, rc, ae, ac = oracle_forward(inp, 48, "panel")
+    small = ~big
+    err = max(rel_err(em[small], re[small], ae[small]).max(), rel_err(cm[small], rc[small], ac[small]).max())
+    say(f"    FP32-pass zones: max rel err {err:.2e}")
+    assert err <= MIXED_TOL
+    ge, gc = synth.random_gradients(inp.T.shape[0], inp.eps.shape[0], 8)
+    g64 = gpu_backward(inp, ge, gc, "fp64", 48, "panel")
+    gm = gpu_backward(inp, ge, gc, "mixed", 48, "panel", eta_fp64=thr)
+    for a, b in zip(gm, g64):
+        assert np.array_equal(a[big], b[big])
+        assert grad_err(a[small], b[small]).max() <= 1e-3
+
+
+def test_backward_batch_independent():
+    """A zone's gradients do not depend on the other zones of the launch (bit for bit)."""
+    inp = synth.make_inputs("medium", nzones=9)
+    ge, gc = synth.random_gradients(9, inp.eps.shape[0], 10)
+    for prec in ("fp64", "mixed"):
+        full = gpu_backward(inp, ge, gc, prec, 48, "panel")
+        one = gpu_backward(synth.subset(inp, [5]), ge[5:6], gc[5:6], prec, 48, "panel")
+        for a, b in zip(full, one):
+            assert np.array_equal(a[5:6], b)
