@@ -27,9 +27,10 @@ namespace {
 constexpr double kLog2e = 1.4426950408889634;
 constexpr int kM4 = kMaxNquad / 4;
 // Node table in LDS (entries of the bulk type): Gauss-Legendre x | 1 - x | w on [0, 1], then
-// Gauss-Laguerre x | w e^x. A map reads its node coordinate through a per-lane offset.
+// Gauss-Laguerre x | w e^x | 1. A map reads its node coordinate through a per-lane offset.
 constexpr int kOffX = 0, kOffY = kM4, kOffW = 2 * kM4, kOffGX = 3 * kM4, kOffGW = 3 * kM4 + kMaxNquad;
-constexpr int kTabLen = 3 * kM4 + 2 * kMaxNquad;
+constexpr int kOffOne = 3 * kM4 + 2 * kMaxNquad;
+constexpr int kTabLen = 3 * kM4 + 3 * kMaxNquad;
 
 // Workgroup size: four waves. The task units of a zone spread over them, and they cover the
 // per-zone contraction's 3 ne lanes up to 32 bins.
@@ -88,6 +89,7 @@ struct Zone {
   double T, eta, invT, mu;
   int64_t z;   // zone index, or -1 for an empty slot
   int valid;
+  int k;       // #{eps_j < mu_e}: selects the task order
 };
 
 template <typename R> __device__ void stage_tab(const DevPlan& P, R* tab);
@@ -102,6 +104,7 @@ template <> __device__ void stage_tab<double>(const DevPlan& P, double* tab) {
     const double4 n = P.lag64[k];
     tab[kOffGX + k] = n.x;
     tab[kOffGW + k] = n.z;
+    tab[kOffOne + k] = 1.0;
   }
 }
 template <> __device__ void stage_tab<float>(const DevPlan& P, float* tab) {
@@ -115,6 +118,7 @@ template <> __device__ void stage_tab<float>(const DevPlan& P, float* tab) {
     const float4 n = P.lag32[k];
     tab[kOffGX + k] = n.x;
     tab[kOffGW + k] = n.z;
+    tab[kOffOne + k] = 1.0f;
   }
 }
 
@@ -196,11 +200,28 @@ __device__ __forceinline__ void pair_breakpoints(double mn, double mx, double w,
   b3 = {below_M ? mx : cv, below_M ? 0.0 : cT, below_M ? 0.0 : cE};
 }
 
-// Group g of a task. Scattering panels lie wholly below or wholly above eps_j (eps_j is a
-// breakpoint whenever a panel could cross it), so only the tail can straddle u = 1. Each
-// pair group lies in one piece: [0, m] (A), [m, M] (B), [M, w] (C).
+// The task's interior breakpoints, sorted (scattering: s1 <= s2 <= s3; pair: b1 <= b2 <= b3).
+struct Brk {
+  Tri b1, b2, b3;
+};
 template <bool PAIR>
-__device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, const Zone& Z, int g) {
+__device__ __forceinline__ Brk task_breakpoints(const Task& K, const Zone& Z) {
+  Brk B;
+  if (!PAIR) {
+    nes_breakpoints(K.ep, K.D, Z, B.b1, B.b2, B.b3);
+  } else {
+    const bool le = K.e <= K.ep;
+    pair_breakpoints(le ? K.e : K.ep, le ? K.ep : K.e, K.D, Z, B.b1, B.b2, B.b3);
+  }
+  return B;
+}
+
+// Group g of a task (g is a constant once the group loop is unrolled). Scattering panels lie
+// wholly below or wholly above eps_j (eps_j is a breakpoint whenever a panel could cross it),
+// so only the tail can straddle u = 1. Each pair group lies in one piece: [0, m] (A),
+// [m, M] (B), [M, w] (C).
+template <bool PAIR>
+__device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, const Brk& Bk, int g) {
   GroupDesc G;
   const Tri zero = {0.0, 0.0, 0.0};
   G.w = 0.0;
@@ -216,8 +237,7 @@ __device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, c
       G.toff = g * P.m4;
       G.mode = kGen;
     } else {
-      Tri s1, s2, s3;
-      nes_breakpoints(K.ep, K.D, Z, s1, s2, s3);
+      const Tri &s1 = Bk.b1, &s2 = Bk.b2, &s3 = Bk.b3;
       G.lo = pick4(g, zero, s1, s2, s3);
       G.hi = pick4(g, s1, s2, s3, s3);
       G.lag = (g == 3);
@@ -227,8 +247,7 @@ __device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, c
   } else {
     const bool le = K.e <= K.ep;
     const double mn = le ? K.e : K.ep, mx = le ? K.ep : K.e, w = K.D;
-    Tri b1, b2, b3;
-    pair_breakpoints(mn, mx, w, Z, b1, b2, b3);
+    const Tri &b1 = Bk.b1, &b2 = Bk.b2, &b3 = Bk.b3;
     const Tri b4 = {w, 0.0, 0.0};
     G.lo = pick4(g, zero, b1, b2, b3);
     G.hi = pick4(g, b1, b2, b3, b4);
@@ -236,7 +255,9 @@ __device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, c
     G.toff = 0;
     const double mid = 0.5 * (G.lo.v + G.hi.v);
     const double imn = P.inv_eps[le ? K.i : K.j], imx = P.inv_eps[le ? K.j : K.i];
-    G.piece = (mid <= mn) ? 0 : ((mid <= mx) ? 1 : 2);
+    // a zero-width group at m (diagonal tasks, or mu_e on a bin) counts as B like its
+    // neighbours in the task order; it contributes nothing, and H is continuous at m
+    G.piece = (mid < mn) ? 0 : ((mid <= mx) ? 1 : 2);
     G.ub = (G.piece == 1) ? imx : imn;
     G.c = (G.piece == 2);
     G.w = w;
@@ -263,6 +284,7 @@ template <typename R>
 struct Loop {
   R u0, u1, a0, a1, b0, b1, split;
   int ou, o1, o2, ow;
+  int oa, ob;   // backward: weights of the group's two end points, 1 - x and x (tail: 1 and x)
 };
 
 // Returns the group's weight scale Es (nodes weigh Es w_k).
@@ -281,6 +303,8 @@ __device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, c
     L.b1 = R(K.sg * zs);
     L.ou = L.o1 = L.o2 = kOffGX + G.toff;
     L.ow = kOffGW + G.toff;
+    L.oa = kOffOne + G.toff;
+    L.ob = kOffGX + G.toff;
   } else {
     Es = G.hi.v - G.lo.v;
     const EndV B = end_values(K, G, Z, G.hi.v);
@@ -295,6 +319,8 @@ __device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, c
     L.o1 = r1 ? kOffY : kOffX;
     L.o2 = r2 ? kOffY : kOffX;
     L.ow = kOffW;
+    L.oa = kOffY;
+    L.ob = kOffX;
   }
   L.split = G.mode == kLow ? R(INFINITY) : (G.mode == kHigh ? R(-INFINITY) : R(1));
   return Es;
@@ -436,9 +462,11 @@ __device__ __forceinline__ Q4 contract_task(const DevPlan& P, int t, const Slots
 template <typename R, bool PAIR>
 __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const Zone& Z, int t) {
   const Task K = make_task<PAIR>(P, t);
+  const Brk Bk = task_breakpoints<PAIR>(K, Z);
   Slots<R> S = {};
+#pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const GroupDesc G = describe<PAIR>(P, K, Z, g);
+    const GroupDesc G = describe<PAIR>(P, K, Bk, g);
     Loop<R> L;
     const double Es = make_loop<R>(K, G, Z, L);
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0};
@@ -451,7 +479,8 @@ __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const
 // ----------------------------------------------------------------------------------------
 // Workgroup layout: one zone per workgroup; in LDS (doubles): f [6 ne] | scattering task
 // values [4 ntn] | pair task values [2 ntp] | exp(-|eps_i - eps_j|/T) [ne^2] |
-// exp(-(eps_i + eps_j)/T) [ne^2]; the backward also holds g_eta, g_chi [12 ne] after f.
+// exp(-(eps_i + eps_j)/T) [ne^2] | contraction parts; the backward also holds g_eta, g_chi
+// [12 ne] after f.
 
 // Zone selection of a pass: every zone, or the zones the FP32 pass takes (|eta_e| not above
 // the threshold, which includes values that do not compare).
@@ -468,6 +497,8 @@ __device__ void stage_zone_state(const DevPlan& P, int64_t z, int selm, const do
     if (selm == kSelBulk && fabs(Z.eta) > P.eta_fp64) Z.valid = 0;
     Z.invT = 1.0 / Z.T;
     Z.mu = Z.eta * Z.T;
+    Z.k = 0;
+    for (int j = 0; j < P.ne; ++j) Z.k += P.eps[j] < Z.mu;
     *zs = Z;
   }
 }
@@ -483,7 +514,8 @@ __device__ void stage_factors(const DevPlan& P, const Zone& Z, double* s_d) {
   }
 }
 
-// Task units: units 0 .. nN-1 hold 64 scattering tasks each, the rest 64 pair tasks. Wave w
+// Task units: units 0 .. nN-1 hold 64 scattering tasks each, the rest 64 pair tasks, in the
+// zone's task order (tasks whose groups take the same node-loop variants sit together). Wave w
 // of workgroup b takes units (w + b) mod W, + W, ...; the rotation spreads the wave that
 // holds one unit fewer over the SIMDs.
 struct Units {
@@ -496,6 +528,13 @@ __device__ __forceinline__ Units task_units(int ntn, int ntp) {
   U.step = blockDim.x >> 6;
   U.first = __builtin_amdgcn_readfirstlane((int)(((threadIdx.x >> 6) + blockIdx.x) % U.step));
   return U;
+}
+
+// Parts of the per-zone contractions: as many as the workgroup holds copies of the 3 ne
+// (species, bin) outputs, at most four.
+__device__ __forceinline__ int contraction_parts(int ne) {
+  const int np = (int)blockDim.x / (3 * ne);
+  return np < 1 ? 1 : (np > 4 ? 4 : np);
 }
 
 template <typename R>
@@ -515,10 +554,13 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   stage_factors(P, Z, smem + off_d);
   const Units U = task_units(ntn, ntp);
   const int lane = threadIdx.x & 63;
+  const uint16_t* nes_order = P.nes_order + Z.k * P.ntn;
+  const uint16_t* pair_order = P.pair_order + Z.k * P.ntp;
   for (int u = U.first; u < U.nU; u += U.step) {
     if (u < U.nN) {
-      const int t = (u << 6) + lane;
-      if (t < ntn) {
+      const int pos = (u << 6) + lane;
+      if (pos < ntn) {
+        const int t = nes_order[pos];
         const Q4 q = task_forward<R, false>(P, tab, Z, t);
         double* o = smem + off_q + 4 * t;
         o[0] = q.a;
@@ -527,8 +569,9 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
         o[3] = q.d;
       }
     } else {
-      const int t = ((u - U.nN) << 6) + lane;
-      if (t < ntp) {
+      const int pos = ((u - U.nN) << 6) + lane;
+      if (pos < ntp) {
+        const int t = pair_order[pos];
         const Q4 q = task_forward<R, true>(P, tab, Z, t);
         double* o = smem + off_p + 2 * t;
         o[0] = q.a;
@@ -537,9 +580,13 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
     }
   }
   __syncthreads();
-  // completion, species combination and contraction: one lane per (species, bin)
-  for (int r = threadIdx.x; r < 3 * ne; r += blockDim.x) {
-    const int s = r / ne, i = r % ne, sb = partner(s);
+  // completion, species combination and contraction: one lane per (part, species, bin); the
+  // sum over j is split into parts over the four waves and the parts are added in order
+  const int nout = 3 * ne, np = contraction_parts(ne);
+  double* s_part = smem + off_d + 2 * n2;
+  for (int r = threadIdx.x; r < np * nout; r += blockDim.x) {
+    const int part = r / nout, o = r - part * nout, s = o / ne, i = o % ne, sb = partner(s);
+    const int j0 = part * ne / np, j1 = (part + 1) * ne / np;
     const double* s_f = smem;
     const double* s_qn = smem + off_q;
     const double* s_pa = smem + off_p;
@@ -547,7 +594,7 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
     const double* s_p = s_d + n2;
     const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
     double e0 = 0.0, c0 = 0.0, e1 = 0.0, c1 = 0.0;
-    for (int j = 0; j < ne; ++j) {
+    for (int j = j0; j < j1; ++j) {
       const double cw = P.c0w[j];
       const double dfac = s_d[i * ne + j];
       if (do_nes) {
@@ -577,17 +624,36 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
         c1 += t1 - t1 * pf;
       }
     }
-    const int64_t o = Z.z * 6 * ne + (2 * s) * ne + i;
-    eta_out[o] = e0;
-    chi_out[o] = c0;
-    eta_out[o + ne] = e1;
-    chi_out[o + ne] = c1;
+    double* pp = s_part + 4 * r;
+    pp[0] = e0;
+    pp[1] = c0;
+    pp[2] = e1;
+    pp[3] = c1;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+    const int s = o / ne, i = o % ne;
+    double e0 = 0.0, c0 = 0.0, e1 = 0.0, c1 = 0.0;
+    for (int part = 0; part < np; ++part) {
+      const double* pp = s_part + 4 * (part * nout + o);
+      e0 += pp[0];
+      c0 += pp[1];
+      e1 += pp[2];
+      c1 += pp[3];
+    }
+    const int64_t out = Z.z * 6 * ne + (2 * s) * ne + i;
+    eta_out[out] = e0;
+    chi_out[out] = c0;
+    eta_out[out + ne] = e1;
+    chi_out[out + ne] = c1;
   }
 }
 
-// Dense pass: workgroup b takes zone b (if selected).
+// Dense pass: workgroup b takes zone b (if selected). Occupancy targets: four waves per SIMD
+// for FP32 (at most 128 VGPRs), three for FP64.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void rates_forward_kernel(DevPlan P, int64_t nz, int selm,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 3)))
+void rates_forward_kernel(DevPlan P, int64_t nz, int selm,
                                                                   const double* __restrict__ Tz,
                                                                   const double* __restrict__ etaz,
                                                                   const double* __restrict__ f,
@@ -636,14 +702,14 @@ __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_
 // same node loop, the derivative of the adjoint-weighted kernel sum_c A_c q_c along T and
 // eta_e, node motion included. A_c are the upstream weights of each task component.
 //
-// With the node maps value = c0 + c1 x for the three maps m (x the node coordinate the map
-// reads) and the group weight Es w_k, the derivative of Es sum_k w_k B_k H(u_k) along
-// theta is
-//   dEs/dtheta sum w B H + Es sum_m [dc0_m/dtheta S_m + dc1_m/dtheta S_mx],
-// S_z = sum w B H r_z, S_zx = sum w B H r_z x (r_z = d log sigma / dz = 1 - sigma(z)) for
-// the two Fermi-Dirac arguments and S_u = sum w B dH/du, S_ux = sum w B dH/du x. The node
-// loop accumulates these sums; the group end applies the FP64 derivatives of the anchored
-// map coefficients, which depend only on the group's end points.
+// Each of the three maps m is affine along a group, m = m_A (1 - x) + m_B x on a panel (x the
+// Legendre node on [0, 1]) or m_A + s_m x on the tail, so with the group weight Es w_k the
+// derivative of Es sum_k w_k B_k H(u_k) along theta is
+//   dEs/dtheta sum w B H + Es sum_m [dm_A/dtheta S_mA + dm_B/dtheta S_mB],
+// S_zA = sum w B H r_z (1 - x), S_zB = sum w B H r_z x (r_z = d log sigma / dz = 1 - sigma(z))
+// for the two Fermi-Dirac arguments and S_uA, S_uB likewise with w B dH/du (tail: weights 1
+// and x, dm_B the slope's derivative). The node loop accumulates these sums; the group end
+// applies the FP64 derivatives of the end points' map values.
 
 struct Adj {
   const double* f;
@@ -716,8 +782,8 @@ __device__ __forceinline__ void make_adj_poly(const double lo[5], const double h
 }
 
 template <typename R, int MODE>
-__device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, R xu, R x1, R x2, R w, R M[5],
-                                         R H[3], R S[7]) {
+__device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, R xu, R x1, R x2, R w, R pa, R pb,
+                                         R M[5], R H[3], R S[7]) {
   using N = Num<R>;
   const R u = N::fma(L.u1, xu, L.u0);
   const R z1 = N::fma(L.a1, x1, L.a0), z2 = N::fma(L.b1, x2, L.b0);
@@ -762,12 +828,12 @@ __device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, 
   }
   S[0] = S[0] + x0;
   const R y1 = x0 * r1, y2 = x0 * r2;
-  S[1] = S[1] + y1;
-  S[2] = N::fma(y1, x1, S[2]);
-  S[3] = S[3] + y2;
-  S[4] = N::fma(y2, x2, S[4]);
-  S[5] = S[5] + yu;
-  S[6] = N::fma(yu, xu, S[6]);
+  S[1] = N::fma(y1, pa, S[1]);
+  S[2] = N::fma(y1, pb, S[2]);
+  S[3] = N::fma(y2, pa, S[3]);
+  S[4] = N::fma(y2, pb, S[4]);
+  S[5] = N::fma(yu, pa, S[5]);
+  S[6] = N::fma(yu, pb, S[6]);
 }
 
 template <typename R, int MODE>
@@ -775,7 +841,8 @@ __device__ __forceinline__ void nodes_bwd(const Loop<R>& L, const AdjPoly<R>& Q,
                                           R H[3], R S[7]) {
 #pragma unroll 2
   for (int k = 0; k < m; ++k)
-    node_bwd<R, MODE>(L, Q, tab[L.ou + k], tab[L.o1 + k], tab[L.o2 + k], tab[L.ow + k], M, H, S);
+    node_bwd<R, MODE>(L, Q, tab[L.ou + k], tab[L.o1 + k], tab[L.o2 + k], tab[L.ow + k], tab[L.oa + k],
+                      tab[L.ob + k], M, H, S);
 }
 
 template <typename R>
@@ -805,48 +872,28 @@ __device__ __forceinline__ EndD end_derivs(const Task& K, const GroupDesc& G, co
 }
 
 // Group end of the backward: adds the group's d/dT and d/deta_e of the adjoint-weighted
-// kernel. The anchoring choices repeat those of make_loop (same inputs, same decisions).
+// kernel. Along the group a map is A (1 - x) + B x (panel) or A + slope x (tail), so its
+// derivative at a node is dA (1 - x) + dB x (or dA + dslope x), and the node sums weighted by
+// those two end weights turn into the derivative with the end points' derivatives alone.
 template <typename R>
 __device__ __forceinline__ void group_grad(const Task& K, const GroupDesc& G, const Zone& Z, double Es, const R S[7],
                                            double& gT, double& gE) {
-  const EndV A = end_values(K, G, Z, G.lo.v);
-  const EndD dA = end_derivs(K, G, Z, G.lo, A);
-  double u0T, u0E, u1T, u1E, a0T, a0E, a1T, a1E, b0T, b0E, b1T, b1E, EsT, EsE;
+  const EndD dA = end_derivs(K, G, Z, G.lo, end_values(K, G, Z, G.lo.v));
+  EndD dB;
+  double EsT, EsE;
   if (G.lag) {
-    u0T = dA.uT;
-    u0E = dA.uE;
-    u1T = G.c ? -G.ub : G.ub;
-    u1E = 0.0;
-    a0T = dA.z1T;
-    a0E = dA.z1E;
-    b0T = dA.z2T;
-    b0E = dA.z2E;
-    a1T = a1E = b1T = b1E = 0.0;
+    dB = {G.c ? -G.ub : G.ub, 0.0, 0.0, 0.0, 0.0, 0.0};   // slopes: u's is ub T, the arguments' are constants
     EsT = 1.0;
     EsE = 0.0;
   } else {
-    const EndV B = end_values(K, G, Z, G.hi.v);
-    const EndD dB = end_derivs(K, G, Z, G.hi, B);
-    const bool ru = fabs(A.u) > fabs(B.u), r1 = fabs(A.z1) > fabs(B.z1), r2 = fabs(A.z2) > fabs(B.z2);
-    u0T = ru ? dB.uT : dA.uT;
-    u0E = ru ? dB.uE : dA.uE;
-    u1T = ru ? dA.uT - dB.uT : dB.uT - dA.uT;
-    u1E = ru ? dA.uE - dB.uE : dB.uE - dA.uE;
-    a0T = r1 ? dB.z1T : dA.z1T;
-    a0E = r1 ? dB.z1E : dA.z1E;
-    a1T = r1 ? dA.z1T - dB.z1T : dB.z1T - dA.z1T;
-    a1E = r1 ? dA.z1E - dB.z1E : dB.z1E - dA.z1E;
-    b0T = r2 ? dB.z2T : dA.z2T;
-    b0E = r2 ? dB.z2E : dA.z2E;
-    b1T = r2 ? dA.z2T - dB.z2T : dB.z2T - dA.z2T;
-    b1E = r2 ? dA.z2E - dB.z2E : dB.z2E - dA.z2E;
+    dB = end_derivs(K, G, Z, G.hi, end_values(K, G, Z, G.hi.v));
     EsT = G.hi.dT - G.lo.dT;
     EsE = G.hi.dE - G.lo.dE;
   }
   const double s0 = double(S[0]), s1 = double(S[1]), s2 = double(S[2]), s3 = double(S[3]), s4 = double(S[4]),
                s5 = double(S[5]), s6 = double(S[6]);
-  gT += Es * (u0T * s5 + u1T * s6 + a0T * s1 + a1T * s2 + b0T * s3 + b1T * s4) + EsT * s0;
-  gE += Es * (u0E * s5 + u1E * s6 + a0E * s1 + a1E * s2 + b0E * s3 + b1E * s4) + EsE * s0;
+  gT += Es * (dA.uT * s5 + dB.uT * s6 + dA.z1T * s1 + dB.z1T * s2 + dA.z2T * s3 + dB.z2T * s4) + EsT * s0;
+  gE += Es * (dA.uE * s5 + dB.uE * s6 + dA.z1E * s1 + dB.z1E * s2 + dA.z2E * s3 + dB.z2E * s4) + EsE * s0;
 }
 
 // Recompute one task with derivatives. adj: upstream weights of the task components
@@ -855,6 +902,7 @@ template <typename R, bool PAIR>
 __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, const Zone& Z, int t, const Q4& adj,
                                             double& gT, double& gE) {
   const Task K = make_task<PAIR>(P, t);
+  const Brk Bk = task_breakpoints<PAIR>(K, Z);
   Slots<R> Sl = {};
   AdjPoly<R> Q;
   if (!PAIR) {
@@ -868,8 +916,10 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
       hi[k] = adj.a * C.hi[0][k] + adj.b * C.hi[1][k] + adj.c * C.hi[2][k] + adj.d * C.hi[3][k];
     make_adj_poly<R>(lo, hi, Q);
   }
+  // kept rolled: unrolled, the four groups' live state exceeds the register budget
+#pragma unroll 1
   for (int g = 0; g < 4; ++g) {
-    const GroupDesc G = describe<PAIR>(P, K, Z, g);
+    const GroupDesc G = describe<PAIR>(P, K, Bk, g);
     Loop<R> L;
     const double Es = make_loop<R>(K, G, Z, L);
     if (PAIR) {
@@ -975,14 +1025,16 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
   const int lane = threadIdx.x & 63;
   // d/dT and d/deta_e: summed per unit in the unit's wave, then over units in unit order, so
   // the result does not depend on which wave ran which unit
+  const uint16_t* nes_order = P.nes_order + Z.k * P.ntn;
+  const uint16_t* pair_order = P.pair_order + Z.k * P.ntp;
   for (int u = U.first; u < U.nU; u += U.step) {
     double dT = 0.0, dE = 0.0;
     if (u < U.nN) {
-      const int t = (u << 6) + lane;
-      if (t < ntn) nes_task_bwd<R>(P, tab, Z, A, smem + off_d, smem + off_u, t, dT, dE);
+      const int pos = (u << 6) + lane;
+      if (pos < ntn) nes_task_bwd<R>(P, tab, Z, A, smem + off_d, smem + off_u, nes_order[pos], dT, dE);
     } else {
-      const int t = ((u - U.nN) << 6) + lane;
-      if (t < ntp) pair_task_bwd<R>(P, tab, Z, A, smem + off_d + n2, smem + off_u, t, dT, dE);
+      const int pos = ((u - U.nN) << 6) + lane;
+      if (pos < ntp) pair_task_bwd<R>(P, tab, Z, A, smem + off_d + n2, smem + off_u, pair_order[pos], dT, dE);
     }
     dT = wave_sum(dT);
     dE = wave_sum(dE);
@@ -1001,9 +1053,13 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
     gT_out[Z.z] = sT;
     gE_out[Z.z] = sE;
   }
-  // g_f: column contractions of the kernels from LDS, one lane per (species, bin)
-  for (int r = threadIdx.x; r < 3 * ne; r += blockDim.x) {
-    const int sg = r / ne, j = r % ne;
+  // g_f: column contractions of the kernels from LDS, one lane per (part, species, bin); the
+  // sum over i is split into parts and the parts are added in order
+  const int nout = 3 * ne, np = contraction_parts(ne);
+  double* s_part = smem + off_d + 2 * n2;
+  for (int r = threadIdx.x; r < np * nout; r += blockDim.x) {
+    const int part = r / nout, o = r - part * nout, sg = o / ne, j = o % ne;
+    const int i0 = part * ne / np, i1 = (part + 1) * ne / np;
     const double* s_qn = smem + off_u;
     const double* s_pa = smem + off_u + 4 * P.ntn;
     const double* s_d = smem + off_d;
@@ -1012,7 +1068,7 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
     double a0 = 0.0, a1 = 0.0;
     if (do_nes) {
       const double bI = beta_of(P, sg, 0), bII = beta_of(P, sg, 1);
-      for (int i = 0; i < ne; ++i) {
+      for (int i = i0; i < i1; ++i) {
         const double* q = s_qn + 4 * (i >= j ? tri(i, j) : tri(j, i));
         const double k0 = bI * q[0] + bII * q[2], k1 = bI * q[1] + bII * q[3];
         const double dfac = s_d[i * ne + j];
@@ -1026,7 +1082,7 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
     if (do_pair) {
       const int s = partner(sg);
       const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
-      for (int i = 0; i < ne; ++i) {
+      for (int i = i0; i < i1; ++i) {
         const double* aij = s_pa + 2 * (i * ne + j);
         const double* aji = s_pa + 2 * (j * ne + i);
         const double ka0 = bI * aij[0] + bII * aji[0];
@@ -1038,14 +1094,28 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
         a1 += -(ge1 * ka1) * pf + gc1 * ka1 - (gc1 * ka1) * pf;
       }
     }
+    s_part[2 * r] = a0;
+    s_part[2 * r + 1] = a1;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+    const int sg = o / ne, j = o % ne;
+    double a0 = 0.0, a1 = 0.0;
+    for (int part = 0; part < np; ++part) {
+      a0 += s_part[2 * (part * nout + o)];
+      a1 += s_part[2 * (part * nout + o) + 1];
+    }
     const int64_t zo = Z.z * 6 * ne;
     gf_out[zo + (2 * sg) * ne + j] = a0;
     gf_out[zo + (2 * sg + 1) * ne + j] = a1;
   }
 }
 
+// Occupancy targets: three waves per SIMD for the FP32 backward (at most 168 VGPRs), two
+// for the FP64 one.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void rates_backward_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
+void rates_backward_kernel(
     DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
     const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
     double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out) {
@@ -1086,11 +1156,13 @@ __global__ __launch_bounds__(kBlock) void rates_backward_sparse(
   }
 }
 
+// Per-zone LDS: the layouts above plus the contraction parts (4 x 3 ne x 4 doubles forward,
+// 4 x 3 ne x 2 backward).
 size_t zone_lds_fwd(const DevPlan& P) {
-  return sizeof(double) * (6 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne);
+  return sizeof(double) * (6 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne + 48 * P.ne);
 }
 size_t zone_lds_bwd(const DevPlan& P) {
-  return sizeof(double) * (18 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne);
+  return sizeof(double) * (18 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne + 24 * P.ne);
 }
 
 // Dynamic LDS beyond the 64 KiB default must be requested per kernel.
