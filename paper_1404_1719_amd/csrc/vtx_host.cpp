@@ -246,19 +246,19 @@ void couplings(double s2w, double beta[3][2]) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Task orders for each k = #{eps_j < mu_e} (0..ne). Where mu_e falls among the bins decides
-// which side of eps_j each quadrature group of a task lies on, hence its node-loop variant:
-// scattering (i >= j): eps_i < mu (i < k); eps_j < mu <= eps_i (j < k <= i); mu <= eps_j
-// (k <= j), the last ordered by column so that the tail's split at mu+ + 10 T stays
-// contiguous. Pair: both bins below mu, one on each side, both above. Each class is a
-// contiguous run, so the waves that run the tasks see few mixed-variant groups.
-void task_orders(int ne, std::vector<uint16_t>& nes, std::vector<uint16_t>& pair) {
-  const int ntn = ne * (ne + 1) / 2, ntp = ne * ne;
-  nes.assign(size_t(ne + 1) * ntn, 0);
-  pair.assign(size_t(ne + 1) * ntp, 0);
+// Task order for each k = #{eps_j < mu_e} (0..ne), over the tasks (i >= j). Where mu_e falls
+// among the bins decides which side of the bins each quadrature group of a task lies on,
+// hence its node-loop variant, the same way for scattering task (i, j) and pair tasks
+// {(i, j), (j, i)}: eps_i < mu (i < k); eps_j < mu <= eps_i (j < k <= i); mu <= eps_j (k <= j),
+// the last ordered by column so that the scattering tail's split at mu+ + 10 T stays
+// contiguous. Each class is a contiguous run, so the waves that run the tasks see few
+// mixed-variant groups.
+void task_order(int ne, std::vector<uint16_t>& order) {
+  const int ntn = ne * (ne + 1) / 2;
+  order.assign(size_t(ne + 1) * ntn, 0);
   auto tri = [](int i, int j) { return i * (i + 1) / 2 + j; };
   for (int k = 0; k <= ne; ++k) {
-    uint16_t* o = nes.data() + size_t(k) * ntn;
+    uint16_t* o = order.data() + size_t(k) * ntn;
     int n = 0;
     for (int i = 0; i < k; ++i)
       for (int j = 0; j <= i; ++j) o[n++] = (uint16_t)tri(i, j);
@@ -266,15 +266,6 @@ void task_orders(int ne, std::vector<uint16_t>& nes, std::vector<uint16_t>& pair
       for (int j = 0; j < k; ++j) o[n++] = (uint16_t)tri(i, j);
     for (int j = k; j < ne; ++j)
       for (int i = j; i < ne; ++i) o[n++] = (uint16_t)tri(i, j);
-    uint16_t* q = pair.data() + size_t(k) * ntp;
-    int m = 0;
-    for (int i = 0; i < k; ++i)
-      for (int j = 0; j < k; ++j) q[m++] = (uint16_t)(i * ne + j);
-    for (int i = 0; i < ne; ++i)
-      for (int j = 0; j < ne; ++j)
-        if ((i < k) != (j < k)) q[m++] = (uint16_t)(i * ne + j);
-    for (int i = k; i < ne; ++i)
-      for (int j = k; j < ne; ++j) q[m++] = (uint16_t)(i * ne + j);
   }
 }
 
@@ -332,10 +323,9 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   const size_t o_pc = place(sizeof(PairCoef) * ntp);
   const size_t o_l64 = place(sizeof(double4) * m4), o_g64 = place(sizeof(double4) * nlag);
   const size_t o_l32 = place(sizeof(float4) * m4), o_g32 = place(sizeof(float4) * nlag);
-  std::vector<uint16_t> nes_order, pair_order;
-  task_orders(ne, nes_order, pair_order);
-  const size_t o_no = place(sizeof(uint16_t) * nes_order.size());
-  const size_t o_po = place(sizeof(uint16_t) * pair_order.size());
+  std::vector<uint16_t> order;
+  task_order(ne, order);
+  const size_t o_to = place(sizeof(uint16_t) * order.size());
   std::vector<unsigned char> img(off, 0);
   auto put = [&](size_t o2, const void* src, size_t bytes) { std::memcpy(img.data() + o2, src, bytes); };
   put(o_eps, g->eps, sizeof(double) * ne);
@@ -348,8 +338,7 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   put(o_g64, lag64.data(), sizeof(double4) * nlag);
   put(o_l32, leg32.data(), sizeof(float4) * m4);
   put(o_g32, lag32.data(), sizeof(float4) * nlag);
-  put(o_no, nes_order.data(), sizeof(uint16_t) * nes_order.size());
-  put(o_po, pair_order.data(), sizeof(uint16_t) * pair_order.size());
+  put(o_to, order.data(), sizeof(uint16_t) * order.size());
   if (hipMalloc(&p->dbuf, off) != hipSuccess) return VTX_ENOMEM;
   if (hipMemcpy(p->dbuf, img.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(p->dbuf);
@@ -374,8 +363,7 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   d.lag64 = (const double4*)(b + o_g64);
   d.leg32 = (const float4*)(b + o_l32);
   d.lag32 = (const float4*)(b + o_g32);
-  d.nes_order = (const uint16_t*)(b + o_no);
-  d.pair_order = (const uint16_t*)(b + o_po);
+  d.task_order = (const uint16_t*)(b + o_to);
   *out = p.get();
   g_plans.push_back(std::move(p));
   return VTX_OK;

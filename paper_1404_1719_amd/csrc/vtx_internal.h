@@ -55,10 +55,10 @@ struct DevPlan {
   const int* nes_ij;        // [ntn] i | (j << 8)
   const NesCoef* nes_coef;  // [ntn]
   const PairCoef* pair_coef;// [ntp]  task p = i * ne + j
-  // Task orders by the zone's k = #{eps_j < mu_e}: row k lists the tasks so that those whose
-  // groups take the same node-loop variants are contiguous (see task_orders in vtx_host.cpp).
-  const uint16_t* nes_order;  // [ne + 1][ntn]
-  const uint16_t* pair_order; // [ne + 1][ntp]
+  // Task order by the zone's k = #{eps_j < mu_e}: row k lists the (i >= j) tasks so that those
+  // whose groups take the same node-loop variants are contiguous (see task_order in
+  // vtx_host.cpp). Scattering tasks and pair tasks (one per unordered pair) share it.
+  const uint16_t* task_order; // [ne + 1][ntn]
   const double4* leg64;     // [m4]   {t, 1 - t, w, 0} on [0, 1]
   const double4* lag64;     // [nlag] {x, x, w exp(x), 0}
   const float4* leg32;

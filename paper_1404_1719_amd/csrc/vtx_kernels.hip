@@ -139,19 +139,18 @@ struct Task {
   double e, ep, sg, D;
 };
 
+// Task t (i >= j). A pair task covers both (i, j) and (j, i): the two share the energy
+// E + E' = eps_i + eps_j, the breakpoints, the blocking factor and the piece variables (which
+// depend on min and max of the two energies only), so one node loop serves both and only
+// the angular-weight coefficients differ.
 template <bool PAIR>
 __device__ __forceinline__ Task make_task(const DevPlan& P, int t) {
   Task K;
   const bool pair = PAIR;
   K.pair = pair;
-  if (pair) {
-    K.i = t / P.ne;
-    K.j = t - K.i * P.ne;
-  } else {
-    const int ij = P.nes_ij[t];
-    K.i = ij & 0xff;
-    K.j = ij >> 8;
-  }
+  const int ij = P.nes_ij[t];
+  K.i = ij & 0xff;
+  K.j = ij >> 8;
   K.e = P.eps[K.i];
   K.ep = P.eps[K.j];
   K.sg = pair ? -1.0 : 1.0;
@@ -416,9 +415,6 @@ struct Q4 {
   double a, b, c, d;
 };
 
-// Task values from the slots (FP64 contraction with the coefficient tables): scattering
-// (a, b, c, d) = (S, l) = (I,0), (I,1), (II,0), (II,1); pair (a, b) = l = 0, 1 of
-// Phi_a,I(i, j).
 // Coefficient tables are read through an opaque pointer at each use, so that the compiler
 // reloads them (from cache) instead of keeping 26-32 doubles live across the node loops.
 template <typename T>
@@ -427,8 +423,29 @@ __device__ __forceinline__ const T* opaque(const T* p) {
   return p;
 }
 
+template <typename R>
+__device__ __forceinline__ void contract_pair(const PairCoef& C, const Slots<R>& S, double& q0, double& q1) {
+  double q[2];
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a = fma(C.A[l][k], double(S.lo0[k]), a);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a = fma(C.B[l][k], double(S.hi[k]), a);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a = fma(C.C[l][k], double(S.lo1[k]), a);
+    q[l] = a;
+  }
+  q0 = q[0];
+  q1 = q[1];
+}
+
+// Task values from the slots (FP64 contraction with the coefficient tables): scattering
+// (a, b, c, d) = (S, l) = (I,0), (I,1), (II,0), (II,1); pair (a, b) = l = 0, 1 of
+// Phi_a,I(i, j) and (c, d) those of Phi_a,I(j, i).
 template <typename R, bool PAIR>
-__device__ __forceinline__ Q4 contract_task(const DevPlan& P, int t, const Slots<R>& S) {
+__device__ __forceinline__ Q4 contract_task(const DevPlan& P, const Task& K, int t, const Slots<R>& S) {
   double q[4];
   if (!PAIR) {
     const NesCoef& C = *opaque(P.nes_coef + t);
@@ -442,19 +459,8 @@ __device__ __forceinline__ Q4 contract_task(const DevPlan& P, int t, const Slots
       q[c] = a;
     }
   } else {
-    const PairCoef& C = *opaque(P.pair_coef + t);
-#pragma unroll
-    for (int l = 0; l < 2; ++l) {
-      double a = 0.0;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) a = fma(C.A[l][k], double(S.lo0[k]), a);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) a = fma(C.B[l][k], double(S.hi[k]), a);
-#pragma unroll
-      for (int k = 0; k < 5; ++k) a = fma(C.C[l][k], double(S.lo1[k]), a);
-      q[l] = a;
-    }
-    q[2] = q[3] = 0.0;
+    contract_pair<R>(*opaque(P.pair_coef + K.i * P.ne + K.j), S, q[0], q[1]);
+    contract_pair<R>(*opaque(P.pair_coef + K.j * P.ne + K.i), S, q[2], q[3]);
   }
   return {q[0], q[1], q[2], q[3]};
 }
@@ -473,7 +479,7 @@ __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const
     run_nodes_fwd<R>(G.mode, L, P.m4, tab, M, H);
     add_group<R>(G, Es, M, H, S);
   }
-  return contract_task<R, PAIR>(P, t, S);
+  return contract_task<R, PAIR>(P, K, t, S);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -545,7 +551,8 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   const int ne = P.ne;
   const int off_q = 6 * ne, off_p = off_q + 4 * P.ntn, off_d = off_p + 2 * P.ntp, n2 = ne * ne;
   const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
-  const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntp : 0;
+  // task counts: scattering tasks (i >= j) and pair tasks (one per unordered pair {i, j})
+  const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;
   stage_zone_state(P, z, selm, Tz, etaz, zs);
   __syncthreads();
   const Zone& Z = *zs;
@@ -554,13 +561,12 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   stage_factors(P, Z, smem + off_d);
   const Units U = task_units(ntn, ntp);
   const int lane = threadIdx.x & 63;
-  const uint16_t* nes_order = P.nes_order + Z.k * P.ntn;
-  const uint16_t* pair_order = P.pair_order + Z.k * P.ntp;
+  const uint16_t* order = P.task_order + Z.k * P.ntn;
   for (int u = U.first; u < U.nU; u += U.step) {
     if (u < U.nN) {
       const int pos = (u << 6) + lane;
       if (pos < ntn) {
-        const int t = nes_order[pos];
+        const int t = order[pos];
         const Q4 q = task_forward<R, false>(P, tab, Z, t);
         double* o = smem + off_q + 4 * t;
         o[0] = q.a;
@@ -571,11 +577,14 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
     } else {
       const int pos = ((u - U.nN) << 6) + lane;
       if (pos < ntp) {
-        const int t = pair_order[pos];
+        const int t = order[pos], ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
         const Q4 q = task_forward<R, true>(P, tab, Z, t);
-        double* o = smem + off_p + 2 * t;
+        double* o = smem + off_p + 2 * (i * ne + j);
         o[0] = q.a;
         o[1] = q.b;
+        o = smem + off_p + 2 * (j * ne + i);   // the same slot on the diagonal, same values
+        o[0] = q.c;
+        o[1] = q.d;
       }
     }
   }
@@ -923,14 +932,19 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
     Loop<R> L;
     const double Es = make_loop<R>(K, G, Z, L);
     if (PAIR) {
-      const PairCoef& C = *opaque(P.pair_coef + t);
+      // adjoint weights (a, b) of Phi_a,I(i, j) and (c, d) of Phi_a,I(j, i), l = 0, 1
+      const PairCoef& C = *opaque(P.pair_coef + K.i * P.ne + K.j);
+      const PairCoef& D = *opaque(P.pair_coef + K.j * P.ne + K.i);
       double lo[5], hi[3];
       const bool pc = G.piece == 2;
 #pragma unroll
       for (int k = 0; k < 5; ++k)
-        lo[k] = G.piece == 1 ? 0.0 : adj.a * (pc ? C.C[0][k] : C.A[0][k]) + adj.b * (pc ? C.C[1][k] : C.A[1][k]);
+        lo[k] = G.piece == 1 ? 0.0
+                             : adj.a * (pc ? C.C[0][k] : C.A[0][k]) + adj.b * (pc ? C.C[1][k] : C.A[1][k]) +
+                                   adj.c * (pc ? D.C[0][k] : D.A[0][k]) + adj.d * (pc ? D.C[1][k] : D.A[1][k]);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) hi[k] = G.piece == 1 ? adj.a * C.B[0][k] + adj.b * C.B[1][k] : 0.0;
+      for (int k = 0; k < 3; ++k)
+        hi[k] = G.piece == 1 ? adj.a * C.B[0][k] + adj.b * C.B[1][k] + adj.c * D.B[0][k] + adj.d * D.B[1][k] : 0.0;
       make_adj_poly<R>(lo, hi, Q);
     }
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0}, S[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -938,7 +952,7 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
     add_group<R>(G, Es, M, H, Sl);
     group_grad<R>(K, G, Z, Es, S, gT, gE);
   }
-  return contract_task<R, PAIR>(P, t, Sl);
+  return contract_task<R, PAIR>(P, K, t, Sl);
 }
 
 // Sum over the 64 lanes of a wave (lane 0's value is the one used: its summation order
@@ -974,26 +988,40 @@ __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, con
   o[3] = q.d;
 }
 
-// Pair task t = i ne + j in the backward; the production factor's weights wait in the
-// task's LDS slot.
+// Pair task t (i >= j) in the backward, covering Phi_a(i, j) and Phi_a(j, i) (once on the
+// diagonal); the production factor's weights wait in the two tasks' LDS slots.
 template <typename R>
 __device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
                                               const double* s_p, double* s_u, int t, double& dT, double& dE) {
-  const int ne = P.ne, i = t / ne, j = t - i * ne;
-  const double pf = s_p[t];
-  double* o = s_u + 4 * P.ntn + 2 * t;
+  const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
+  const bool off = i != j;
+  const double pf = s_p[i * ne + j];   // symmetric in (i, j)
+  double* o1 = s_u + 4 * P.ntn + 2 * (i * ne + j);
+  double* o2 = s_u + 4 * P.ntn + 2 * (j * ne + i);
   const double w0 = pair_gw(P, A, 0, 0, i, j, pf, false) + pair_gw(P, A, 1, 0, j, i, pf, false);
   const double w1 = pair_gw(P, A, 0, 1, i, j, pf, false) + pair_gw(P, A, 1, 1, j, i, pf, false);
-  o[0] = pair_gw(P, A, 0, 0, i, j, pf, true) + pair_gw(P, A, 1, 0, j, i, pf, true);
-  o[1] = pair_gw(P, A, 0, 1, i, j, pf, true) + pair_gw(P, A, 1, 1, j, i, pf, true);
-  const Q4 q = task_backward<R, true>(P, tab, Z, t, Q4{w0, w1, 0.0, 0.0}, dT, dE);
+  const double w2 = off ? pair_gw(P, A, 0, 0, j, i, pf, false) + pair_gw(P, A, 1, 0, i, j, pf, false) : 0.0;
+  const double w3 = off ? pair_gw(P, A, 0, 1, j, i, pf, false) + pair_gw(P, A, 1, 1, i, j, pf, false) : 0.0;
+  o1[0] = pair_gw(P, A, 0, 0, i, j, pf, true) + pair_gw(P, A, 1, 0, j, i, pf, true);
+  o1[1] = pair_gw(P, A, 0, 1, i, j, pf, true) + pair_gw(P, A, 1, 1, j, i, pf, true);
+  if (off) {
+    o2[0] = pair_gw(P, A, 0, 0, j, i, pf, true) + pair_gw(P, A, 1, 0, i, j, pf, true);
+    o2[1] = pair_gw(P, A, 0, 1, j, i, pf, true) + pair_gw(P, A, 1, 1, i, j, pf, true);
+  }
+  const Q4 q = task_backward<R, true>(P, tab, Z, t, Q4{w0, w1, w2, w3}, dT, dE);
   // production factor p = exp(-(eps_i + eps_j)/T): d/dT = (eps_i + eps_j)/T^2 p
-  dT += (q.a * o[0] + q.b * o[1]) * pf * (P.eps[i] + P.eps[j]) * (Z.invT * Z.invT);
-  o[0] = q.a;
-  o[1] = q.b;
+  const double pw = pf * (P.eps[i] + P.eps[j]) * (Z.invT * Z.invT);
+  dT += (q.a * o1[0] + q.b * o1[1]) * pw;
+  o1[0] = q.a;
+  o1[1] = q.b;
+  if (off) {
+    dT += (q.c * o2[0] + q.d * o2[1]) * pw;
+    o2[0] = q.c;
+    o2[1] = q.d;
+  }
 }
 
-// Task units of one zone, at most: scattering ceil(528/64) + pair 1024/64 at 32 bins.
+// Task units of one zone, at most: 2 ceil(528/64) at 32 bins.
 constexpr int kMaxUnits = 32;
 
 template <typename R>
@@ -1004,7 +1032,7 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
                               double* __restrict__ gE_out, double* __restrict__ gf_out) {
   const int ne = P.ne, n2 = ne * ne;
   const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
-  const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntp : 0;
+  const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;   // pair tasks: unordered pairs
   // f | g_eta | g_chi [6 ne each] | task values [4 ntn + 2 ntp] (full-size offsets whatever
   // the process mask) | detailed-balance factors [2 ne^2]
   const int off_ge = 6 * ne, off_gc = 12 * ne, off_u = 18 * ne, off_d = off_u + 4 * P.ntn + 2 * P.ntp;
@@ -1025,16 +1053,15 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
   const int lane = threadIdx.x & 63;
   // d/dT and d/deta_e: summed per unit in the unit's wave, then over units in unit order, so
   // the result does not depend on which wave ran which unit
-  const uint16_t* nes_order = P.nes_order + Z.k * P.ntn;
-  const uint16_t* pair_order = P.pair_order + Z.k * P.ntp;
+  const uint16_t* order = P.task_order + Z.k * P.ntn;
   for (int u = U.first; u < U.nU; u += U.step) {
     double dT = 0.0, dE = 0.0;
     if (u < U.nN) {
       const int pos = (u << 6) + lane;
-      if (pos < ntn) nes_task_bwd<R>(P, tab, Z, A, smem + off_d, smem + off_u, nes_order[pos], dT, dE);
+      if (pos < ntn) nes_task_bwd<R>(P, tab, Z, A, smem + off_d, smem + off_u, order[pos], dT, dE);
     } else {
       const int pos = ((u - U.nN) << 6) + lane;
-      if (pos < ntp) pair_task_bwd<R>(P, tab, Z, A, smem + off_d + n2, smem + off_u, pair_order[pos], dT, dE);
+      if (pos < ntp) pair_task_bwd<R>(P, tab, Z, A, smem + off_d + n2, smem + off_u, order[pos], dT, dE);
     }
     dT = wave_sum(dT);
     dE = wave_sum(dE);
