@@ -286,19 +286,34 @@ struct Loop {
   int oa, ob;   // backward: weights of the group's two end points, 1 - x and x (tail: 1 and x)
 };
 
-// Returns the group's weight scale Es (nodes weigh Es w_k).
+// Anchored map from its end values (already in the bulk type): value = c0 + c1 x with x read
+// from the column of x or 1 - x. The FP64 end values are rounded first, so c1 carries the
+// rounding of the larger end, as the node values themselves would.
+template <typename R>
+__device__ __forceinline__ void anchor(R a, R b, R& c0, R& c1, int& off) {
+  const bool rev = fabs(a) > fabs(b);
+  const R d = b - a;
+  c0 = rev ? b : a;
+  c1 = rev ? -d : d;
+  off = rev ? kOffY : kOffX;
+}
+
+// Returns the group's weight scale Es (nodes weigh Es w_k). The Fermi-Dirac arguments are
+// formed in the units of the bulk type's exponential (Num<R>::zscale).
 template <typename R>
 __device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, const Zone& Z, Loop<R>& L) {
-  const double zs = Num<R>::zscale;
-  const EndV A = end_values(K, G, Z, G.lo.v);
+  const double zs = Num<R>::zscale, its = Z.invT * zs;
+  const double dA = Z.mu - G.lo.v;
+  const double uA = G.c ? (G.w - G.lo.v) * G.ub : G.lo.v * G.ub;
+  const double z1A = K.sg * dA * its, z2A = (K.D - K.sg * dA) * its;
   double Es;
   if (G.lag) {
     Es = Z.T;
-    L.u0 = R(A.u);
+    L.u0 = R(uA);
     L.u1 = R((G.c ? -G.ub : G.ub) * Z.T);
-    L.a0 = R(A.z1 * zs);
+    L.a0 = R(z1A);
     L.a1 = R(-K.sg * zs);
-    L.b0 = R(A.z2 * zs);
+    L.b0 = R(z2A);
     L.b1 = R(K.sg * zs);
     L.ou = L.o1 = L.o2 = kOffGX + G.toff;
     L.ow = kOffGW + G.toff;
@@ -306,17 +321,11 @@ __device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, c
     L.ob = kOffGX + G.toff;
   } else {
     Es = G.hi.v - G.lo.v;
-    const EndV B = end_values(K, G, Z, G.hi.v);
-    const bool ru = fabs(A.u) > fabs(B.u), r1 = fabs(A.z1) > fabs(B.z1), r2 = fabs(A.z2) > fabs(B.z2);
-    L.u0 = R(ru ? B.u : A.u);
-    L.u1 = R(ru ? A.u - B.u : B.u - A.u);
-    L.a0 = R((r1 ? B.z1 : A.z1) * zs);
-    L.a1 = R((r1 ? A.z1 - B.z1 : B.z1 - A.z1) * zs);
-    L.b0 = R((r2 ? B.z2 : A.z2) * zs);
-    L.b1 = R((r2 ? A.z2 - B.z2 : B.z2 - A.z2) * zs);
-    L.ou = ru ? kOffY : kOffX;
-    L.o1 = r1 ? kOffY : kOffX;
-    L.o2 = r2 ? kOffY : kOffX;
+    const double dB = Z.mu - G.hi.v;
+    const double uB = G.c ? (G.w - G.hi.v) * G.ub : G.hi.v * G.ub;
+    anchor<R>(R(uA), R(uB), L.u0, L.u1, L.ou);
+    anchor<R>(R(z1A), R(K.sg * dB * its), L.a0, L.a1, L.o1);
+    anchor<R>(R(z2A), R((K.D - K.sg * dB) * its), L.b0, L.b1, L.o2);
     L.ow = kOffW;
     L.oa = kOffY;
     L.ob = kOffX;
@@ -790,6 +799,22 @@ __device__ __forceinline__ void make_adj_poly(const double lo[5], const double h
   Q.dh[1] = R(2.0 * hi[2]);
 }
 
+// The same from coefficients already in the bulk type.
+template <typename R>
+__device__ __forceinline__ void make_adj_poly_r(const R lo[5], const R hi[3], AdjPoly<R>& Q) {
+  Q.dl[0] = R(3) * lo[0];
+  Q.dl[1] = R(4) * (lo[1] - lo[0]);
+  Q.dl[2] = R(5) * lo[2] - R(3) * lo[1];
+  Q.dl[3] = R(6) * lo[3] - R(2) * lo[2];
+  Q.dl[4] = R(7) * lo[4] - lo[3];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) Q.hl[k] = lo[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Q.hh[k] = hi[k];
+  Q.dh[0] = hi[1];
+  Q.dh[1] = R(2) * hi[2];
+}
+
 template <typename R, int MODE>
 __device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, R xu, R x1, R x2, R w, R pa, R pb,
                                          R M[5], R H[3], R S[7]) {
@@ -906,10 +931,12 @@ __device__ __forceinline__ void group_grad(const Task& K, const GroupDesc& G, co
 }
 
 // Recompute one task with derivatives. adj: upstream weights of the task components
-// (scattering: 4; pair: 2). Returns the task values q and adds d/dT, d/deta_e to gT, gE.
+// (scattering: the four (S, l); pair: l = 0, 1 of both orientations). Returns the task
+// values q and adds d/dT, d/deta_e to gT, gE. lq: the lane's LDS slot (13 values, stride
+// kBlock) that holds a pair task's adjoint-weighted piece coefficients A[5] | B[3] | C[5].
 template <typename R, bool PAIR>
 __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, const Zone& Z, int t, const Q4& adj,
-                                            double& gT, double& gE) {
+                                            R* lq, double& gT, double& gE) {
   const Task K = make_task<PAIR>(P, t);
   const Brk Bk = task_breakpoints<PAIR>(K, Z);
   Slots<R> Sl = {};
@@ -924,6 +951,18 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
     for (int k = 0; k < 3; ++k)
       hi[k] = adj.a * C.hi[0][k] + adj.b * C.hi[1][k] + adj.c * C.hi[2][k] + adj.d * C.hi[3][k];
     make_adj_poly<R>(lo, hi, Q);
+  } else {
+    // adjoint weights (a, b) of Phi_a,I(i, j) and (c, d) of Phi_a,I(j, i), l = 0, 1
+    const PairCoef& C = *opaque(P.pair_coef + K.i * P.ne + K.j);
+    const PairCoef& D = *opaque(P.pair_coef + K.j * P.ne + K.i);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      lq[k * kBlock] = R(adj.a * C.A[0][k] + adj.b * C.A[1][k] + adj.c * D.A[0][k] + adj.d * D.A[1][k]);
+      lq[(8 + k) * kBlock] = R(adj.a * C.C[0][k] + adj.b * C.C[1][k] + adj.c * D.C[0][k] + adj.d * D.C[1][k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      lq[(5 + k) * kBlock] = R(adj.a * C.B[0][k] + adj.b * C.B[1][k] + adj.c * D.B[0][k] + adj.d * D.B[1][k]);
   }
   // kept rolled: unrolled, the four groups' live state exceeds the register budget
 #pragma unroll 1
@@ -932,20 +971,14 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
     Loop<R> L;
     const double Es = make_loop<R>(K, G, Z, L);
     if (PAIR) {
-      // adjoint weights (a, b) of Phi_a,I(i, j) and (c, d) of Phi_a,I(j, i), l = 0, 1
-      const PairCoef& C = *opaque(P.pair_coef + K.i * P.ne + K.j);
-      const PairCoef& D = *opaque(P.pair_coef + K.j * P.ne + K.i);
-      double lo[5], hi[3];
-      const bool pc = G.piece == 2;
+      // the group's piece: A (slots 0-4), B (5-7) or C (8-12); the other part stays zero
+      const R* pl = lq + (G.piece == 2 ? 8 : 0) * kBlock;
+      R lo[5], hi[3];
 #pragma unroll
-      for (int k = 0; k < 5; ++k)
-        lo[k] = G.piece == 1 ? 0.0
-                             : adj.a * (pc ? C.C[0][k] : C.A[0][k]) + adj.b * (pc ? C.C[1][k] : C.A[1][k]) +
-                                   adj.c * (pc ? D.C[0][k] : D.A[0][k]) + adj.d * (pc ? D.C[1][k] : D.A[1][k]);
+      for (int k = 0; k < 5; ++k) lo[k] = G.piece == 1 ? R(0) : pl[k * kBlock];
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        hi[k] = G.piece == 1 ? adj.a * C.B[0][k] + adj.b * C.B[1][k] + adj.c * D.B[0][k] + adj.d * D.B[1][k] : 0.0;
-      make_adj_poly<R>(lo, hi, Q);
+      for (int k = 0; k < 3; ++k) hi[k] = G.piece == 1 ? lq[(5 + k) * kBlock] : R(0);
+      make_adj_poly_r<R>(lo, hi, Q);
     }
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0}, S[7] = {0, 0, 0, 0, 0, 0, 0};
     run_nodes_bwd<R>(G.mode, L, Q, P.m4, tab, M, H, S);
@@ -967,7 +1000,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // holds the completion weights until the task values replace them.
 template <typename R>
 __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
-                                             const double* s_d, double* s_u, int t, double& dT, double& dE) {
+                                             const double* s_d, double* s_u, R* lq, int t, double& dT, double& dE) {
   const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
   const double d = s_d[i * ne + j];
   double* o = s_u + 4 * t;
@@ -979,7 +1012,7 @@ __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, con
     w[c] = nes_ghat(P, A, S, l, i, j) + up;
     o[c] = up;
   }
-  const Q4 q = task_backward<R, false>(P, tab, Z, t, Q4{w[0], w[1], w[2], w[3]}, dT, dE);
+  const Q4 q = task_backward<R, false>(P, tab, Z, t, Q4{w[0], w[1], w[2], w[3]}, lq, dT, dE);
   // completion: Phi_out(j, i) = exp(-(eps_i - eps_j)/T) q, d/dT = (eps_i - eps_j)/T^2 times it
   dT += (q.a * o[0] + q.b * o[1] + q.c * o[2] + q.d * o[3]) * (P.eps[i] - P.eps[j]) * (Z.invT * Z.invT);
   o[0] = q.a;
@@ -992,7 +1025,7 @@ __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, con
 // diagonal); the production factor's weights wait in the two tasks' LDS slots.
 template <typename R>
 __device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
-                                              const double* s_p, double* s_u, int t, double& dT, double& dE) {
+                                              const double* s_p, double* s_u, R* lq, int t, double& dT, double& dE) {
   const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
   const bool off = i != j;
   const double pf = s_p[i * ne + j];   // symmetric in (i, j)
@@ -1008,7 +1041,7 @@ __device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, co
     o2[0] = pair_gw(P, A, 0, 0, j, i, pf, true) + pair_gw(P, A, 1, 0, i, j, pf, true);
     o2[1] = pair_gw(P, A, 0, 1, j, i, pf, true) + pair_gw(P, A, 1, 1, i, j, pf, true);
   }
-  const Q4 q = task_backward<R, true>(P, tab, Z, t, Q4{w0, w1, w2, w3}, dT, dE);
+  const Q4 q = task_backward<R, true>(P, tab, Z, t, Q4{w0, w1, w2, w3}, lq, dT, dE);
   // production factor p = exp(-(eps_i + eps_j)/T): d/dT = (eps_i + eps_j)/T^2 p
   const double pw = pf * (P.eps[i] + P.eps[j]) * (Z.invT * Z.invT);
   dT += (q.a * o1[0] + q.b * o1[1]) * pw;
@@ -1051,6 +1084,8 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
   const Adj A{smem, smem + off_ge, smem + off_gc, ne};
   const Units U = task_units(ntn, ntp);
   const int lane = threadIdx.x & 63;
+  // per-lane slots after the contraction parts: 13 bulk-type values per lane, stride kBlock
+  R* lq = reinterpret_cast<R*>(smem + off_d + 2 * n2 + 24 * ne) + threadIdx.x;
   // d/dT and d/deta_e: summed per unit in the unit's wave, then over units in unit order, so
   // the result does not depend on which wave ran which unit
   const uint16_t* order = P.task_order + Z.k * P.ntn;
@@ -1058,10 +1093,10 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
     double dT = 0.0, dE = 0.0;
     if (u < U.nN) {
       const int pos = (u << 6) + lane;
-      if (pos < ntn) nes_task_bwd<R>(P, tab, Z, A, smem + off_d, smem + off_u, order[pos], dT, dE);
+      if (pos < ntn) nes_task_bwd<R>(P, tab, Z, A, smem + off_d, smem + off_u, lq, order[pos], dT, dE);
     } else {
       const int pos = ((u - U.nN) << 6) + lane;
-      if (pos < ntp) pair_task_bwd<R>(P, tab, Z, A, smem + off_d + n2, smem + off_u, order[pos], dT, dE);
+      if (pos < ntp) pair_task_bwd<R>(P, tab, Z, A, smem + off_d + n2, smem + off_u, lq, order[pos], dT, dE);
     }
     dT = wave_sum(dT);
     dE = wave_sum(dE);
@@ -1188,8 +1223,9 @@ __global__ __launch_bounds__(kBlock) void rates_backward_sparse(
 size_t zone_lds_fwd(const DevPlan& P) {
   return sizeof(double) * (6 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne + 48 * P.ne);
 }
-size_t zone_lds_bwd(const DevPlan& P) {
-  return sizeof(double) * (18 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne + 24 * P.ne);
+// The backward adds 13 values per lane of the bulk type (elem bytes) for the pair tasks.
+size_t zone_lds_bwd(const DevPlan& P, size_t elem) {
+  return sizeof(double) * (18 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne + 24 * P.ne) + 13 * kBlock * elem;
 }
 
 // Dynamic LDS beyond the 64 KiB default must be requested per kernel.
@@ -1231,21 +1267,21 @@ hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const 
                            const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
                            hipStream_t s) {
   if (nz <= 0) return hipSuccess;
-  const size_t lds = zone_lds_bwd(P);
+  const size_t lds32 = zone_lds_bwd(P, sizeof(float)), lds64 = zone_lds_bwd(P, sizeof(double));
   const dim3 grid((unsigned)nz), block(kBlock);
   hipError_t e;
   if (P.precision == VTX_MIXED) {
-    if ((e = allow_lds(rates_backward_kernel<float>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_backward_kernel<float>, grid, block, lds, s, P, nz, kSelBulk, T, eta_e, f, g_eta, g_chi,
-                       g_T, g_eta_e, g_f);
+    if ((e = allow_lds(rates_backward_kernel<float>, lds32)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_backward_kernel<float>, grid, block, lds32, s, P, nz, kSelBulk, T, eta_e, f, g_eta,
+                       g_chi, g_T, g_eta_e, g_f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = allow_lds(rates_backward_sparse, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_backward_sparse, dim3(sparse_grid(nz)), block, lds, s, P, nz, T, eta_e, f, g_eta, g_chi,
-                       g_T, g_eta_e, g_f);
+    if ((e = allow_lds(rates_backward_sparse, lds64)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_backward_sparse, dim3(sparse_grid(nz)), block, lds64, s, P, nz, T, eta_e, f, g_eta,
+                       g_chi, g_T, g_eta_e, g_f);
   } else {
-    if ((e = allow_lds(rates_backward_kernel<double>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_backward_kernel<double>, grid, block, lds, s, P, nz, kSelAll, T, eta_e, f, g_eta, g_chi,
-                       g_T, g_eta_e, g_f);
+    if ((e = allow_lds(rates_backward_kernel<double>, lds64)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rates_backward_kernel<double>, grid, block, lds64, s, P, nz, kSelAll, T, eta_e, f, g_eta,
+                       g_chi, g_T, g_eta_e, g_f);
   }
   return hipGetLastError();
 }
