@@ -545,10 +545,10 @@ __device__ __forceinline__ Units task_units(int ntn, int ntp) {
   return U;
 }
 
-// Parts of the per-zone contractions: as many as the workgroup holds copies of the 3 ne
-// (species, bin) outputs, at most four.
-__device__ __forceinline__ int contraction_parts(int ne) {
-  const int np = (int)blockDim.x / (3 * ne);
+// Parts of the per-zone contractions: lanes run (part, bin) and all three species, so that
+// the lanes fill about one wave (64 / ne parts, from one to four).
+__device__ __forceinline__ int bin_parts(int ne) {
+  const int np = 64 / ne;
   return np < 1 ? 1 : (np > 4 ? 4 : np);
 }
 
@@ -598,62 +598,78 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
     }
   }
   __syncthreads();
-  // completion, species combination and contraction: one lane per (part, species, bin); the
-  // sum over j is split into parts over the four waves and the parts are added in order
-  const int nout = 3 * ne, np = contraction_parts(ne);
-  double* s_part = smem + off_d + 2 * n2;
-  for (int r = threadIdx.x; r < np * nout; r += blockDim.x) {
-    const int part = r / nout, o = r - part * nout, s = o / ne, i = o % ne, sb = partner(s);
-    const int j0 = part * ne / np, j1 = (part + 1) * ne / np;
+  // completion, species combination and contraction: one lane per (part, bin i) runs all
+  // three species over a part of j, so each (i, j) pair's task values, detailed-balance
+  // factors and weights are read and combined once; the parts are added in order
+  const int npb = bin_parts(ne);
+  double* s_part = smem + off_d + 2 * n2;   // [part][i][species][eta0, chi0, eta1, chi1]
+  for (int r = threadIdx.x; r < npb * ne; r += blockDim.x) {
+    const int part = r / ne, i = r - part * ne;
+    const int j0 = part * ne / npb, j1 = (part + 1) * ne / npb;
     const double* s_f = smem;
     const double* s_qn = smem + off_q;
     const double* s_pa = smem + off_p;
     const double* s_d = smem + off_d;
     const double* s_p = s_d + n2;
-    const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
-    double e0 = 0.0, c0 = 0.0, e1 = 0.0, c1 = 0.0;
+    double acc[3][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     for (int j = j0; j < j1; ++j) {
       const double cw = P.c0w[j];
       const double dfac = s_d[i * ne + j];
+      const double cin = (i > j) ? cw * dfac : cw, cout = (i < j) ? cw * dfac : cw;
+      double fj[3][2];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        fj[s][0] = s_f[(2 * s) * ne + j];
+        fj[s][1] = s_f[(2 * s + 1) * ne + j];
+      }
       if (do_nes) {
         const double* q = s_qn + 4 * (i >= j ? tri(i, j) : tri(j, i));
-        const double k0 = bI * q[0] + bII * q[2];
-        const double k1 = bI * q[1] + bII * q[3];
-        const double a_in = (i > j) ? dfac : 1.0, a_out = (i < j) ? dfac : 1.0;
-        const double f0 = s_f[(2 * s) * ne + j], f1 = s_f[(2 * s + 1) * ne + j];
-        const double in0 = (cw * f0 * k0) * a_in, in1 = (cw * f1 * k1) * a_in;
-        e0 += in0;
-        c0 += in0 + (cw * (1.0 - f0) * k0) * a_out;
-        e1 += in1;
-        c1 += in1 - (cw * f1 * k1) * a_out;
+        const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+          const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
+          const double k0 = bI * q0 + bII * q2, k1 = bI * q1 + bII * q3;
+          const double t0 = fj[s][0] * k0, t1 = fj[s][1] * k1;
+          acc[s][0] += cin * t0;
+          acc[s][1] += cin * t0 + cout * (k0 - t0);
+          acc[s][2] += cin * t1;
+          acc[s][3] += (cin - cout) * t1;
+        }
       }
       if (do_pair) {
         const double* aij = s_pa + 2 * (i * ne + j);
         const double* aji = s_pa + 2 * (j * ne + i);
-        const double ka0 = bI * aij[0] + bII * aji[0];
-        const double ka1 = bI * aij[1] + bII * aji[1];
-        const double pf = s_p[i * ne + j];
-        const double g0 = s_f[(2 * sb) * ne + j], g1 = s_f[(2 * sb + 1) * ne + j];
-        const double pr0 = (cw * (1.0 - g0) * ka0) * pf;
-        const double t1 = cw * g1 * ka1;
-        e0 += pr0;
-        c0 += pr0 + cw * g0 * ka0;
-        e1 -= t1 * pf;
-        c1 += t1 - t1 * pf;
+        const double a0 = aij[0], a1 = aij[1], b0 = aji[0], b1 = aji[1];
+        const double pf = s_p[i * ne + j], cwp = cw * pf;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+          const int sb = partner(s);
+          const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
+          const double ka0 = bI * a0 + bII * b0, ka1 = bI * a1 + bII * b1;
+          const double tp = fj[sb][0] * ka0, t1 = cw * fj[sb][1] * ka1;
+          const double pr0 = cwp * (ka0 - tp);
+          acc[s][0] += pr0;
+          acc[s][1] += pr0 + cw * tp;
+          acc[s][2] -= t1 * pf;
+          acc[s][3] += t1 * (1.0 - pf);
+        }
       }
     }
-    double* pp = s_part + 4 * r;
-    pp[0] = e0;
-    pp[1] = c0;
-    pp[2] = e1;
-    pp[3] = c1;
+    double* pp = s_part + 12 * r;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      pp[4 * s] = acc[s][0];
+      pp[4 * s + 1] = acc[s][1];
+      pp[4 * s + 2] = acc[s][2];
+      pp[4 * s + 3] = acc[s][3];
+    }
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+  for (int o = threadIdx.x; o < 3 * ne; o += blockDim.x) {
     const int s = o / ne, i = o % ne;
     double e0 = 0.0, c0 = 0.0, e1 = 0.0, c1 = 0.0;
-    for (int part = 0; part < np; ++part) {
-      const double* pp = s_part + 4 * (part * nout + o);
+    for (int part = 0; part < npb; ++part) {
+      const double* pp = s_part + 12 * (part * ne + i) + 4 * s;
       e0 += pp[0];
       c0 += pp[1];
       e1 += pp[2];
@@ -1115,57 +1131,71 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
     gT_out[Z.z] = sT;
     gE_out[Z.z] = sE;
   }
-  // g_f: column contractions of the kernels from LDS, one lane per (part, species, bin); the
-  // sum over i is split into parts and the parts are added in order
-  const int nout = 3 * ne, np = contraction_parts(ne);
-  double* s_part = smem + off_d + 2 * n2;
-  for (int r = threadIdx.x; r < np * nout; r += blockDim.x) {
-    const int part = r / nout, o = r - part * nout, sg = o / ne, j = o % ne;
-    const int i0 = part * ne / np, i1 = (part + 1) * ne / np;
+  // g_f: column contractions of the kernels from LDS, one lane per (part, bin j) for all three
+  // species over a part of i (c0 w_j factors out of the sum); the parts are added in order
+  const int npb = bin_parts(ne);
+  double* s_part = smem + off_d + 2 * n2;   // [part][j][species][g_f0, g_f1]
+  for (int r = threadIdx.x; r < npb * ne; r += blockDim.x) {
+    const int part = r / ne, j = r - part * ne;
+    const int i0 = part * ne / npb, i1 = (part + 1) * ne / npb;
     const double* s_qn = smem + off_u;
     const double* s_pa = smem + off_u + 4 * P.ntn;
     const double* s_d = smem + off_d;
     const double* s_p = s_d + n2;
-    const double cw = P.c0w[j];
-    double a0 = 0.0, a1 = 0.0;
-    if (do_nes) {
-      const double bI = beta_of(P, sg, 0), bII = beta_of(P, sg, 1);
-      for (int i = i0; i < i1; ++i) {
+    double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int i = i0; i < i1; ++i) {
+      double ge[3][2], gc[3][2];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        ge[s][0] = A.GE(s, 0, i);
+        ge[s][1] = A.GE(s, 1, i);
+        gc[s][0] = A.GC(s, 0, i);
+        gc[s][1] = A.GC(s, 1, i);
+      }
+      if (do_nes) {
         const double* q = s_qn + 4 * (i >= j ? tri(i, j) : tri(j, i));
-        const double k0 = bI * q[0] + bII * q[2], k1 = bI * q[1] + bII * q[3];
+        const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
         const double dfac = s_d[i * ne + j];
         const double a_in = (i > j) ? dfac : 1.0, a_out = (i < j) ? dfac : 1.0;
-        const double ge0 = cw * A.GE(sg, 0, i), gc0 = cw * A.GC(sg, 0, i);
-        const double ge1 = cw * A.GE(sg, 1, i), gc1 = cw * A.GC(sg, 1, i);
-        a0 += ((ge0 + gc0) * k0) * a_in - (gc0 * k0) * a_out;
-        a1 += ((ge1 + gc1) * k1) * a_in - (gc1 * k1) * a_out;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+          const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
+          const double k0 = bI * q0 + bII * q2, k1 = bI * q1 + bII * q3;
+          acc[s][0] += k0 * ((ge[s][0] + gc[s][0]) * a_in - gc[s][0] * a_out);
+          acc[s][1] += k1 * ((ge[s][1] + gc[s][1]) * a_in - gc[s][1] * a_out);
+        }
       }
-    }
-    if (do_pair) {
-      const int s = partner(sg);
-      const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
-      for (int i = i0; i < i1; ++i) {
+      if (do_pair) {
         const double* aij = s_pa + 2 * (i * ne + j);
         const double* aji = s_pa + 2 * (j * ne + i);
-        const double ka0 = bI * aij[0] + bII * aji[0];
-        const double ka1 = bI * aij[1] + bII * aji[1];
+        const double a0 = aij[0], a1 = aij[1], b0 = aji[0], b1 = aji[1];
         const double pf = s_p[i * ne + j];
-        const double ge0 = cw * A.GE(s, 0, i), gc0 = cw * A.GC(s, 0, i);
-        const double ge1 = cw * A.GE(s, 1, i), gc1 = cw * A.GC(s, 1, i);
-        a0 += -((ge0 + gc0) * ka0) * pf + gc0 * ka0;
-        a1 += -(ge1 * ka1) * pf + gc1 * ka1 - (gc1 * ka1) * pf;
+#pragma unroll
+        for (int sg = 0; sg < 3; ++sg) {
+          const int s = partner(sg);
+          const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
+          const double ka0 = bI * a0 + bII * b0, ka1 = bI * a1 + bII * b1;
+          acc[sg][0] += ka0 * (gc[s][0] - (ge[s][0] + gc[s][0]) * pf);
+          acc[sg][1] += ka1 * (gc[s][1] * (1.0 - pf) - ge[s][1] * pf);
+        }
       }
     }
-    s_part[2 * r] = a0;
-    s_part[2 * r + 1] = a1;
+    const double cw = P.c0w[j];
+    double* pp = s_part + 6 * r;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      pp[2 * s] = cw * acc[s][0];
+      pp[2 * s + 1] = cw * acc[s][1];
+    }
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+  for (int o = threadIdx.x; o < 3 * ne; o += blockDim.x) {
     const int sg = o / ne, j = o % ne;
     double a0 = 0.0, a1 = 0.0;
-    for (int part = 0; part < np; ++part) {
-      a0 += s_part[2 * (part * nout + o)];
-      a1 += s_part[2 * (part * nout + o) + 1];
+    for (int part = 0; part < npb; ++part) {
+      const double* pp = s_part + 6 * (part * ne + j) + 2 * sg;
+      a0 += pp[0];
+      a1 += pp[1];
     }
     const int64_t zo = Z.z * 6 * ne;
     gf_out[zo + (2 * sg) * ne + j] = a0;
@@ -1218,8 +1248,8 @@ __global__ __launch_bounds__(kBlock) void rates_backward_sparse(
   }
 }
 
-// Per-zone LDS: the layouts above plus the contraction parts (4 x 3 ne x 4 doubles forward,
-// 4 x 3 ne x 2 backward).
+// Per-zone LDS: the layouts above plus the contraction parts (at most 4 x ne x 3 x 4 doubles
+// forward, 4 x ne x 3 x 2 backward).
 size_t zone_lds_fwd(const DevPlan& P) {
   return sizeof(double) * (6 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne + 48 * P.ne);
 }
