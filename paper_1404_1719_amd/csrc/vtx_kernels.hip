@@ -518,14 +518,18 @@ __device__ void stage_zone_state(const DevPlan& P, int64_t z, int selm, const do
   }
 }
 
-// Detailed-balance factors exp(-|eps_i - eps_j|/T) and exp(-(eps_i + eps_j)/T), FP64.
+// Detailed-balance factors exp(-|eps_i - eps_j|/T) and exp(-(eps_i + eps_j)/T), FP64; both
+// are symmetric in (i, j), so each is formed once for i >= j and stored twice.
 __device__ void stage_factors(const DevPlan& P, const Zone& Z, double* s_d) {
   const int ne = P.ne, n2 = ne * ne;
-  for (int r = threadIdx.x; r < n2; r += blockDim.x) {
-    const int i = r / ne, j = r % ne;
+  for (int r = threadIdx.x; r < P.ntn; r += blockDim.x) {
+    const int ij = P.nes_ij[r], i = ij & 0xff, j = ij >> 8;
     const double ei = P.eps[i], ej = P.eps[j];
-    s_d[r] = exp(-fabs(ei - ej) * Z.invT);
-    s_d[n2 + r] = exp(-(ei + ej) * Z.invT);
+    const double d = exp(-(ei - ej) * Z.invT), pf = exp(-(ei + ej) * Z.invT);
+    s_d[i * ne + j] = d;
+    s_d[j * ne + i] = d;
+    s_d[n2 + i * ne + j] = pf;
+    s_d[n2 + j * ne + i] = pf;
   }
 }
 
