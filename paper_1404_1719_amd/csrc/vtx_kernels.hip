@@ -759,39 +759,87 @@ struct Adj {
   __device__ double GC(int s, int m, int i) const { return gc[(2 * s + m) * ne + i]; }
 };
 
-// Scattering: weight of Phi_out_{l,S}(a, b) plus that of Phi_in_{l,S}(b, a) in L.
-__device__ double nes_ghat(const DevPlan& P, const Adj& A, int S, int l, int a, int b) {
-  double go = 0.0, gi = 0.0;
-  for (int s = 0; s < 3; ++s) {
-    const double bs = beta_of(P, s, S);
-    if (l == 0) {
-      go += bs * A.GC(s, 0, a) * (1.0 - A.F(s, 0, b));
-      gi += bs * (A.GE(s, 0, b) + A.GC(s, 0, b)) * A.F(s, 0, a);
-    } else {
-      go -= bs * A.GC(s, 1, a) * A.F(s, 1, b);
-      gi += bs * (A.GE(s, 1, b) + A.GC(s, 1, b)) * A.F(s, 1, a);
+// Upstream weights of a scattering task (i >= j): for (S, l), the weight of Phi_out_{l,S}(a, b)
+// plus that of Phi_in_{l,S}(b, a) in L is
+//   ghat(a, b) = c0 w_b sum_s beta_S(s) gchi_l(s, a) ft_l(s, b) + c0 w_a sum_s beta_S(s) (geta + gchi)_l(s, b) f_l(s, a),
+// ft_0 = 1 - f_0, ft_1 = -f_1. The task carries ghat(i, j) + d ghat(j, i) (d the detailed-balance
+// factor, i > j); up receives d ghat(j, i). Each species' values at i and j are read once.
+__device__ __forceinline__ void nes_adjoint(const DevPlan& P, const Adj& A, int i, int j, double d, double w[4],
+                                            double up[4]) {
+  const double cwi = P.c0w[i], cwj = P.c0w[j];
+  const bool off = i > j;
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    double oI = 0.0, oII = 0.0, iI = 0.0, iII = 0.0;   // (a, b) = (i, j): out and in sums
+    double pI = 0.0, pII = 0.0, qI = 0.0, qII = 0.0;   // (a, b) = (j, i)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
+      const double fi = A.F(s, l, i), fj = A.F(s, l, j);
+      const double ci = A.GC(s, l, i), cj = A.GC(s, l, j);
+      const double gi = A.GE(s, l, i) + ci, gj = A.GE(s, l, j) + cj;
+      const double fti = l == 0 ? 1.0 - fi : -fi, ftj = l == 0 ? 1.0 - fj : -fj;
+      const double o1 = ci * ftj, i1 = gj * fi, o2 = cj * fti, i2 = gi * fj;
+      oI += bI * o1;
+      oII += bII * o1;
+      iI += bI * i1;
+      iII += bII * i1;
+      pI += bI * o2;
+      pII += bII * o2;
+      qI += bI * i2;
+      qII += bII * i2;
     }
+    const double uI = off ? d * (cwi * pI + cwj * qI) : 0.0, uII = off ? d * (cwi * pII + cwj * qII) : 0.0;
+    up[l] = uI;
+    up[2 + l] = uII;
+    w[l] = cwj * oI + cwi * iI + uI;
+    w[2 + l] = cwj * oII + cwi * iII + uII;
   }
-  return P.c0w[b] * go + P.c0w[a] * gi;
 }
 
-// Pair: weight of Phi_a_{l,S}(a, b) in L (pf = p_ab), or only its p-coefficient.
-__device__ double pair_gw(const DevPlan& P, const Adj& A, int S, int l, int a, int b, double pf, bool ponly) {
-  double acc = 0.0;
-  for (int s = 0; s < 3; ++s) {
-    const double bs = beta_of(P, s, S);
-    const int sb = partner(s);
-    if (l == 0) {
-      const double ge = A.GE(s, 0, a) + A.GC(s, 0, a);
-      const double f0 = A.F(sb, 0, b);
-      acc += ponly ? bs * ge * (1.0 - f0) : bs * (ge * (1.0 - f0) * pf + A.GC(s, 0, a) * f0);
-    } else {
-      const double f1 = A.F(sb, 1, b);
-      acc += ponly ? -bs * f1 * (A.GE(s, 1, a) + A.GC(s, 1, a))
-                   : bs * f1 * (-A.GE(s, 1, a) * pf + A.GC(s, 1, a) * (1.0 - pf));
+// Upstream weights of a pair task {i, j}: for orientation (a, b) and l, the weight of
+// Phi_a,I(a, b) collects Phi_a_{l,I}(a, b) and Phi_a_{l,II}(b, a). With partner species sb,
+//   ponly_S(a, b) = c0 w_b sum_s beta_S(s) (geta + gchi)_l(s, a) ft_l(sb, b),
+//   P2_S(a, b)    = c0 w_b sum_s beta_S(s) gchi_l(s, a) f_l(sb, b),
+// the weight is p (ponly_I(a, b) + ponly_II(b, a)) + P2_I(a, b) + P2_II(b, a) and its
+// p-coefficient (for d/dT of the production factor) ponly_I(a, b) + ponly_II(b, a).
+__device__ __forceinline__ void pair_adjoint(const DevPlan& P, const Adj& A, int i, int j, double pf, double w[4],
+                                             double pc[4]) {
+  const double cwi = P.c0w[i], cwj = P.c0w[j];
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    double fi[3], fj[3], ci[3], cj[3], gi[3], gj[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      fi[s] = A.F(s, l, i);
+      fj[s] = A.F(s, l, j);
+      ci[s] = A.GC(s, l, i);
+      cj[s] = A.GC(s, l, j);
+      gi[s] = A.GE(s, l, i) + ci[s];
+      gj[s] = A.GE(s, l, j) + cj[s];
     }
+    // sums over s with the partner's f at b: (a, b) = (i, j) -> 1, (j, i) -> 2
+    double pI1 = 0.0, pII1 = 0.0, cI1 = 0.0, cII1 = 0.0, pI2 = 0.0, pII2 = 0.0, cI2 = 0.0, cII2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int sb = partner(s);
+      const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
+      const double ftj = l == 0 ? 1.0 - fj[sb] : -fj[sb], fti = l == 0 ? 1.0 - fi[sb] : -fi[sb];
+      pI1 += bI * gi[s] * ftj;    // ponly_I(i, j) / c0 w_j
+      pII1 += bII * gj[s] * fti;  // ponly_II(j, i) / c0 w_i
+      cI1 += bI * ci[s] * fj[sb];
+      cII1 += bII * cj[s] * fi[sb];
+      pI2 += bI * gj[s] * fti;    // ponly_I(j, i) / c0 w_i
+      pII2 += bII * gi[s] * ftj;  // ponly_II(i, j) / c0 w_j
+      cI2 += bI * cj[s] * fi[sb];
+      cII2 += bII * ci[s] * fj[sb];
+    }
+    const double p1 = cwj * pI1 + cwi * pII1, p2 = cwi * pI2 + cwj * pII2;
+    pc[l] = p1;
+    pc[2 + l] = p2;
+    w[l] = pf * p1 + cwj * cI1 + cwi * cII1;
+    w[2 + l] = pf * p2 + cwi * cI2 + cwj * cII2;
   }
-  return P.c0w[b] * acc;
 }
 
 // Adjoint-weighted angular weight of a piece and its u-derivative:
@@ -1022,16 +1070,13 @@ template <typename R>
 __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
                                              const double* s_d, double* s_u, R* lq, int t, double& dT, double& dE) {
   const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
-  const double d = s_d[i * ne + j];
   double* o = s_u + 4 * t;
-  double w[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int S = c >> 1, l = c & 1;
-    const double up = (i > j) ? d * nes_ghat(P, A, S, l, j, i) : 0.0;
-    w[c] = nes_ghat(P, A, S, l, i, j) + up;
-    o[c] = up;
-  }
+  double w[4], up[4];
+  nes_adjoint(P, A, i, j, s_d[i * ne + j], w, up);
+  o[0] = up[0];
+  o[1] = up[1];
+  o[2] = up[2];
+  o[3] = up[3];
   const Q4 q = task_backward<R, false>(P, tab, Z, t, Q4{w[0], w[1], w[2], w[3]}, lq, dT, dE);
   // completion: Phi_out(j, i) = exp(-(eps_i - eps_j)/T) q, d/dT = (eps_i - eps_j)/T^2 times it
   dT += (q.a * o[0] + q.b * o[1] + q.c * o[2] + q.d * o[3]) * (P.eps[i] - P.eps[j]) * (Z.invT * Z.invT);
@@ -1051,17 +1096,15 @@ __device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, co
   const double pf = s_p[i * ne + j];   // symmetric in (i, j)
   double* o1 = s_u + 4 * P.ntn + 2 * (i * ne + j);
   double* o2 = s_u + 4 * P.ntn + 2 * (j * ne + i);
-  const double w0 = pair_gw(P, A, 0, 0, i, j, pf, false) + pair_gw(P, A, 1, 0, j, i, pf, false);
-  const double w1 = pair_gw(P, A, 0, 1, i, j, pf, false) + pair_gw(P, A, 1, 1, j, i, pf, false);
-  const double w2 = off ? pair_gw(P, A, 0, 0, j, i, pf, false) + pair_gw(P, A, 1, 0, i, j, pf, false) : 0.0;
-  const double w3 = off ? pair_gw(P, A, 0, 1, j, i, pf, false) + pair_gw(P, A, 1, 1, i, j, pf, false) : 0.0;
-  o1[0] = pair_gw(P, A, 0, 0, i, j, pf, true) + pair_gw(P, A, 1, 0, j, i, pf, true);
-  o1[1] = pair_gw(P, A, 0, 1, i, j, pf, true) + pair_gw(P, A, 1, 1, j, i, pf, true);
+  double w[4], pc[4];
+  pair_adjoint(P, A, i, j, pf, w, pc);
+  o1[0] = pc[0];
+  o1[1] = pc[1];
   if (off) {
-    o2[0] = pair_gw(P, A, 0, 0, j, i, pf, true) + pair_gw(P, A, 1, 0, i, j, pf, true);
-    o2[1] = pair_gw(P, A, 0, 1, j, i, pf, true) + pair_gw(P, A, 1, 1, i, j, pf, true);
+    o2[0] = pc[2];
+    o2[1] = pc[3];
   }
-  const Q4 q = task_backward<R, true>(P, tab, Z, t, Q4{w0, w1, w2, w3}, lq, dT, dE);
+  const Q4 q = task_backward<R, true>(P, tab, Z, t, Q4{w[0], w[1], off ? w[2] : 0.0, off ? w[3] : 0.0}, lq, dT, dE);
   // production factor p = exp(-(eps_i + eps_j)/T): d/dT = (eps_i + eps_j)/T^2 p
   const double pw = pf * (P.eps[i] + P.eps[j]) * (Z.invT * Z.invT);
   dT += (q.a * o1[0] + q.b * o1[1]) * pw;
