@@ -219,8 +219,17 @@ __device__ __forceinline__ Brk task_breakpoints(const Task& K, const Zone& Z) {
 // wholly below or wholly above eps_j (eps_j is a breakpoint whenever a panel could cross it),
 // so only the tail can straddle u = 1. Each pair group lies in one piece: [0, m] (A),
 // [m, M] (B), [M, w] (C).
+// The ends of group g: (0, b1), (b1, b2), (b2, b3), then (b3, b3) for the scattering tail or
+// (b3, w) for the pair's last panel.
 template <bool PAIR>
-__device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, const Brk& Bk, int g) {
+__device__ __forceinline__ Tri group_hi(const Task& K, const Brk& Bk, int g) {
+  const Tri last = PAIR ? Tri{K.D, 0.0, 0.0} : Bk.b3;
+  return pick4(g, Bk.b1, Bk.b2, Bk.b3, last);
+}
+
+template <bool PAIR>
+__device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, const Brk& Bk, int g, const Tri& lo,
+                                              const Tri& hi) {
   GroupDesc G;
   const Tri zero = {0.0, 0.0, 0.0};
   G.w = 0.0;
@@ -236,20 +245,17 @@ __device__ __forceinline__ GroupDesc describe(const DevPlan& P, const Task& K, c
       G.toff = g * P.m4;
       G.mode = kGen;
     } else {
-      const Tri &s1 = Bk.b1, &s2 = Bk.b2, &s3 = Bk.b3;
-      G.lo = pick4(g, zero, s1, s2, s3);
-      G.hi = pick4(g, s1, s2, s3, s3);
+      G.lo = lo;
+      G.hi = hi;
       G.lag = (g == 3);
       G.toff = 0;
-      G.mode = G.lag ? (s3.v >= K.ep ? kHigh : kGen) : (G.hi.v <= K.ep ? kLow : kHigh);
+      G.mode = G.lag ? (Bk.b3.v >= K.ep ? kHigh : kGen) : (G.hi.v <= K.ep ? kLow : kHigh);
     }
   } else {
     const bool le = K.e <= K.ep;
     const double mn = le ? K.e : K.ep, mx = le ? K.ep : K.e, w = K.D;
-    const Tri &b1 = Bk.b1, &b2 = Bk.b2, &b3 = Bk.b3;
-    const Tri b4 = {w, 0.0, 0.0};
-    G.lo = pick4(g, zero, b1, b2, b3);
-    G.hi = pick4(g, b1, b2, b3, b4);
+    G.lo = lo;
+    G.hi = hi;
     G.lag = false;
     G.toff = 0;
     const double mid = 0.5 * (G.lo.v + G.hi.v);
@@ -481,7 +487,9 @@ __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const
   Slots<R> S = {};
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const GroupDesc G = describe<PAIR>(P, K, Bk, g);
+    const Tri zero = {0.0, 0.0, 0.0};
+    const Tri lo = g == 0 ? zero : group_hi<PAIR>(K, Bk, g - 1);
+    const GroupDesc G = describe<PAIR>(P, K, Bk, g, lo, group_hi<PAIR>(K, Bk, g));
     Loop<R> L;
     const double Es = make_loop<R>(K, G, Z, L);
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0};
@@ -1032,10 +1040,14 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
     for (int k = 0; k < 3; ++k)
       lq[(5 + k) * kBlock] = R(adj.a * C.B[0][k] + adj.b * C.B[1][k] + adj.c * D.B[0][k] + adj.d * D.B[1][k]);
   }
-  // kept rolled: unrolled, the four groups' live state exceeds the register budget
+  // kept rolled: unrolled, the four groups' live state exceeds the register budget; the lower
+  // end of a group is the upper end of the one before
+  Tri lo = {0.0, 0.0, 0.0};
 #pragma unroll 1
   for (int g = 0; g < 4; ++g) {
-    const GroupDesc G = describe<PAIR>(P, K, Bk, g);
+    const Tri hi = group_hi<PAIR>(K, Bk, g);
+    const GroupDesc G = describe<PAIR>(P, K, Bk, g, lo, hi);
+    lo = hi;
     Loop<R> L;
     const double Es = make_loop<R>(K, G, Z, L);
     if (PAIR) {
