@@ -8,8 +8,10 @@ both processes, l = 0, 1, one forward and one backward evaluation).
 
 Also reported: the same step in plain FP64 (speedup of mixed over FP64), the maximal
 relative error per output against the FP64 oracle on sampled zones, a roofline entry for
-the dominant kernel (algorithmic FLOPs per launch / measured launch time), and the oracle
-timed on the host cores on a bounded sample.
+the dominant kernel (algorithmic FLOPs per launch / measured launch time), the oracle
+timed on the host cores on a bounded sample, the same step with the workload held in
+pinned host memory and streamed through the GPU chunk by chunk (PCIe transfers included),
+and the explicit Jacobian blocks timed over one chunk.
 """
 import argparse
 import hashlib
@@ -197,6 +199,139 @@ class Runner:
         return float(np.mean(fwd)), float(np.mean(bwd)), float(np.mean(zones))
 
 
+class Streamer:
+    """The workload held in pinned host memory and streamed through the GPU: per chunk, inputs
+    host-to-device on one stream, forward + backward on a second, outputs device-to-host on a
+    third (all default priority), with two device buffer sets so that the transfers of one
+    chunk overlap the kernels of its neighbours."""
+
+    IN = ("T", "E", "f", "g_eta", "g_chi")
+    OUT = ("eta", "chi", "gT", "gE", "gf")
+
+    def __init__(self, run):
+        torch = run.torch
+        self.torch, self.vtx, self.run = torch, run.vtx, run
+        src = {"T": run.T, "E": run.E, "f": run.f, "g_eta": run.g_eta, "g_chi": run.g_chi,
+               "eta": run.eta, "chi": run.chi, "gT": run.gT, "gE": run.gE, "gf": run.gf}
+        total = sum(t.numel() for t in src.values())
+        pool = torch.empty(total, dtype=torch.float64, pin_memory=True)   # one pinned allocation
+        self.host, off = {}, 0
+        for k, t in src.items():
+            self.host[k] = pool[off:off + t.numel()].view(t.shape)
+            off += t.numel()
+        for k in self.IN:
+            self.host[k].copy_(src[k])
+        self.bytes_in = sum(self.host[k].numel() for k in self.IN) * 8
+        self.bytes_out = sum(self.host[k].numel() for k in self.OUT) * 8
+        n = max(b - a for a, b in run.chunks)
+        dev = run.T.device
+        self.slots = []
+        for _ in range(2):
+            d = {k: torch.empty((n,) + tuple(src[k].shape[1:]), dtype=torch.float64, device=dev) for k in src}
+            d["in_free"] = torch.cuda.Event()
+            d["out_free"] = torch.cuda.Event()
+            d["used"] = False
+            self.slots.append(d)
+        self.h2d, self.comp, self.d2h = (torch.cuda.Stream(device=dev) for _ in range(3))
+
+    def step(self):
+        torch, vtx, run, H = self.torch, self.vtx, self.run, self.host
+        cur = torch.cuda.current_stream()
+        for st in (self.h2d, self.comp, self.d2h):
+            st.wait_stream(cur)
+        for c, (a, b) in enumerate(run.chunks):
+            d = self.slots[c % 2]
+            n = b - a
+            ready = torch.cuda.Event()
+            with torch.cuda.stream(self.h2d):
+                if d["used"]:
+                    self.h2d.wait_event(d["in_free"])
+                for k in self.IN:
+                    d[k][:n].copy_(H[k][a:b], non_blocking=True)
+                ready.record(self.h2d)
+            with torch.cuda.stream(self.comp):
+                self.comp.wait_event(ready)
+                if d["used"]:
+                    self.comp.wait_event(d["out_free"])
+                vtx.forward(run.grid, run.opts, d["T"][:n], d["E"][:n], d["f"][:n], d["eta"][:n], d["chi"][:n],
+                            stream=self.comp)
+                vtx.backward(run.grid, run.opts, d["T"][:n], d["E"][:n], d["f"][:n], d["g_eta"][:n],
+                             d["g_chi"][:n], d["gT"][:n], d["gE"][:n], d["gf"][:n], stream=self.comp)
+                d["in_free"].record(self.comp)
+            done = torch.cuda.Event()
+            done.record(self.comp)
+            with torch.cuda.stream(self.d2h):
+                self.d2h.wait_event(done)
+                for k in self.OUT:
+                    H[k][a:b].copy_(d[k][:n], non_blocking=True)
+                d["out_free"].record(self.d2h)
+            d["used"] = True
+        cur.wait_stream(self.d2h)
+        cur.wait_stream(self.comp)
+
+    def timed(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / max(steps, 1)
+
+
+def streaming_leg(run, units, steps, warmup):
+    """Whole-job rate with the workload in pinned host memory (PCIe transfers included)."""
+    torch = run.torch
+    st = Streamer(run)
+    t = st.timed(steps, warmup)
+    same = bool(torch.equal(st.host["gT"].to(run.gT.device), run.gT) and
+                torch.equal(st.host["eta"].to(run.eta.device), run.eta))
+    out = {"value": units / t, "unit": "zone*(eps,eps')/s", "ms_per_step": t * 1e3, "steps": steps,
+           "bytes_h2d": st.bytes_in, "bytes_d2h": st.bytes_out,
+           "h2d_plus_d2h_GBps": (st.bytes_in + st.bytes_out) / t / 1e9,
+           "outputs_equal_resident_run": same,
+           "note": "pinned host buffers, 3 streams (H2D, compute, D2H), 2 device buffer sets"}
+    del st
+    torch.cuda.empty_cache()
+    return out
+
+
+def jacobian_leg(inp, wl, precision, launches):
+    """Explicit Jacobian blocks over one chunk: launch time (HIP events on the launch stream)
+    and the HBM write rate of its 24 NE^2 doubles per zone."""
+    import torch
+    from paper_1404_1719_amd import vtx
+    nz = wl.nzones // wl.chunks
+    dev = torch.device("cuda:0")
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+    T = torch.from_numpy(inp.T[:nz]).to(dev)
+    E = torch.from_numpy(inp.eta_e[:nz]).to(dev)
+    jac = torch.empty((nz, 3, 2, 4, wl.ne, wl.ne), dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream())
+    ms = []
+    with torch.cuda.stream(s):
+        vtx.jacobian(grid, opts, T, E, jac, stream=s)
+        for _ in range(launches):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(s)
+            vtx.jacobian(grid, opts, T, E, jac, stream=s)
+            ev[1].record(s)
+            ms.append(ev)
+    s.synchronize()
+    t = float(np.mean([a.elapsed_time(b) for a, b in ms]))
+    written = jac.numel() * 8
+    del jac
+    torch.cuda.empty_cache()
+    tag = f"rates_jacobian_{precision}_{wl.name}"
+    return {"zones_per_launch": nz, "launch_ms": t, "bytes_written": written,
+            "write_GBps": written / (t * 1e-3) / 1e9, "hbm_peak_GBps": 8000.0,
+            "hbm_frac": written / (t * 1e-3) / 8e12, "traffic": traffic_from_profiles(tag), "kernel": tag}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +342,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2, help="steps of the FP64 comparison run (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
+    ap.add_argument("--stream-steps", type=int, default=2,
+                    help="steps of the pinned-host streaming run, PCIe included (0: skip)")
+    ap.add_argument("--jacobian-launches", type=int, default=3,
+                    help="timed launches of the explicit Jacobian over one chunk (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run one device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -236,6 +375,10 @@ def main():
     value = units / t_step
     t_fwd, t_bwd, zl = run.launch_times()
     errors = None if args.no_errors else sampled_errors(inp, run.eta, run.chi, wl)
+    streaming = None
+    if args.stream_steps > 0:
+        print(f"[bench] streaming from pinned host memory: {args.stream_steps} steps", file=sys.stderr, flush=True)
+        streaming = streaming_leg(run, units, args.stream_steps, 1)
     del run
     torch.cuda.empty_cache()
 
@@ -260,6 +403,11 @@ def main():
         fp64 = {"value": units / t64, "ms_per_step": t64 * 1e3, "speedup_mixed_over_fp64": t64 / t_step,
                 "rel_err": e64}
 
+    jac = None
+    if args.jacobian_launches > 0:
+        print(f"[bench] explicit Jacobian: {args.jacobian_launches} launches", file=sys.stderr, flush=True)
+        jac = jacobian_leg(inp, wl, precision, args.jacobian_launches)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -274,6 +422,7 @@ def main():
                                f"{wl.rule} rule, {precision}, fwd+bwd, {wl.chunks} chunks, inputs resident in HBM",
                    "zones": wl.nzones, "ne": wl.ne, "nquad": wl.nquad, "precision": precision},
         "rel_err_vs_oracle": errors, "fp64": fp64, "roofline": roof, "cpu_baseline": cpu,
+        "streaming_pcie": streaming, "jacobian": jac,
     }
     print(json.dumps(line), flush=True)
 

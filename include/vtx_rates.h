@@ -118,6 +118,22 @@ int vtx_rates_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzone
                        const double* g_eta, const double* g_chi,
                        double* g_T, double* g_eta_e, double* g_f, void* hip_stream);
 
+/*
+ * Explicit Jacobian blocks with respect to f (the f-part of the Newton-Raphson Jacobian of
+ * the implicit ray-by-ray transport solve, Sect. 2.1). The outputs are affine in f, so the
+ * blocks depend on T and eta_e only:
+ *   jac[nz][3 species s][2 process p][4 output o][ne i][ne j] = d out_o^s(i) / d f_m^{s'}(j),
+ *   o = eta0, chi0, eta1, chi1 with m = o / 2; s' = s for p = 0 (scattering) and the pair
+ *   partner of s (nu_e <-> anti-nu_e, nu_x <-> nu_x) for p = 1 (pair). For nu_x both blocks act
+ *   on the same f and add. Entries, with the kernels completed as above:
+ *     p = 0: c0 w_j [Phi_in_0, Phi_in_0 - Phi_out_0, Phi_in_1, Phi_in_1 - Phi_out_1](i, j)
+ *     p = 1: c0 w_j [-Phi_p_0, Phi_a_0 - Phi_p_0, -Phi_p_1, Phi_a_1 - Phi_p_1](i, j)
+ *   A process left out of opts->processes gives zero blocks. Same precision rules as the
+ *   forward. jac (device memory, 192 ne^2 bytes per zone) is overwritten; T, eta_e as above.
+ */
+int vtx_rates_jacobian(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
+                       const double* T, const double* eta_e, double* jac, void* hip_stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* vtx_strerror(int code);
 

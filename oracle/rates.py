@@ -28,9 +28,15 @@ Steps, in the order the method takes them (FP64 throughout, complex-safe):
    (the J, H moments of the paper's Eq. 1; intensity normalisation with (2 pi hbar c)^3,
    Sect. 2.1). A consumer forms S0 = eta0 - chi0 f0 - 3 chi1 f1, S1 = eta1 - chi1 f0 - chi0 f1.
 Outputs eta[z][s][m][i], chi[z][s][m][i] in cm^-1.
+6. Explicit Jacobian blocks (``jacobian``): the outputs are affine in f, so d out/d f is the
+   coefficient of each f entry in step 5, block [s][p][o][i][j] for process p (scattering
+   against f of s, pair against f of the partner) and output o = eta0, chi0, eta1, chi1 against
+   f_{o//2}(j): the f-part of the Newton-Raphson Jacobian of the implicit solve (Sect. 2.1).
 
 Pins: tests/test_oracle_rates.py (vacuum and non-degenerate closed forms, equilibrium null
-test, continuous detailed balance by adaptive integration, linearity, couplings).
+test, continuous detailed balance by adaptive integration, linearity, couplings);
+tests/test_oracle_jacobian.py (Jacobian blocks against the contraction and the complex-step
+f-gradient).
 """
 import dataclasses
 import math
@@ -81,8 +87,10 @@ def nes_tasks(ne):
     return ii, jj
 
 
-def scattering_quadrature(eps, T, mu, opts):
-    """q[z, t, S, l] for tasks t = (i >= j) of ``nes_tasks``; S, l in {0, 1} (S index 0 = I)."""
+def scattering_quadrature(eps, T, mu, opts, absolute=False):
+    """q[z, t, S, l] for tasks t = (i >= j) of ``nes_tasks``; S, l in {0, 1} (S index 0 = I).
+    With ``absolute`` the angular weight enters as |H|: the sum of the absolute quadrature
+    terms, the scale against which the rounding of a cancelling (l = 1) sum is judged."""
     ii, jj = nes_tasks(eps.shape[0])
     ei = eps[ii][None, :]
     ej = eps[jj][None, :]
@@ -97,13 +105,14 @@ def scattering_quadrature(eps, T, mu, opts):
         row = []
         for l in (0, 1):
             H = h_nes(l, S, ei[..., None], ej[..., None], E)
+            H = np.abs(H) if absolute else H
             row.append(pref * np.sum(W * B * H, axis=-1))
         out.append(np.stack(row, axis=-1))
     return np.stack(out, axis=-2)  # [z, t, S, l]
 
 
-def pair_quadrature(eps, T, mu, opts):
-    """A[z, i, j, l] for all bin pairs."""
+def pair_quadrature(eps, T, mu, opts, absolute=False):
+    """A[z, i, j, l] for all bin pairs (``absolute``: |H|, as for the scattering quadrature)."""
     ne = eps.shape[0]
     ei = eps[:, None][None]
     ej = eps[None, :][None]
@@ -117,11 +126,12 @@ def pair_quadrature(eps, T, mu, opts):
     out = []
     for l in (0, 1):
         H = h_pair(l, 1, ei[..., None], ej[..., None], E)
+        H = np.abs(H) if absolute else H
         out.append(pref * np.sum(W * B * H, axis=-1))
     return np.stack(out, axis=-1).reshape(T.shape[0], ne, ne, 2)
 
 
-def zone_kernels(eps, T, eta_e, opts):
+def zone_kernels(eps, T, eta_e, opts, absolute=False):
     """S-split kernels after completion: dict of arrays [z, i, j, S, l] (S index 0 = I)."""
     eps = np.asarray(eps, dtype=float)
     T = np.asarray(T)
@@ -130,7 +140,7 @@ def zone_kernels(eps, T, eta_e, opts):
     nz = T.shape[0]
     out = {}
     if opts.processes & PROC_NES:
-        q = scattering_quadrature(eps, T, mu, opts)
+        q = scattering_quadrature(eps, T, mu, opts, absolute)
         ii, jj = nes_tasks(ne)
         full = np.zeros((nz, ne, ne, 2, 2), dtype=q.dtype)
         full[:, ii, jj] = q
@@ -142,7 +152,7 @@ def zone_kernels(eps, T, eta_e, opts):
         out["nes_out"] = phi_out
         out["nes_in"] = np.swapaxes(phi_out, 1, 2)
     if opts.processes & PROC_PAIR:
-        A = pair_quadrature(eps, T, mu, opts)
+        A = pair_quadrature(eps, T, mu, opts, absolute)
         phi_a = np.stack([A, np.swapaxes(A, 1, 2)], axis=-2)  # [z, i, j, S, l]
         prod = np.exp(-(eps[None, :, None] + eps[None, None, :]) / T[:, None, None])
         out["pair_a"] = phi_a
@@ -222,6 +232,57 @@ def contract_abs(kernels, w, f, opts):
             aeta[:, s, 1] += np.sum(pp[..., 1] * f1, axis=-1)
             achi[:, s, 1] += np.sum((pa[..., 1] + pp[..., 1]) * f1, axis=-1)
     return aeta, achi
+
+
+PARTNER_OF_PROCESS = ((0, 1, 2), physics.PARTNER)   # species whose f a block multiplies
+
+
+def jacobian_blocks(kernels, w, opts, absolute=False):
+    """Explicit Jacobian blocks jac[z, s, p, o, i, j] = d out_o^s(i) / d f_m^{s'}(j).
+
+    The outputs of step 5 are affine in f, so the derivative of each output with respect to
+    one f entry is that entry's coefficient in step 5: p = 0 (scattering, s' = s) and p = 1
+    (pair, s' = partner of s); o = eta0, chi0, eta1, chi1 with m = o // 2. These are the
+    f-blocks of the Newton-Raphson Jacobian of the implicit transport step (Sect. 2.1).
+    With ``absolute`` the entries are sums of |terms| instead (the error-floor scale).
+    """
+    k = {n: np.abs(v) for n, v in kernels.items()} if absolute else kernels
+    cw = physics.C0 * np.asarray(w, dtype=float)          # [j]
+    nz, ne = next(iter(k.values())).shape[:2]
+    dtype = np.result_type(*[v for v in k.values()])
+    jac = np.zeros((nz, 3, 2, 4, ne, ne), dtype=dtype)
+    sgn = 1.0 if absolute else -1.0
+    betas = physics.couplings(opts.sin2w)
+    for s in range(3):
+        b = betas[s]
+        if "nes_out" in k:
+            pin = _species(k["nes_in"], b) * cw[:, None]     # [z, i, j, l]
+            pout = _species(k["nes_out"], b) * cw[:, None]
+            jac[:, s, 0, 0] = pin[..., 0]
+            jac[:, s, 0, 1] = pin[..., 0] + sgn * pout[..., 0]
+            jac[:, s, 0, 2] = pin[..., 1]
+            jac[:, s, 0, 3] = pin[..., 1] + sgn * pout[..., 1]
+        if "pair_a" in k:
+            pa = _species(k["pair_a"], b) * cw[:, None]
+            pp = _species(k["pair_p"], b) * cw[:, None]
+            jac[:, s, 1, 0] = sgn * pp[..., 0]
+            jac[:, s, 1, 1] = pa[..., 0] + sgn * pp[..., 0]
+            jac[:, s, 1, 2] = sgn * pp[..., 1]
+            jac[:, s, 1, 3] = pa[..., 1] + sgn * pp[..., 1]
+    return jac
+
+
+def jacobian(eps, w, T, eta_e, opts=Options(), chunk=32, absolute=False):
+    """Jacobian blocks [z, 3, 2, 4, NE, NE] for zone states T[z], eta_e[z] (no f needed).
+    ``absolute``: every block entry as its sum of absolute terms, down to the quadrature
+    terms (|H| in the kernels), the error scale of one entry."""
+    T = np.asarray(T)
+    eta_e = np.asarray(eta_e)
+    out = []
+    for z0 in range(0, T.shape[0], chunk):
+        sl = slice(z0, z0 + chunk)
+        out.append(jacobian_blocks(zone_kernels(eps, T[sl], eta_e[sl], opts, absolute), w, opts, absolute))
+    return np.concatenate(out)
 
 
 def forward(eps, w, T, eta_e, f, opts=Options(), chunk=32):

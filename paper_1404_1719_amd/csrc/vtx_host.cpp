@@ -469,6 +469,19 @@ int vtx_rates_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzone
   return e == hipSuccess ? VTX_OK : VTX_EHIP;
 }
 
+int vtx_rates_jacobian(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
+                       const double* eta_e, double* jac, void* hip_stream) {
+  int rc = vtx::check_args(grid, opts, nzones);
+  if (rc != VTX_OK) return rc;
+  if (nzones == 0) return VTX_OK;
+  if (!T || !eta_e || !jac) return VTX_EINVAL;
+  vtx::DevPlan P;
+  rc = vtx::get_plan(grid, opts, &P);
+  if (rc != VTX_OK) return rc;
+  const hipError_t e = vtx::launch_jacobian(P, nzones, T, eta_e, jac, (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+
 const char* vtx_strerror(int code) {
   switch (code) {
     case VTX_OK: return "ok";

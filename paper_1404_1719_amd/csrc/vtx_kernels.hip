@@ -564,11 +564,68 @@ __device__ __forceinline__ int bin_parts(int ne) {
   return np < 1 ? 1 : (np > 4 ? 4 : np);
 }
 
-template <typename R>
+// Explicit Jacobian blocks of one zone, jac[s][p][o][i][j] (24 ne^2 doubles): the derivative
+// of output o (eta0, chi0, eta1, chi1) of species s in bin i with respect to f_{o/2}(j) of
+// species s (process p = 0, scattering) or of its pair partner (p = 1). The outputs are
+// affine in f, so each block is a completed kernel times c0 w_j, the f-independent part of
+// the Newton-Raphson Jacobian of the implicit transport step (Sect. 2.1). Lanes run bin
+// pairs (i, j) and write each of the 24 blocks with consecutive j: every store of a wave is
+// contiguous.
+__device__ void zone_jacobian(const DevPlan& P, const Zone& Z, const double* smem, double* __restrict__ jac) {
+  const int ne = P.ne, n2 = ne * ne;
+  const int off_q = 6 * ne, off_p = off_q + 4 * P.ntn, off_d = off_p + 2 * P.ntp;
+  const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
+  double* out = jac + Z.z * (int64_t)(24 * n2);
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+    const int i = e / ne, j = e - i * ne;
+    const double cw = P.c0w[j];
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0, cin = 0.0, cout = 0.0;
+    if (do_nes) {
+      const double* q = smem + off_q + 4 * (i >= j ? tri(i, j) : tri(j, i));
+      q0 = q[0];
+      q1 = q[1];
+      q2 = q[2];
+      q3 = q[3];
+      const double dcw = cw * smem[off_d + e];
+      cin = (i > j) ? dcw : cw;
+      cout = (i < j) ? dcw : cw;
+    }
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, pf = 0.0;
+    if (do_pair) {
+      const double* aij = smem + off_p + 2 * e;
+      const double* aji = smem + off_p + 2 * (j * ne + i);
+      a0 = aij[0];
+      a1 = aij[1];
+      b0 = aji[0];
+      b1 = aji[1];
+      pf = smem[off_d + n2 + e];
+    }
+    const double cwp = cw * pf, cwa = cw * (1.0 - pf);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
+      const double k0 = bI * q0 + bII * q2, k1 = bI * q1 + bII * q3;
+      const double ka0 = bI * a0 + bII * b0, ka1 = bI * a1 + bII * b1;
+      double* o = out + s * 8 * n2 + e;
+      o[0] = cin * k0;
+      o[n2] = (cin - cout) * k0;
+      o[2 * n2] = cin * k1;
+      o[3 * n2] = (cin - cout) * k1;
+      o[4 * n2] = -cwp * ka0;
+      o[5 * n2] = cwa * ka0;
+      o[6 * n2] = -cwp * ka1;
+      o[7 * n2] = cwa * ka1;
+    }
+  }
+}
+
+// Forward of one zone: task values into LDS, then either the contraction with f into eta, chi
+// or (JAC) the explicit Jacobian blocks, which need no f.
+template <typename R, bool JAC>
 __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* smem, int64_t z, int selm,
                              const double* __restrict__ Tz, const double* __restrict__ etaz,
                              const double* __restrict__ f, double* __restrict__ eta_out,
-                             double* __restrict__ chi_out) {
+                             double* __restrict__ chi_out, double* __restrict__ jac) {
   const int ne = P.ne;
   const int off_q = 6 * ne, off_p = off_q + 4 * P.ntn, off_d = off_p + 2 * P.ntp, n2 = ne * ne;
   const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
@@ -578,7 +635,8 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   __syncthreads();
   const Zone& Z = *zs;
   if (!Z.valid) return;   // uniform: every lane reads the same zone state
-  for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
+  if (!JAC)
+    for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
   stage_factors(P, Z, smem + off_d);
   const Units U = task_units(ntn, ntp);
   const int lane = threadIdx.x & 63;
@@ -610,6 +668,10 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
     }
   }
   __syncthreads();
+  if (JAC) {
+    zone_jacobian(P, Z, smem, jac);
+    return;
+  }
   // completion, species combination and contraction: one lane per (part, bin i) runs all
   // three species over a part of j, so each (i, j) pair's task values, detailed-balance
   // factors and weights are read and combined once; the parts are added in order
@@ -697,30 +759,28 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
 
 // Dense pass: workgroup b takes zone b (if selected). Occupancy targets: four waves per SIMD
 // for FP32 (at most 128 VGPRs), three for FP64.
-template <typename R>
+template <typename R, bool JAC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 3)))
-void rates_forward_kernel(DevPlan P, int64_t nz, int selm,
-                                                                  const double* __restrict__ Tz,
-                                                                  const double* __restrict__ etaz,
-                                                                  const double* __restrict__ f,
-                                                                  double* __restrict__ eta_out,
-                                                                  double* __restrict__ chi_out) {
+void rates_forward_kernel(DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz,
+                          const double* __restrict__ etaz, const double* __restrict__ f,
+                          double* __restrict__ eta_out, double* __restrict__ chi_out, double* __restrict__ jac) {
   __shared__ R tab[kTabLen];
   __shared__ Zone zs;
   extern __shared__ double smem[];
   stage_tab<R>(P, tab);
   const int64_t z = blockIdx.x;
-  zone_forward<R>(P, tab, &zs, smem, z < nz ? z : -1, selm, Tz, etaz, f, eta_out, chi_out);
+  zone_forward<R, JAC>(P, tab, &zs, smem, z < nz ? z : -1, selm, Tz, etaz, f, eta_out, chi_out, jac);
 }
 
 // Sparse FP64 pass: workgroups scan windows of blockDim zones and run the zones with
 // |eta_e| above the threshold, one at a time. The scan order does not change any result.
-__global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_t nz,
-                                                                  const double* __restrict__ Tz,
+template <bool JAC>
+__global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_t nz, const double* __restrict__ Tz,
                                                                   const double* __restrict__ etaz,
                                                                   const double* __restrict__ f,
                                                                   double* __restrict__ eta_out,
-                                                                  double* __restrict__ chi_out) {
+                                                                  double* __restrict__ chi_out,
+                                                                  double* __restrict__ jac) {
   __shared__ double tab[kTabLen];
   __shared__ Zone zs;
   __shared__ int list[kBlock];
@@ -735,7 +795,7 @@ __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_
     __syncthreads();
     const int n = count;
     for (int c = 0; c < n; ++c) {
-      zone_forward<double>(P, tab, &zs, smem, base + list[c], kSelAll, Tz, etaz, f, eta_out, chi_out);
+      zone_forward<double, JAC>(P, tab, &zs, smem, base + list[c], kSelAll, Tz, etaz, f, eta_out, chi_out, jac);
       __syncthreads();
     }
     __syncthreads();   // every lane has read count before the next window resets it
@@ -1331,31 +1391,34 @@ unsigned sparse_grid(int64_t nz) {
   return (unsigned)(windows < 1024 ? windows : 1024);
 }
 
-}  // namespace
+// Zones per launch: one workgroup per zone, and a dispatch holds fewer than 2^32 work-items.
+// Larger calls are issued as consecutive slices on the same stream.
+constexpr int64_t kSliceZones = int64_t(1) << 22;
 
-hipError_t launch_forward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
-                          double* eta, double* chi, hipStream_t s) {
-  if (nz <= 0) return hipSuccess;
+hipError_t forward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                         double* eta, double* chi, double* jac, hipStream_t s) {
   const size_t lds = zone_lds_fwd(P);
   const dim3 grid((unsigned)nz), block(kBlock);
   hipError_t e;
   if (P.precision == VTX_MIXED) {
-    if ((e = allow_lds(rates_forward_kernel<float>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_forward_kernel<float>, grid, block, lds, s, P, nz, kSelBulk, T, eta_e, f, eta, chi);
+    auto bulk = jac ? rates_forward_kernel<float, true> : rates_forward_kernel<float, false>;
+    auto sparse = jac ? rates_forward_sparse<true> : rates_forward_sparse<false>;
+    if ((e = allow_lds(bulk, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(bulk, grid, block, lds, s, P, nz, kSelBulk, T, eta_e, f, eta, chi, jac);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = allow_lds(rates_forward_sparse, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_forward_sparse, dim3(sparse_grid(nz)), block, lds, s, P, nz, T, eta_e, f, eta, chi);
+    if ((e = allow_lds(sparse, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(sparse, dim3(sparse_grid(nz)), block, lds, s, P, nz, T, eta_e, f, eta, chi, jac);
   } else {
-    if ((e = allow_lds(rates_forward_kernel<double>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_forward_kernel<double>, grid, block, lds, s, P, nz, kSelAll, T, eta_e, f, eta, chi);
+    auto dense = jac ? rates_forward_kernel<double, true> : rates_forward_kernel<double, false>;
+    if ((e = allow_lds(dense, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(dense, grid, block, lds, s, P, nz, kSelAll, T, eta_e, f, eta, chi, jac);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
-                           const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
-                           hipStream_t s) {
-  if (nz <= 0) return hipSuccess;
+hipError_t backward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                          const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
+                          hipStream_t s) {
   const size_t lds32 = zone_lds_bwd(P, sizeof(float)), lds64 = zone_lds_bwd(P, sizeof(double));
   const dim3 grid((unsigned)nz), block(kBlock);
   hipError_t e;
@@ -1373,6 +1436,44 @@ hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const 
                        g_chi, g_T, g_eta_e, g_f);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_forward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                          double* eta, double* chi, hipStream_t s) {
+  const int64_t zs = 6 * P.ne;
+  for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
+    const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
+    const hipError_t e = forward_slice(P, n, T + z0, eta_e + z0, f + z0 * zs, eta + z0 * zs, chi + z0 * zs,
+                                       nullptr, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_jacobian(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, double* jac,
+                           hipStream_t s) {
+  const int64_t js = 24 * P.ne * P.ne;
+  for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
+    const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
+    const hipError_t e = forward_slice(P, n, T + z0, eta_e + z0, nullptr, nullptr, nullptr, jac + z0 * js, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                           const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
+                           hipStream_t s) {
+  const int64_t zs = 6 * P.ne;
+  for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
+    const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
+    const hipError_t e = backward_slice(P, n, T + z0, eta_e + z0, f + z0 * zs, g_eta + z0 * zs, g_chi + z0 * zs,
+                                        g_T + z0, g_eta_e + z0, g_f + z0 * zs, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace vtx

@@ -52,6 +52,8 @@ def library():
     lib.vtx_rates_backward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64,
                                        vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.vtx_rates_backward.restype = ctypes.c_int
+    lib.vtx_rates_jacobian.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp]
+    lib.vtx_rates_jacobian.restype = ctypes.c_int
     lib.vtx_strerror.argtypes = [ctypes.c_int]
     lib.vtx_strerror.restype = ctypes.c_char_p
     lib.vtx_abi_version.argtypes = []
@@ -161,6 +163,20 @@ def backward(grid: GridHandle, opts: Opts, T, eta_e, f, g_eta, g_chi, g_T=None, 
         _stream_handle(stream))
     _check(rc, "vtx_rates_backward")
     return g_T, g_eta_e, g_f
+
+
+def jacobian(grid: GridHandle, opts: Opts, T, eta_e, jac=None, stream=None):
+    """Explicit blocks jac[nz, 3, 2, 4, ne, ne] = d(eta, chi)/df (layout in include/vtx_rates.h)."""
+    import torch
+    nz = T.shape[0]
+    shp = (nz, 3, 2, 4, grid.ne, grid.ne)
+    if jac is None:
+        jac = torch.empty(shp, dtype=torch.float64, device=T.device)
+    rc = library().vtx_rates_jacobian(ctypes.byref(grid.c), ctypes.byref(opts), nz, _dev_ptr(T, "T", (nz,)),
+                                      _dev_ptr(eta_e, "eta_e", (nz,)), _dev_ptr(jac, "jac", shp),
+                                      _stream_handle(stream))
+    _check(rc, "vtx_rates_jacobian")
+    return jac
 
 
 def gauss_rule(kind: int, n: int):

@@ -21,7 +21,8 @@ lib = vtx.library()
 
 def test_exports_every_declared_symbol():
     names = vtx.declared_functions()
-    assert {"vtx_rates_forward", "vtx_rates_backward", "vtx_strerror", "vtx_abi_version"} <= set(names)
+    assert {"vtx_rates_forward", "vtx_rates_backward", "vtx_rates_jacobian", "vtx_strerror",
+            "vtx_abi_version"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
 
@@ -51,6 +52,11 @@ def _call_bwd(grid, opts, nz, ptr=1):
     return lib.vtx_rates_backward(ctypes.byref(grid.c), ctypes.byref(opts), nz, p, p, p, p, p, p, p, p, None)
 
 
+def _call_jac(grid, opts, nz, ptr=1):
+    p = ctypes.c_void_p(ptr) if ptr else None
+    return lib.vtx_rates_jacobian(ctypes.byref(grid.c), ctypes.byref(opts), nz, p, p, p, None)
+
+
 def test_invalid_arguments():
     eps, w = synth.energy_grid(21, 2.0, 380.0)
     g = vtx.GridHandle(eps, w)
@@ -60,6 +66,9 @@ def test_invalid_arguments():
     assert _call_fwd(g, o, -1) == vtx.VTX_EINVAL
     assert _call_fwd(g, o, 4, ptr=0) == vtx.VTX_EINVAL         # null device pointers
     assert _call_bwd(g, o, 4, ptr=0) == vtx.VTX_EINVAL
+    assert _call_jac(g, o, 4, ptr=0) == vtx.VTX_EINVAL
+    assert _call_jac(g, o, -1) == vtx.VTX_EINVAL
+    assert _call_jac(g, o, 0) == vtx.VTX_OK
     for field, bad in [("nquad", 6), ("nquad", 50), ("nquad", 68), ("rule", 2), ("precision", 3),
                        ("processes", 0), ("processes", 4), ("sin2w", float("nan"))]:
         ob = vtx.make_opts()
@@ -85,6 +94,7 @@ def test_no_device_is_reported():
     eps, w = synth.energy_grid(12, 2.0, 300.0)
     assert _call_fwd(vtx.GridHandle(eps, w), vtx.make_opts(), 4) == vtx.VTX_EDEVICE
     assert _call_bwd(vtx.GridHandle(eps, w), vtx.make_opts(), 4) == vtx.VTX_EDEVICE
+    assert _call_jac(vtx.GridHandle(eps, w), vtx.make_opts(), 4) == vtx.VTX_EDEVICE
 
 
 def test_fault_injection_reports_hip_error(monkeypatch):

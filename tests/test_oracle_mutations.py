@@ -73,3 +73,29 @@ def test_unswapped_antineutrino_coupling(monkeypatch):
     pa_nu = b[0][0] * k["pair_a"][..., 0, :] + b[0][1] * k["pair_a"][..., 1, :]
     pa_bar = b[1][0] * k["pair_a"][..., 0, :] + b[1][1] * k["pair_a"][..., 1, :]
     assert not np.allclose(pa_bar, np.swapaxes(pa_nu, 1, 2), rtol=1e-6, atol=0)
+
+
+def test_transposed_pair_jacobian_block(monkeypatch):
+    import test_oracle_jacobian as pins_jac
+    orig = rates.jacobian_blocks
+
+    def bad(kernels, w, opts, absolute=False):
+        j = orig(kernels, w, opts, absolute)
+        j[:, :, 1] = np.swapaxes(j[:, :, 1], -1, -2)
+        return j
+    monkeypatch.setattr(rates, "jacobian_blocks", bad)
+    with pytest.raises(AssertionError):
+        pins_jac.test_jacobian_reproduces_contraction("medium", 48, rule.RULE_PANEL)
+
+
+def test_production_sign_in_jacobian(monkeypatch):
+    import test_oracle_jacobian as pins_jac
+    orig = rates.jacobian_blocks
+
+    def bad(kernels, w, opts, absolute=False):
+        j = orig(kernels, w, opts, absolute)
+        j[:, :, 1, 2] *= -1.0
+        return j
+    monkeypatch.setattr(rates, "jacobian_blocks", bad)
+    with pytest.raises(AssertionError):
+        pins_jac.test_jacobian_transpose_is_f_gradient()
