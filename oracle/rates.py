@@ -5,6 +5,9 @@ Steps, in the order the method takes them (FP64 throughout, complex-safe):
 1. Scattering quadrature, tasks eps_i >= eps_j (down-scatter and diagonal):
      q_{l,S}(i,j) = G_F^2/(pi eps_i eps_j) sum_k W_k F(E_k) [1 - F(E_k + eps_i - eps_j)] H^{N,S}_l(eps_i, eps_j, E_k)
    with F(E) = 1/(exp((E - mu_e)/T) + 1) and the rule of ``oracle.rule``.
+   Optional, scattering on positrons (process bit PROC_NPS): the same quadrature with the
+   positron occupation Fbar(E) = F(E; -mu_e) in place of F, i.e. q evaluated at -mu_e, and
+   the couplings of the antiparticle target, C_A -> -C_A, which swaps beta_I and beta_II.
 2. Scattering completion (detailed balance, in/out symmetry), no quadrature:
      Phi_out(i,j) = q(i,j) for i >= j,  Phi_out(i,j) = exp(-(eps_j - eps_i)/T) q(j,i) for j > i,
      Phi_in(i,j) = Phi_out(j,i).
@@ -49,6 +52,7 @@ from .rule import RULE_PANEL, nes_nodes, pair_nodes
 
 PROC_NES = 1
 PROC_PAIR = 2
+PROC_NPS = 4     # neutrino-positron scattering
 
 
 @dataclasses.dataclass(frozen=True)
@@ -139,18 +143,19 @@ def zone_kernels(eps, T, eta_e, opts, absolute=False):
     ne = eps.shape[0]
     nz = T.shape[0]
     out = {}
-    if opts.processes & PROC_NES:
-        q = scattering_quadrature(eps, T, mu, opts, absolute)
-        ii, jj = nes_tasks(ne)
-        full = np.zeros((nz, ne, ne, 2, 2), dtype=q.dtype)
-        full[:, ii, jj] = q
-        # up-scatter j > i from the down-scatter task (j, i): exp(-(eps_j - eps_i)/T)
-        up = np.exp(-(eps[None, None, :] - eps[None, :, None]) / T[:, None, None])  # [z, i, j]
-        upper = np.triu(np.ones((ne, ne), dtype=bool), 1)
-        trans = np.swapaxes(full, 1, 2)
-        phi_out = np.where(upper[None, :, :, None, None], up[..., None, None] * trans, full)
-        out["nes_out"] = phi_out
-        out["nes_in"] = np.swapaxes(phi_out, 1, 2)
+    for bit, name, m in ((PROC_NES, "nes", mu), (PROC_NPS, "nps", -mu)):
+        if opts.processes & bit:
+            q = scattering_quadrature(eps, T, m, opts, absolute)
+            ii, jj = nes_tasks(ne)
+            full = np.zeros((nz, ne, ne, 2, 2), dtype=q.dtype)
+            full[:, ii, jj] = q
+            # up-scatter j > i from the down-scatter task (j, i): exp(-(eps_j - eps_i)/T)
+            up = np.exp(-(eps[None, None, :] - eps[None, :, None]) / T[:, None, None])  # [z, i, j]
+            upper = np.triu(np.ones((ne, ne), dtype=bool), 1)
+            trans = np.swapaxes(full, 1, 2)
+            phi_out = np.where(upper[None, :, :, None, None], up[..., None, None] * trans, full)
+            out[name + "_out"] = phi_out
+            out[name + "_in"] = np.swapaxes(phi_out, 1, 2)
     if opts.processes & PROC_PAIR:
         A = pair_quadrature(eps, T, mu, opts, absolute)
         phi_a = np.stack([A, np.swapaxes(A, 1, 2)], axis=-2)  # [z, i, j, S, l]
@@ -164,6 +169,23 @@ def _species(kern, beta):
     return beta[0] * kern[..., 0, :] + beta[1] * kern[..., 1, :]   # [z, i, j, l]
 
 
+def scattering_kernels(kernels, b):
+    """(Phi_in, Phi_out) [z, i, j, l] of one species with couplings b = (beta_I, beta_II),
+    summed over the scattering targets present: electrons with b, positrons with b swapped."""
+    pin = pout = 0.0
+    if "nes_out" in kernels:
+        pin = pin + _species(kernels["nes_in"], b)
+        pout = pout + _species(kernels["nes_out"], b)
+    if "nps_out" in kernels:
+        pin = pin + _species(kernels["nps_in"], (b[1], b[0]))
+        pout = pout + _species(kernels["nps_out"], (b[1], b[0]))
+    return pin, pout
+
+
+def has_scattering(kernels):
+    return "nes_out" in kernels or "nps_out" in kernels
+
+
 def contract(kernels, w, f, opts):
     """eta, chi [z, s, m, i] from completed kernels and f [z, s, m, j]."""
     w = np.asarray(w, dtype=float)
@@ -175,9 +197,8 @@ def contract(kernels, w, f, opts):
     betas = physics.couplings(opts.sin2w)
     for s in range(3):
         b = betas[s]
-        if "nes_out" in kernels:
-            pin = _species(kernels["nes_in"], b)    # [z, i, j, l]
-            pout = _species(kernels["nes_out"], b)
+        if has_scattering(kernels):
+            pin, pout = scattering_kernels(kernels, b)    # [z, i, j, l]
             f0 = f[:, s, 0, None, :] * cw
             g0 = (1.0 - f[:, s, 0, None, :]) * cw
             f1 = f[:, s, 1, None, :] * cw
@@ -210,9 +231,8 @@ def contract_abs(kernels, w, f, opts):
     betas = physics.couplings(opts.sin2w)
     for s in range(3):
         b = betas[s]
-        if "nes_out" in ak:
-            pin = _species(ak["nes_in"], b)
-            pout = _species(ak["nes_out"], b)
+        if has_scattering(ak):
+            pin, pout = scattering_kernels(ak, b)
             f0 = f[:, s, 0, None, :] * cw
             g0 = np.abs(1.0 - f[:, s, 0, None, :]) * cw
             f1 = np.abs(f[:, s, 1, None, :]) * cw
@@ -255,9 +275,10 @@ def jacobian_blocks(kernels, w, opts, absolute=False):
     betas = physics.couplings(opts.sin2w)
     for s in range(3):
         b = betas[s]
-        if "nes_out" in k:
-            pin = _species(k["nes_in"], b) * cw[:, None]     # [z, i, j, l]
-            pout = _species(k["nes_out"], b) * cw[:, None]
+        if has_scattering(k):
+            pin, pout = scattering_kernels(k, b)
+            pin = pin * cw[:, None]     # [z, i, j, l]
+            pout = pout * cw[:, None]
             jac[:, s, 0, 0] = pin[..., 0]
             jac[:, s, 0, 1] = pin[..., 0] + sgn * pout[..., 0]
             jac[:, s, 0, 2] = pin[..., 1]

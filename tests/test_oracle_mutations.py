@@ -99,3 +99,31 @@ def test_production_sign_in_jacobian(monkeypatch):
     monkeypatch.setattr(rates, "jacobian_blocks", bad)
     with pytest.raises(AssertionError):
         pins_jac.test_jacobian_transpose_is_f_gradient()
+
+
+def test_unswapped_positron_couplings(monkeypatch):
+    import test_oracle_positron as pins_pos
+
+    def bad(kernels, b):
+        pin = pout = 0.0
+        for name in ("nes", "nps"):
+            if name + "_out" in kernels:
+                pin = pin + rates._species(kernels[name + "_in"], b)
+                pout = pout + rates._species(kernels[name + "_out"], b)
+        return pin, pout
+    monkeypatch.setattr(rates, "scattering_kernels", bad)
+    with pytest.raises(AssertionError):
+        pins_pos.test_nondegenerate_positron_rate()
+
+
+def test_positron_scattering_with_electron_potential(monkeypatch):
+    import test_oracle_positron as pins_pos
+    orig = rates.scattering_quadrature
+    calls = []
+
+    def bad(eps, T, mu, opts, absolute=False):
+        calls.append(1)
+        return orig(eps, T, np.abs(mu), opts, absolute)     # positron tasks at +mu_e
+    monkeypatch.setattr(rates, "scattering_quadrature", bad)
+    with pytest.raises(AssertionError):
+        pins_pos.test_nondegenerate_positron_rate()

@@ -116,7 +116,7 @@ def test_equilibrium_null():
     f0(partner) = FD(-mu_nu) likewise (detailed balance of the discrete kernels)."""
     inp = synth.make_inputs("medium", nzones=3)
     eps, w = inp.eps, inp.w
-    for proc in (rates.PROC_NES, rates.PROC_PAIR):
+    for proc in (rates.PROC_NES, rates.PROC_PAIR, rates.PROC_NPS, 7):
         opts = rates.Options(nquad=48, processes=proc)
         f = np.zeros((3, 3, 2, eps.shape[0]))
         for z in range(3):
