@@ -124,13 +124,13 @@ def sampled_errors(inp, eta, chi, wl, count=6):
 class Runner:
     """Device-resident buffers of one workload and the chunked two-stream step."""
 
-    def __init__(self, inp, wl, precision, chunks):
+    def __init__(self, inp, wl, precision, chunks, processes=3):
         import torch
         from paper_1404_1719_amd import vtx
         self.torch, self.vtx = torch, vtx
         dev = torch.device("cuda:0")
         self.grid = vtx.GridHandle(inp.eps, inp.w)
-        self.opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+        self.opts = vtx.make_opts(precision, wl.nquad, wl.rule, processes)
         self.nz, self.ne = inp.T.shape[0], wl.ne
         self.T = torch.from_numpy(inp.T).to(dev)
         self.E = torch.from_numpy(inp.eta_e).to(dev)
@@ -377,6 +377,8 @@ def main():
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--stream-steps", type=int, default=2,
                     help="steps of the pinned-host streaming run, PCIe included (0: skip)")
+    ap.add_argument("--positron-steps", type=int, default=2,
+                    help="steps of the run with neutrino-positron scattering added (0: skip)")
     ap.add_argument("--jacobian-launches", type=int, default=3,
                     help="timed launches of the explicit Jacobian over one chunk (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -436,6 +438,18 @@ def main():
         fp64 = {"value": units / t64, "ms_per_step": t64 * 1e3, "speedup_mixed_over_fp64": t64 / t_step,
                 "rel_err": e64}
 
+    positron = None
+    if args.positron_steps > 0:
+        print(f"[bench] with neutrino-positron scattering: {args.positron_steps} steps", file=sys.stderr, flush=True)
+        runp = Runner(inp, wl, precision, wl.chunks, processes=7)
+        tp = runp.timed(args.positron_steps, 1)
+        pf, pb, _ = runp.launch_times()
+        positron = {"value": units / tp, "unit": "zone*(eps,eps')/s", "ms_per_step": tp * 1e3,
+                    "fwd_launch_ms": pf, "bwd_launch_ms": pb,
+                    "note": "all three processes (nu-e-, nu-e+ scattering, pair), same units"}
+        del runp
+        torch.cuda.empty_cache()
+
     jac = None
     if args.jacobian_launches > 0:
         print(f"[bench] explicit Jacobian: {args.jacobian_launches} launches", file=sys.stderr, flush=True)
@@ -455,7 +469,7 @@ def main():
                                f"{wl.rule} rule, {precision}, fwd+bwd, {wl.chunks} chunks, inputs resident in HBM",
                    "zones": wl.nzones, "ne": wl.ne, "nquad": wl.nquad, "precision": precision},
         "rel_err_vs_oracle": errors, "fp64": fp64, "roofline": roof, "cpu_baseline": cpu,
-        "streaming_pcie": streaming, "jacobian": jac,
+        "streaming_pcie": streaming, "jacobian": jac, "with_positron_scattering": positron,
     }
     print(json.dumps(line), flush=True)
 

@@ -78,7 +78,12 @@ enum vtx_precision {
 
 enum vtx_rule { VTX_RULE_LAGUERRE = 0, VTX_RULE_PANEL = 1 };
 
-enum vtx_process { VTX_NES = 1, VTX_PAIR = 2 };
+/* Processes: neutrino-electron scattering, pair annihilation/production, and (optional)
+ * neutrino-positron scattering: the scattering kernels with the positron occupation
+ * Fbar(E) = F(E; -mu_e) and the antiparticle-target couplings (C_A -> -C_A, which swaps
+ * beta_I and beta_II); its Phi_in, Phi_out add to the electron ones in eta, chi and in the
+ * scattering Jacobian block. */
+enum vtx_process { VTX_NES = 1, VTX_PAIR = 2, VTX_NPS = 4 };
 
 typedef struct {
   int32_t ne;          /* number of energy bins, 1..32 */
@@ -90,7 +95,7 @@ typedef struct {
   int32_t precision;   /* vtx_precision */
   int32_t nquad;       /* nodes per kernel integral: multiple of 4 in [8, 64] */
   int32_t rule;        /* vtx_rule */
-  uint32_t processes;  /* bitmask of vtx_process, nonzero */
+  uint32_t processes;  /* bitmask of vtx_process, nonzero (default VTX_NES | VTX_PAIR) */
   double sin2w;        /* weak mixing angle sin^2(theta_W), default 0.2312 */
   double eta_fp64;     /* mixed precision: zones with |eta_e| > eta_fp64 run in FP64 (default 64) */
 } vtx_opts;
@@ -127,6 +132,7 @@ int vtx_rates_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzone
  *   partner of s (nu_e <-> anti-nu_e, nu_x <-> nu_x) for p = 1 (pair). For nu_x both blocks act
  *   on the same f and add. Entries, with the kernels completed as above:
  *     p = 0: c0 w_j [Phi_in_0, Phi_in_0 - Phi_out_0, Phi_in_1, Phi_in_1 - Phi_out_1](i, j)
+ *            (scattering on electrons, plus on positrons with VTX_NPS)
  *     p = 1: c0 w_j [-Phi_p_0, Phi_a_0 - Phi_p_0, -Phi_p_1, Phi_a_1 - Phi_p_1](i, j)
  *   A process left out of opts->processes gives zero blocks. Same precision rules as the
  *   forward. jac (device memory, 192 ne^2 bytes per zone) is overwritten; T, eta_e as above.

@@ -380,7 +380,7 @@ int check_args(const vtx_grid* g, const vtx_opts* o, int64_t nz) {
   if (o->precision != VTX_FP64 && o->precision != VTX_MIXED) return VTX_EINVAL;
   if (o->nquad < 8 || o->nquad > kMaxNquad || (o->nquad % 4) != 0) return VTX_EINVAL;
   if (o->rule != VTX_RULE_LAGUERRE && o->rule != VTX_RULE_PANEL) return VTX_EINVAL;
-  if (o->processes == 0 || (o->processes & ~3u) != 0) return VTX_EINVAL;
+  if (o->processes == 0 || (o->processes & ~7u) != 0) return VTX_EINVAL;
   if (!std::isfinite(o->sin2w) || !std::isfinite(o->eta_fp64)) return VTX_EINVAL;
   if (nz > 0x7fffffffLL) return VTX_EINVAL;
   return VTX_OK;

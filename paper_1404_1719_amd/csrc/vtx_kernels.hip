@@ -84,7 +84,9 @@ __device__ __forceinline__ Tri pick4(int g, const Tri& a, const Tri& b, const Tr
   return sel(g == 0, a, sel(g == 1, b, sel(g == 2, c, d)));
 }
 
-// Per-zone state shared by the lanes of a workgroup.
+// Per-zone state shared by the lanes of a workgroup. A workgroup holds two: the zone, and its
+// mirror (eta_e, mu_e negated) under which the scattering tasks become scattering on
+// positrons, whose occupation is F(E; -mu_e).
 struct Zone {
   double T, eta, invT, mu;
   int64_t z;   // zone index, or -1 for an empty slot
@@ -510,7 +512,7 @@ __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const
 constexpr int kSelAll = 0, kSelBulk = 1;
 
 __device__ void stage_zone_state(const DevPlan& P, int64_t z, int selm, const double* Tz, const double* etaz,
-                                 Zone* zs) {
+                                 Zone* zs) {   // zs[0]: the zone, zs[1]: its mirror
   if (threadIdx.x == 0) {
     Zone Z;
     Z.z = z;
@@ -520,9 +522,60 @@ __device__ void stage_zone_state(const DevPlan& P, int64_t z, int selm, const do
     if (selm == kSelBulk && fabs(Z.eta) > P.eta_fp64) Z.valid = 0;
     Z.invT = 1.0 / Z.T;
     Z.mu = Z.eta * Z.T;
+    Zone M = Z;
+    M.eta = -Z.eta;
+    M.mu = -Z.mu;
     Z.k = 0;
-    for (int j = 0; j < P.ne; ++j) Z.k += P.eps[j] < Z.mu;
-    *zs = Z;
+    M.k = 0;
+    for (int j = 0; j < P.ne; ++j) {
+      Z.k += P.eps[j] < Z.mu;
+      M.k += P.eps[j] < M.mu;
+    }
+    zs[0] = Z;
+    zs[1] = M;
+  }
+}
+
+// LDS layout of a zone's task values (doubles), after `base` values of f (and gradients):
+// scattering [4 ntn] | scattering on positrons [4 ntn, kernels built with NPS] | pair [2 ntp,
+// slot of (i, j) at i ne + j] | detailed-balance factors [2 ne^2] | the rest.
+//
+// NPS (neutrino-positron scattering) is a template parameter of the kernels, chosen by the
+// host from the process mask: kernels built without it carry none of its code, so the
+// default processes run the smallest code.
+struct Lay {
+  int q, m, p, d;
+};
+template <bool NPS>
+__device__ __forceinline__ Lay layout(const DevPlan& P, int base) {
+  Lay L;
+  L.q = base;
+  L.m = L.q + 4 * P.ntn;
+  L.p = L.m + (NPS ? 4 * P.ntn : 0);
+  L.d = L.p + 2 * P.ntp;
+  return L;
+}
+
+// Scattering kernel components of bin pair (i, j), electron and positron targets together in
+// the electron-target coupling labels: the positron components (S, l) carry the couplings of
+// (S', l), S' the other S (C_A -> -C_A), so they add to the other S. v[0..3] = (I,0), (I,1),
+// (II,0), (II,1) of the down-scatter task tri(max, min).
+__device__ __forceinline__ void scattering_values(const double* smem, const Lay& L, bool nes, bool nps, int tq,
+                                                  double v[4]) {
+  v[0] = v[1] = v[2] = v[3] = 0.0;
+  if (nes) {
+    const double* q = smem + L.q + tq;
+    v[0] = q[0];
+    v[1] = q[1];
+    v[2] = q[2];
+    v[3] = q[3];
+  }
+  if (nps) {
+    const double* m = smem + L.m + tq;
+    v[0] += m[2];
+    v[1] += m[3];
+    v[2] += m[0];
+    v[3] += m[1];
   }
 }
 
@@ -541,17 +594,19 @@ __device__ void stage_factors(const DevPlan& P, const Zone& Z, double* s_d) {
   }
 }
 
-// Task units: units 0 .. nN-1 hold 64 scattering tasks each, the rest 64 pair tasks, in the
-// zone's task order (tasks whose groups take the same node-loop variants sit together). Wave w
-// of workgroup b takes units (w + b) mod W, + W, ...; the rotation spreads the wave that
-// holds one unit fewer over the SIMDs.
+// Task units: units 0 .. nN-1 hold 64 scattering tasks each, the next nM 64 positron
+// scattering tasks, the rest 64 pair tasks, each in its zone's task order (tasks whose groups
+// take the same node-loop variants sit together). Wave w of workgroup b takes units
+// (w + b) mod W, + W, ...; the rotation spreads the wave that holds one unit fewer over the
+// SIMDs.
 struct Units {
-  int nN, nU, first, step;
+  int nN, nM, nU, first, step;
 };
-__device__ __forceinline__ Units task_units(int ntn, int ntp) {
+__device__ __forceinline__ Units task_units(int ntn, int ntm, int ntp) {
   Units U;
   U.nN = (ntn + 63) >> 6;
-  U.nU = U.nN + ((ntp + 63) >> 6);
+  U.nM = (ntm + 63) >> 6;
+  U.nU = U.nN + U.nM + ((ntp + 63) >> 6);
   U.step = blockDim.x >> 6;
   U.first = __builtin_amdgcn_readfirstlane((int)(((threadIdx.x >> 6) + blockIdx.x) % U.step));
   return U;
@@ -571,34 +626,30 @@ __device__ __forceinline__ int bin_parts(int ne) {
 // the Newton-Raphson Jacobian of the implicit transport step (Sect. 2.1). Lanes run bin
 // pairs (i, j) and write each of the 24 blocks with consecutive j: every store of a wave is
 // contiguous.
+template <bool NPS>
 __device__ void zone_jacobian(const DevPlan& P, const Zone& Z, const double* smem, double* __restrict__ jac) {
   const int ne = P.ne, n2 = ne * ne;
-  const int off_q = 6 * ne, off_p = off_q + 4 * P.ntn, off_d = off_p + 2 * P.ntp;
-  const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
+  const Lay L = layout<NPS>(P, 6 * ne);
+  const bool do_nes = P.processes & VTX_NES, do_nps = NPS && (P.processes & VTX_NPS),
+             do_pair = P.processes & VTX_PAIR;
   double* out = jac + Z.z * (int64_t)(24 * n2);
   for (int e = threadIdx.x; e < n2; e += blockDim.x) {
     const int i = e / ne, j = e - i * ne;
     const double cw = P.c0w[j];
-    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0, cin = 0.0, cout = 0.0;
-    if (do_nes) {
-      const double* q = smem + off_q + 4 * (i >= j ? tri(i, j) : tri(j, i));
-      q0 = q[0];
-      q1 = q[1];
-      q2 = q[2];
-      q3 = q[3];
-      const double dcw = cw * smem[off_d + e];
-      cin = (i > j) ? dcw : cw;
-      cout = (i < j) ? dcw : cw;
-    }
+    double v[4];
+    scattering_values(smem, L, do_nes, do_nps, 4 * (i >= j ? tri(i, j) : tri(j, i)), v);
+    const double q0 = v[0], q1 = v[1], q2 = v[2], q3 = v[3];
+    const double dcw = cw * smem[L.d + e];
+    const double cin = (i > j) ? dcw : cw, cout = (i < j) ? dcw : cw;
     double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, pf = 0.0;
     if (do_pair) {
-      const double* aij = smem + off_p + 2 * e;
-      const double* aji = smem + off_p + 2 * (j * ne + i);
+      const double* aij = smem + L.p + 2 * e;
+      const double* aji = smem + L.p + 2 * (j * ne + i);
       a0 = aij[0];
       a1 = aij[1];
       b0 = aji[0];
       b1 = aji[1];
-      pf = smem[off_d + n2 + e];
+      pf = smem[L.d + n2 + e];
     }
     const double cwp = cw * pf, cwa = cw * (1.0 - pf);
 #pragma unroll
@@ -621,47 +672,56 @@ __device__ void zone_jacobian(const DevPlan& P, const Zone& Z, const double* sme
 
 // Forward of one zone: task values into LDS, then either the contraction with f into eta, chi
 // or (JAC) the explicit Jacobian blocks, which need no f.
-template <typename R, bool JAC>
+// Scattering task at position pos of the zone's task order: its four values into its slot.
+template <typename R>
+__device__ __forceinline__ void scattering_fwd(const DevPlan& P, const R* tab, const Zone& Z, double* slots,
+                                               int pos) {
+  const int t = P.task_order[Z.k * P.ntn + pos];
+  const Q4 q = task_forward<R, false>(P, tab, Z, t);
+  double* o = slots + 4 * t;
+  o[0] = q.a;
+  o[1] = q.b;
+  o[2] = q.c;
+  o[3] = q.d;
+}
+
+template <typename R, bool JAC, bool NPS>
 __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* smem, int64_t z, int selm,
                              const double* __restrict__ Tz, const double* __restrict__ etaz,
                              const double* __restrict__ f, double* __restrict__ eta_out,
                              double* __restrict__ chi_out, double* __restrict__ jac) {
-  const int ne = P.ne;
-  const int off_q = 6 * ne, off_p = off_q + 4 * P.ntn, off_d = off_p + 2 * P.ntp, n2 = ne * ne;
-  const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
-  // task counts: scattering tasks (i >= j) and pair tasks (one per unordered pair {i, j})
-  const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;
+  const int ne = P.ne, n2 = ne * ne;
+  const Lay L = layout<NPS>(P, 6 * ne);
+  const bool do_nes = P.processes & VTX_NES, do_nps = NPS && (P.processes & VTX_NPS),
+             do_pair = P.processes & VTX_PAIR;
+  // task counts: scattering tasks (i >= j) on electrons and on positrons, pair tasks (one per
+  // unordered pair {i, j})
+  const int ntn = do_nes ? P.ntn : 0, ntm = do_nps ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;
   stage_zone_state(P, z, selm, Tz, etaz, zs);
   __syncthreads();
-  const Zone& Z = *zs;
+  const Zone& Z = zs[0];
   if (!Z.valid) return;   // uniform: every lane reads the same zone state
   if (!JAC)
     for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
-  stage_factors(P, Z, smem + off_d);
-  const Units U = task_units(ntn, ntp);
+  stage_factors(P, Z, smem + L.d);
+  const Units U = task_units(ntn, ntm, ntp);
   const int lane = threadIdx.x & 63;
-  const uint16_t* order = P.task_order + Z.k * P.ntn;
   for (int u = U.first; u < U.nU; u += U.step) {
-    if (u < U.nN) {
-      const int pos = (u << 6) + lane;
-      if (pos < ntn) {
-        const int t = order[pos];
-        const Q4 q = task_forward<R, false>(P, tab, Z, t);
-        double* o = smem + off_q + 4 * t;
-        o[0] = q.a;
-        o[1] = q.b;
-        o[2] = q.c;
-        o[3] = q.d;
-      }
+    // scattering on electrons, then on positrons (the mirrored zone); one call site serves
+    // both, and without NPS the selection folds away
+    if (u < U.nN + U.nM) {
+      const bool mir = NPS && u >= U.nN;
+      const int pos = ((mir ? u - U.nN : u) << 6) + lane;
+      if (pos < (mir ? ntm : ntn)) scattering_fwd<R>(P, tab, zs[mir ? 1 : 0], smem + (mir ? L.m : L.q), pos);
     } else {
-      const int pos = ((u - U.nN) << 6) + lane;
+      const int pos = ((u - U.nN - U.nM) << 6) + lane;
       if (pos < ntp) {
-        const int t = order[pos], ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
+        const int t = P.task_order[Z.k * P.ntn + pos], ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
         const Q4 q = task_forward<R, true>(P, tab, Z, t);
-        double* o = smem + off_p + 2 * (i * ne + j);
+        double* o = smem + L.p + 2 * (i * ne + j);
         o[0] = q.a;
         o[1] = q.b;
-        o = smem + off_p + 2 * (j * ne + i);   // the same slot on the diagonal, same values
+        o = smem + L.p + 2 * (j * ne + i);   // the same slot on the diagonal, same values
         o[0] = q.c;
         o[1] = q.d;
       }
@@ -669,21 +729,20 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   }
   __syncthreads();
   if (JAC) {
-    zone_jacobian(P, Z, smem, jac);
+    zone_jacobian<NPS>(P, Z, smem, jac);
     return;
   }
   // completion, species combination and contraction: one lane per (part, bin i) runs all
   // three species over a part of j, so each (i, j) pair's task values, detailed-balance
   // factors and weights are read and combined once; the parts are added in order
   const int npb = bin_parts(ne);
-  double* s_part = smem + off_d + 2 * n2;   // [part][i][species][eta0, chi0, eta1, chi1]
+  double* s_part = smem + L.d + 2 * n2;   // [part][i][species][eta0, chi0, eta1, chi1]
   for (int r = threadIdx.x; r < npb * ne; r += blockDim.x) {
     const int part = r / ne, i = r - part * ne;
     const int j0 = part * ne / npb, j1 = (part + 1) * ne / npb;
     const double* s_f = smem;
-    const double* s_qn = smem + off_q;
-    const double* s_pa = smem + off_p;
-    const double* s_d = smem + off_d;
+    const double* s_pa = smem + L.p;
+    const double* s_d = smem + L.d;
     const double* s_p = s_d + n2;
     double acc[3][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     for (int j = j0; j < j1; ++j) {
@@ -696,9 +755,10 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
         fj[s][0] = s_f[(2 * s) * ne + j];
         fj[s][1] = s_f[(2 * s + 1) * ne + j];
       }
-      if (do_nes) {
-        const double* q = s_qn + 4 * (i >= j ? tri(i, j) : tri(j, i));
-        const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+      if (do_nes || do_nps) {
+        double v[4];
+        scattering_values(smem, L, do_nes, do_nps, 4 * (i >= j ? tri(i, j) : tri(j, i)), v);
+        const double q0 = v[0], q1 = v[1], q2 = v[2], q3 = v[3];
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
           const double bI = beta_of(P, s, 0), bII = beta_of(P, s, 1);
@@ -759,22 +819,22 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
 
 // Dense pass: workgroup b takes zone b (if selected). Occupancy targets: four waves per SIMD
 // for FP32 (at most 128 VGPRs), three for FP64.
-template <typename R, bool JAC>
+template <typename R, bool JAC, bool NPS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 3)))
 void rates_forward_kernel(DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz,
                           const double* __restrict__ etaz, const double* __restrict__ f,
                           double* __restrict__ eta_out, double* __restrict__ chi_out, double* __restrict__ jac) {
   __shared__ R tab[kTabLen];
-  __shared__ Zone zs;
+  __shared__ Zone zs[2];
   extern __shared__ double smem[];
   stage_tab<R>(P, tab);
   const int64_t z = blockIdx.x;
-  zone_forward<R, JAC>(P, tab, &zs, smem, z < nz ? z : -1, selm, Tz, etaz, f, eta_out, chi_out, jac);
+  zone_forward<R, JAC, NPS>(P, tab, zs, smem, z < nz ? z : -1, selm, Tz, etaz, f, eta_out, chi_out, jac);
 }
 
 // Sparse FP64 pass: workgroups scan windows of blockDim zones and run the zones with
 // |eta_e| above the threshold, one at a time. The scan order does not change any result.
-template <bool JAC>
+template <bool JAC, bool NPS>
 __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_t nz, const double* __restrict__ Tz,
                                                                   const double* __restrict__ etaz,
                                                                   const double* __restrict__ f,
@@ -782,7 +842,7 @@ __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_
                                                                   double* __restrict__ chi_out,
                                                                   double* __restrict__ jac) {
   __shared__ double tab[kTabLen];
-  __shared__ Zone zs;
+  __shared__ Zone zs[2];
   __shared__ int list[kBlock];
   __shared__ int count;
   extern __shared__ double smem[];
@@ -795,7 +855,8 @@ __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_
     __syncthreads();
     const int n = count;
     for (int c = 0; c < n; ++c) {
-      zone_forward<double, JAC>(P, tab, &zs, smem, base + list[c], kSelAll, Tz, etaz, f, eta_out, chi_out, jac);
+      zone_forward<double, JAC, NPS>(P, tab, zs, smem, base + list[c], kSelAll, Tz, etaz, f, eta_out, chi_out,
+                                     jac);
       __syncthreads();
     }
     __syncthreads();   // every lane has read count before the next window resets it
@@ -1137,14 +1198,26 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Scattering task t in the backward: upstream weights of its components, recomputation with
 // derivatives, and the T-derivative of its detailed-balance completion. The task's LDS slot
-// holds the completion weights until the task values replace them.
+// holds the completion weights until the task values replace them. On positron targets
+// (swap) the component (S, l) carries the couplings of the other S, so the weights of S = I
+// and S = II trade places.
 template <typename R>
 __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
-                                             const double* s_d, double* s_u, R* lq, int t, double& dT, double& dE) {
+                                             const double* s_d, double* s_u, bool swap, R* lq, int t, double& dT,
+                                             double& dE) {
   const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
   double* o = s_u + 4 * t;
-  double w[4], up[4];
-  nes_adjoint(P, A, i, j, s_d[i * ne + j], w, up);
+  double v[4], vu[4], w[4], up[4];
+  nes_adjoint(P, A, i, j, s_d[i * ne + j], v, vu);
+  const double v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3], u0 = vu[0], u1 = vu[1], u2 = vu[2], u3 = vu[3];
+  w[0] = swap ? v2 : v0;
+  w[1] = swap ? v3 : v1;
+  w[2] = swap ? v0 : v2;
+  w[3] = swap ? v1 : v3;
+  up[0] = swap ? u2 : u0;
+  up[1] = swap ? u3 : u1;
+  up[2] = swap ? u0 : u2;
+  up[3] = swap ? u1 : u3;
   o[0] = up[0];
   o[1] = up[1];
   o[2] = up[2];
@@ -1162,12 +1235,12 @@ __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, con
 // diagonal); the production factor's weights wait in the two tasks' LDS slots.
 template <typename R>
 __device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
-                                              const double* s_p, double* s_u, R* lq, int t, double& dT, double& dE) {
+                                              const double* s_p, double* s_pa, R* lq, int t, double& dT, double& dE) {
   const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
   const bool off = i != j;
   const double pf = s_p[i * ne + j];   // symmetric in (i, j)
-  double* o1 = s_u + 4 * P.ntn + 2 * (i * ne + j);
-  double* o2 = s_u + 4 * P.ntn + 2 * (j * ne + i);
+  double* o1 = s_pa + 2 * (i * ne + j);
+  double* o2 = s_pa + 2 * (j * ne + i);
   double w[4], pc[4];
   pair_adjoint(P, A, i, j, pf, w, pc);
   o1[0] = pc[0];
@@ -1189,24 +1262,26 @@ __device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, co
   }
 }
 
-// Task units of one zone, at most: 2 ceil(528/64) at 32 bins.
+// Task units of one zone, at most: 3 ceil(528/64) at 32 bins.
 constexpr int kMaxUnits = 32;
 
-template <typename R>
+template <typename R, bool NPS>
 __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* red, double* smem, int64_t z,
                               int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
                               const double* __restrict__ f, const double* __restrict__ g_eta,
                               const double* __restrict__ g_chi, double* __restrict__ gT_out,
                               double* __restrict__ gE_out, double* __restrict__ gf_out) {
   const int ne = P.ne, n2 = ne * ne;
-  const bool do_nes = P.processes & VTX_NES, do_pair = P.processes & VTX_PAIR;
-  const int ntn = do_nes ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;   // pair tasks: unordered pairs
-  // f | g_eta | g_chi [6 ne each] | task values [4 ntn + 2 ntp] (full-size offsets whatever
-  // the process mask) | detailed-balance factors [2 ne^2]
-  const int off_ge = 6 * ne, off_gc = 12 * ne, off_u = 18 * ne, off_d = off_u + 4 * P.ntn + 2 * P.ntp;
+  const bool do_nes = P.processes & VTX_NES, do_nps = NPS && (P.processes & VTX_NPS),
+             do_pair = P.processes & VTX_PAIR;
+  const int ntn = do_nes ? P.ntn : 0, ntm = do_nps ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;
+  // f | g_eta | g_chi [6 ne each] | task values (layout(), full-size scattering and pair
+  // regions whatever the process mask) | detailed-balance factors [2 ne^2]
+  const int off_ge = 6 * ne, off_gc = 12 * ne;
+  const Lay L = layout<NPS>(P, 18 * ne);
   stage_zone_state(P, z, selm, Tz, etaz, zs);
   __syncthreads();
-  const Zone& Z = *zs;
+  const Zone& Z = zs[0];
   if (!Z.valid) return;   // uniform: every lane reads the same zone state
   for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) {
     const int64_t g = Z.z * 6 * ne + r;
@@ -1214,24 +1289,31 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
     smem[off_ge + r] = g_eta[g];
     smem[off_gc + r] = g_chi[g];
   }
-  stage_factors(P, Z, smem + off_d);
+  stage_factors(P, Z, smem + L.d);
   __syncthreads();
   const Adj A{smem, smem + off_ge, smem + off_gc, ne};
-  const Units U = task_units(ntn, ntp);
+  const Units U = task_units(ntn, ntm, ntp);
   const int lane = threadIdx.x & 63;
   // per-lane slots after the contraction parts: 13 bulk-type values per lane, stride kBlock
-  R* lq = reinterpret_cast<R*>(smem + off_d + 2 * n2 + 24 * ne) + threadIdx.x;
+  R* lq = reinterpret_cast<R*>(smem + L.d + 2 * n2 + 24 * ne) + threadIdx.x;
   // d/dT and d/deta_e: summed per unit in the unit's wave, then over units in unit order, so
   // the result does not depend on which wave ran which unit
-  const uint16_t* order = P.task_order + Z.k * P.ntn;
   for (int u = U.first; u < U.nU; u += U.step) {
     double dT = 0.0, dE = 0.0;
-    if (u < U.nN) {
-      const int pos = (u << 6) + lane;
-      if (pos < ntn) nes_task_bwd<R>(P, tab, Z, A, smem + off_d, smem + off_u, lq, order[pos], dT, dE);
+    if (u < U.nN + U.nM) {
+      // positron targets: the mirrored zone, eta' = -eta_e, so d/deta_e = -d/deta'; without
+      // NPS the selection folds away
+      const bool mir = NPS && u >= U.nN;
+      const Zone& ZS = zs[mir ? 1 : 0];
+      const int pos = ((mir ? u - U.nN : u) << 6) + lane;
+      if (pos < (mir ? ntm : ntn))
+        nes_task_bwd<R>(P, tab, ZS, A, smem + L.d, smem + (mir ? L.m : L.q), mir, lq,
+                        P.task_order[ZS.k * P.ntn + pos], dT, dE);
+      if (mir) dE = -dE;
     } else {
-      const int pos = ((u - U.nN) << 6) + lane;
-      if (pos < ntp) pair_task_bwd<R>(P, tab, Z, A, smem + off_d + n2, smem + off_u, lq, order[pos], dT, dE);
+      const int pos = ((u - U.nN - U.nM) << 6) + lane;
+      if (pos < ntp)
+        pair_task_bwd<R>(P, tab, Z, A, smem + L.d + n2, smem + L.p, lq, P.task_order[Z.k * P.ntn + pos], dT, dE);
     }
     dT = wave_sum(dT);
     dE = wave_sum(dE);
@@ -1253,13 +1335,12 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
   // g_f: column contractions of the kernels from LDS, one lane per (part, bin j) for all three
   // species over a part of i (c0 w_j factors out of the sum); the parts are added in order
   const int npb = bin_parts(ne);
-  double* s_part = smem + off_d + 2 * n2;   // [part][j][species][g_f0, g_f1]
+  double* s_part = smem + L.d + 2 * n2;   // [part][j][species][g_f0, g_f1]
   for (int r = threadIdx.x; r < npb * ne; r += blockDim.x) {
     const int part = r / ne, j = r - part * ne;
     const int i0 = part * ne / npb, i1 = (part + 1) * ne / npb;
-    const double* s_qn = smem + off_u;
-    const double* s_pa = smem + off_u + 4 * P.ntn;
-    const double* s_d = smem + off_d;
+    const double* s_pa = smem + L.p;
+    const double* s_d = smem + L.d;
     const double* s_p = s_d + n2;
     double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     for (int i = i0; i < i1; ++i) {
@@ -1271,9 +1352,10 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
         gc[s][0] = A.GC(s, 0, i);
         gc[s][1] = A.GC(s, 1, i);
       }
-      if (do_nes) {
-        const double* q = s_qn + 4 * (i >= j ? tri(i, j) : tri(j, i));
-        const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+      if (do_nes || do_nps) {
+        double v[4];
+        scattering_values(smem, L, do_nes, do_nps, 4 * (i >= j ? tri(i, j) : tri(j, i)), v);
+        const double q0 = v[0], q1 = v[1], q2 = v[2], q3 = v[3];
         const double dfac = s_d[i * ne + j];
         const double a_in = (i > j) ? dfac : 1.0, a_out = (i < j) ? dfac : 1.0;
 #pragma unroll
@@ -1324,28 +1406,29 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
 
 // Occupancy targets: three waves per SIMD for the FP32 backward (at most 168 VGPRs), two
 // for the FP64 one.
-template <typename R>
+template <typename R, bool NPS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
 void rates_backward_kernel(
     DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
     const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
     double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out) {
   __shared__ R tab[kTabLen];
-  __shared__ Zone zs;
+  __shared__ Zone zs[2];
   __shared__ double red[2 * kMaxUnits];
   extern __shared__ double smem[];
   stage_tab<R>(P, tab);
   const int64_t z = blockIdx.x;
-  zone_backward<R>(P, tab, &zs, red, smem, z < nz ? z : -1, selm, Tz, etaz, f, g_eta, g_chi, gT_out, gE_out,
+  zone_backward<R, NPS>(P, tab, zs, red, smem, z < nz ? z : -1, selm, Tz, etaz, f, g_eta, g_chi, gT_out, gE_out,
                    gf_out);
 }
 
+template <bool NPS>
 __global__ __launch_bounds__(kBlock) void rates_backward_sparse(
     DevPlan P, int64_t nz, const double* __restrict__ Tz, const double* __restrict__ etaz,
     const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
     double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out) {
   __shared__ double tab[kTabLen];
-  __shared__ Zone zs;
+  __shared__ Zone zs[2];
   __shared__ double red[2 * kMaxUnits];
   __shared__ int list[kBlock];
   __shared__ int count;
@@ -1359,7 +1442,7 @@ __global__ __launch_bounds__(kBlock) void rates_backward_sparse(
     __syncthreads();
     const int n = count;
     for (int c = 0; c < n; ++c) {
-      zone_backward<double>(P, tab, &zs, red, smem, base + list[c], kSelAll, Tz, etaz, f, g_eta, g_chi, gT_out,
+      zone_backward<double, NPS>(P, tab, zs, red, smem, base + list[c], kSelAll, Tz, etaz, f, g_eta, g_chi, gT_out,
                             gE_out, gf_out);
       __syncthreads();
     }
@@ -1369,12 +1452,15 @@ __global__ __launch_bounds__(kBlock) void rates_backward_sparse(
 
 // Per-zone LDS: the layouts above plus the contraction parts (at most 4 x ne x 3 x 4 doubles
 // forward, 4 x ne x 3 x 2 backward).
+int task_values(const DevPlan& P) {
+  return 4 * P.ntn * ((P.processes & VTX_NPS) ? 2 : 1) + 2 * P.ntp;
+}
 size_t zone_lds_fwd(const DevPlan& P) {
-  return sizeof(double) * (6 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne + 48 * P.ne);
+  return sizeof(double) * (6 * P.ne + task_values(P) + 2 * P.ne * P.ne + 48 * P.ne);
 }
 // The backward adds 13 values per lane of the bulk type (elem bytes) for the pair tasks.
 size_t zone_lds_bwd(const DevPlan& P, size_t elem) {
-  return sizeof(double) * (18 * P.ne + 4 * P.ntn + 2 * P.ntp + 2 * P.ne * P.ne + 24 * P.ne) + 13 * kBlock * elem;
+  return sizeof(double) * (18 * P.ne + task_values(P) + 2 * P.ne * P.ne + 24 * P.ne) + 13 * kBlock * elem;
 }
 
 // Dynamic LDS beyond the 64 KiB default must be requested per kernel.
@@ -1395,23 +1481,54 @@ unsigned sparse_grid(int64_t nz) {
 // Larger calls are issued as consecutive slices on the same stream.
 constexpr int64_t kSliceZones = int64_t(1) << 22;
 
-hipError_t forward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
-                         double* eta, double* chi, double* jac, hipStream_t s) {
+template <bool NPS>
+hipError_t forward_slice_t(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                           double* eta, double* chi, double* jac, hipStream_t s) {
   const size_t lds = zone_lds_fwd(P);
   const dim3 grid((unsigned)nz), block(kBlock);
   hipError_t e;
   if (P.precision == VTX_MIXED) {
-    auto bulk = jac ? rates_forward_kernel<float, true> : rates_forward_kernel<float, false>;
-    auto sparse = jac ? rates_forward_sparse<true> : rates_forward_sparse<false>;
+    auto bulk = jac ? rates_forward_kernel<float, true, NPS> : rates_forward_kernel<float, false, NPS>;
+    auto sparse = jac ? rates_forward_sparse<true, NPS> : rates_forward_sparse<false, NPS>;
     if ((e = allow_lds(bulk, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(bulk, grid, block, lds, s, P, nz, kSelBulk, T, eta_e, f, eta, chi, jac);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = allow_lds(sparse, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(sparse, dim3(sparse_grid(nz)), block, lds, s, P, nz, T, eta_e, f, eta, chi, jac);
   } else {
-    auto dense = jac ? rates_forward_kernel<double, true> : rates_forward_kernel<double, false>;
+    auto dense = jac ? rates_forward_kernel<double, true, NPS> : rates_forward_kernel<double, false, NPS>;
     if ((e = allow_lds(dense, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(dense, grid, block, lds, s, P, nz, kSelAll, T, eta_e, f, eta, chi, jac);
+  }
+  return hipGetLastError();
+}
+
+hipError_t forward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                         double* eta, double* chi, double* jac, hipStream_t s) {
+  return (P.processes & VTX_NPS) ? forward_slice_t<true>(P, nz, T, eta_e, f, eta, chi, jac, s)
+                                 : forward_slice_t<false>(P, nz, T, eta_e, f, eta, chi, jac, s);
+}
+
+template <bool NPS>
+hipError_t backward_slice_t(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                            const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
+                            hipStream_t s) {
+  const size_t lds32 = zone_lds_bwd(P, sizeof(float)), lds64 = zone_lds_bwd(P, sizeof(double));
+  const dim3 grid((unsigned)nz), block(kBlock);
+  hipError_t e;
+  if (P.precision == VTX_MIXED) {
+    auto bulk = rates_backward_kernel<float, NPS>;
+    auto sparse = rates_backward_sparse<NPS>;
+    if ((e = allow_lds(bulk, lds32)) != hipSuccess) return e;
+    hipLaunchKernelGGL(bulk, grid, block, lds32, s, P, nz, kSelBulk, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = allow_lds(sparse, lds64)) != hipSuccess) return e;
+    hipLaunchKernelGGL(sparse, dim3(sparse_grid(nz)), block, lds64, s, P, nz, T, eta_e, f, g_eta, g_chi, g_T,
+                       g_eta_e, g_f);
+  } else {
+    auto dense = rates_backward_kernel<double, NPS>;
+    if ((e = allow_lds(dense, lds64)) != hipSuccess) return e;
+    hipLaunchKernelGGL(dense, grid, block, lds64, s, P, nz, kSelAll, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f);
   }
   return hipGetLastError();
 }
@@ -1419,23 +1536,9 @@ hipError_t forward_slice(const DevPlan& P, int64_t nz, const double* T, const do
 hipError_t backward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
                           const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
                           hipStream_t s) {
-  const size_t lds32 = zone_lds_bwd(P, sizeof(float)), lds64 = zone_lds_bwd(P, sizeof(double));
-  const dim3 grid((unsigned)nz), block(kBlock);
-  hipError_t e;
-  if (P.precision == VTX_MIXED) {
-    if ((e = allow_lds(rates_backward_kernel<float>, lds32)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_backward_kernel<float>, grid, block, lds32, s, P, nz, kSelBulk, T, eta_e, f, g_eta,
-                       g_chi, g_T, g_eta_e, g_f);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = allow_lds(rates_backward_sparse, lds64)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_backward_sparse, dim3(sparse_grid(nz)), block, lds64, s, P, nz, T, eta_e, f, g_eta,
-                       g_chi, g_T, g_eta_e, g_f);
-  } else {
-    if ((e = allow_lds(rates_backward_kernel<double>, lds64)) != hipSuccess) return e;
-    hipLaunchKernelGGL(rates_backward_kernel<double>, grid, block, lds64, s, P, nz, kSelAll, T, eta_e, f, g_eta,
-                       g_chi, g_T, g_eta_e, g_f);
-  }
-  return hipGetLastError();
+  return (P.processes & VTX_NPS)
+             ? backward_slice_t<true>(P, nz, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, s)
+             : backward_slice_t<false>(P, nz, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, s);
 }
 
 }  // namespace

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vtx_rates.h")
 VTX_OK, VTX_EINVAL, VTX_EDEVICE, VTX_EHIP, VTX_ENOMEM = 0, 1, 2, 3, 4
 VTX_FP64, VTX_MIXED = 0, 1
 VTX_RULE_LAGUERRE, VTX_RULE_PANEL = 0, 1
-VTX_NES, VTX_PAIR = 1, 2
+VTX_NES, VTX_PAIR, VTX_NPS = 1, 2, 4
 
 
 class Grid(ctypes.Structure):

@@ -70,7 +70,7 @@ def test_invalid_arguments():
     assert _call_jac(g, o, -1) == vtx.VTX_EINVAL
     assert _call_jac(g, o, 0) == vtx.VTX_OK
     for field, bad in [("nquad", 6), ("nquad", 50), ("nquad", 68), ("rule", 2), ("precision", 3),
-                       ("processes", 0), ("processes", 4), ("sin2w", float("nan"))]:
+                       ("processes", 0), ("processes", 8), ("sin2w", float("nan"))]:
         ob = vtx.make_opts()
         setattr(ob, field, bad)
         assert _call_fwd(g, ob, 4) == vtx.VTX_EINVAL, (field, bad)

@@ -75,7 +75,7 @@ def test_small_all_zones():
     check(inp, "mixed", 32, "laguerre", MIXED_TOL, label="small")
 
 
-@pytest.mark.parametrize("processes", [1, 2, 3])
+@pytest.mark.parametrize("processes", [1, 2, 3, 4, 7])
 def test_medium_and_process_masks(processes):
     inp = synth.make_inputs("medium", nzones=9)
     J = check(inp, "fp64", 48, "panel", FP64_TOL, processes, label="medium-9")
@@ -83,6 +83,8 @@ def test_medium_and_process_masks(processes):
         assert np.all(J[:, :, 1] == 0)
     if processes == 2:
         assert np.all(J[:, :, 0] == 0)
+    if processes == 4:
+        assert np.all(J[:, :, 1] == 0) and np.any(J[:, :, 0] != 0)
     check(inp, "mixed", 48, "panel", MIXED_TOL, processes, label="medium-9")
 
 

@@ -87,7 +87,7 @@ def test_small_fp64_panel_and_mixed():
     check_forward(inp, "mixed", 32, "panel", MIXED_TOL, label="small/panel")
 
 
-@pytest.mark.parametrize("processes", [1, 2])
+@pytest.mark.parametrize("processes", [1, 2, 4])
 def test_single_process(processes):
     inp = synth.make_inputs("medium", nzones=8)
     check_forward(inp, "fp64", 48, "panel", FP64_TOL, processes, label="medium-8")
@@ -176,9 +176,9 @@ def test_deterministic_and_batch_independent():
 
 # ---------------------------------------------------------------------------- backward
 
-def gpu_backward(inp, ge, gc, precision, nquad, rule, eta_fp64=64.0):
+def gpu_backward(inp, ge, gc, precision, nquad, rule, eta_fp64=64.0, processes=3):
     grid = vtx.GridHandle(inp.eps, inp.w)
-    opts = vtx.make_opts(precision, nquad, rule, eta_fp64=eta_fp64)
+    opts = vtx.make_opts(precision, nquad, rule, processes, eta_fp64=eta_fp64)
     out = vtx.backward(grid, opts, to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f), to_dev(ge), to_dev(gc))
     torch.cuda.synchronize()
     return [t.cpu().numpy() for t in out]
@@ -293,3 +293,55 @@ def test_backward_batch_independent():
         one = gpu_backward(synth.subset(inp, [5]), ge[5:6], gc[5:6], prec, 48, "panel")
         for a, b in zip(full, one):
             assert np.array_equal(a[5:6], b)
+
+
+# ------------------------------------------------------------------ positron scattering
+
+def test_positron_scattering_forward():
+    """All three processes (VTX_NPS added), over eta_e signs and the degenerate end: the
+    mirrored zone's task order is nontrivial for eta_e < 0."""
+    inp = synth.make_inputs("medium", nzones=10)
+    inp.eta_e[:5] = [-12.0, -3.0, 0.0, 45.0, 60.0]
+    inp.T[:5] = [2.0, 8.0, 30.0, 1.5, 0.5]
+    check_forward(inp, "fp64", 48, "panel", FP64_TOL, processes=7, label="all processes")
+    check_forward(inp, "mixed", 48, "panel", MIXED_TOL, processes=7, label="all processes")
+    check_forward(inp, "fp64", 48, "panel", FP64_TOL, processes=5, label="both scatterings")
+    small = synth.make_inputs("small", nzones=6)
+    check_forward(small, "fp64", 32, "laguerre", FP64_TOL, processes=7, label="small/laguerre")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 1e-3)])
+def test_positron_scattering_backward(precision, tol):
+    inp = synth.make_inputs("medium", nzones=6)
+    inp.eta_e[:3] = [-8.0, 0.5, 30.0]
+    ge, gc = synth.random_gradients(6, inp.eps.shape[0], 13)
+    for proc in (4, 7):
+        say(f"[gpu] backward processes={proc} {precision}")
+        gT, gE, gf = gpu_backward(inp, ge, gc, precision, 48, "panel", processes=proc)
+        rT, rE, rf = ograd.vjp(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, ge, gc,
+                               orates.Options(nquad=48, rule="panel", processes=proc))
+        eT, eE, ef = grad_err(gT, rT).max(), grad_err(gE, rE).max(), grad_err(gf, rf).max()
+        say(f"    rel err g_T {eT:.2e} g_eta_e {eE:.2e} g_f {ef:.2e}")
+        assert max(eT, eE, ef) <= tol
+
+
+def test_positron_scattering_large_sampled():
+    """One launch over 307,200 zones of the large workload with all processes, mixed, sampled
+    zones against the oracle."""
+    wl = synth.WORKLOADS["large"]
+    nz = wl.nzones // wl.chunks
+    inp = synth.make_inputs("large", nzones=nz)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts("mixed", wl.nquad, wl.rule, 7)
+    say(f"[gpu] all processes, large chunk of {nz} zones")
+    eta, chi = vtx.forward(grid, opts, to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f))
+    torch.cuda.synchronize()
+    idx = synth.sample_zones(inp, 12)
+    it = torch.from_numpy(idx).to(DEV)
+    e, c = eta.index_select(0, it).cpu().numpy(), chi.index_select(0, it).cpu().numpy()
+    del eta, chi
+    sub = synth.subset(inp, idx)
+    re, rc, ae, ac = oracle_forward(sub, wl.nquad, wl.rule, 7)
+    err = max(rel_err(e, re, ae).max(), rel_err(c, rc, ac).max())
+    say(f"    sampled {len(idx)} zones, max rel err {err:.2e}")
+    assert err <= MIXED_TOL
