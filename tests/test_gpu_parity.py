@@ -345,3 +345,36 @@ def test_positron_scattering_large_sampled():
     err = max(rel_err(e, re, ae).max(), rel_err(c, rc, ac).max())
     say(f"    sampled {len(idx)} zones, max rel err {err:.2e}")
     assert err <= MIXED_TOL
+
+
+def test_launch_slicing_over_2_22_zones():
+    """A call over more than 2^22 zones is issued as slices: zones on both sides of the slice
+    boundary and in the last, short slice equal separate launches over them, bit for bit
+    (forward and backward, mixed precision)."""
+    nz = (1 << 22) + 300
+    say(f"[gpu] slicing: {nz} zones")
+    inp = synth.make_inputs("large", nzones=nz)
+    wl = synth.WORKLOADS["large"]
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts("mixed", wl.nquad, wl.rule)
+    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
+    eta, chi = vtx.forward(grid, opts, T, E, f)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(14)
+    ge = torch.randn(f.shape, dtype=torch.float64, device=DEV, generator=gen)
+    gc = torch.randn(f.shape, dtype=torch.float64, device=DEV, generator=gen)
+    gT, gE, gf = vtx.backward(grid, opts, T, E, f, ge, gc)
+    torch.cuda.synchronize()
+    idx = np.array([0, (1 << 22) - 2, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, nz - 1])
+    it = torch.from_numpy(idx).to(DEV)
+    full = [t.index_select(0, it).cpu().numpy() for t in (eta, chi, gT, gE, gf)]
+    ges, gcs = ge.index_select(0, it).contiguous(), gc.index_select(0, it).contiguous()
+    del eta, chi, gT, gE, gf, T, E, f, ge, gc
+    torch.cuda.empty_cache()
+    sub = synth.subset(inp, idx)
+    Ts, Es, fs = to_dev(sub.T), to_dev(sub.eta_e), to_dev(sub.f)
+    e1, c1 = vtx.forward(grid, opts, Ts, Es, fs)
+    g1 = vtx.backward(grid, opts, Ts, Es, fs, ges, gcs)
+    torch.cuda.synchronize()
+    for a, b in zip(full, [t.cpu().numpy() for t in (e1, c1) + tuple(g1)]):
+        assert np.array_equal(a, b)
