@@ -190,6 +190,29 @@ class Runner:
         self.events = events
         return dt
 
+    def fused_step(self):
+        """Forward and backward of every chunk in one call each (vtx_rates_forward_backward)."""
+        torch, vtx = self.torch, self.vtx
+        s = self.streams[0]
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for a, b in self.chunks:
+                vtx.forward_backward(self.grid, self.opts, self.T[a:b], self.E[a:b], self.f[a:b], self.g_eta[a:b],
+                                     self.g_chi[a:b], out=(self.eta[a:b], self.chi[a:b], self.gT[a:b],
+                                                           self.gE[a:b], self.gf[a:b]), stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+
+    def timed_fused(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.fused_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.fused_step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / max(steps, 1)
+
     def launch_times(self):
         """Average forward / backward launch durations (ms) and zones per launch, from the
         events of the timed region."""
@@ -377,6 +400,8 @@ def main():
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--stream-steps", type=int, default=2,
                     help="steps of the pinned-host streaming run, PCIe included (0: skip)")
+    ap.add_argument("--fused-steps", type=int, default=2,
+                    help="steps with forward and backward fused in one call per chunk (0: skip)")
     ap.add_argument("--positron-steps", type=int, default=2,
                     help="steps of the run with neutrino-positron scattering added (0: skip)")
     ap.add_argument("--jacobian-launches", type=int, default=3,
@@ -410,6 +435,13 @@ def main():
     value = units / t_step
     t_fwd, t_bwd, zl = run.launch_times()
     errors = None if args.no_errors else sampled_errors(inp, run.eta, run.chi, wl)
+    fused = None
+    if args.fused_steps > 0:
+        print(f"[bench] fused forward+backward: {args.fused_steps} steps", file=sys.stderr, flush=True)
+        tf = run.timed_fused(args.fused_steps, 1)
+        fused = {"value": units / tf, "unit": "zone*(eps,eps')/s", "ms_per_step": tf * 1e3,
+                 "note": "vtx_rates_forward_backward: one call per chunk computes eta, chi and the VJP; "
+                         "for callers holding g_eta, g_chi before the forward values"}
     streaming = None
     if args.stream_steps > 0:
         print(f"[bench] streaming from pinned host memory: {args.stream_steps} steps", file=sys.stderr, flush=True)
@@ -470,6 +502,7 @@ def main():
                    "zones": wl.nzones, "ne": wl.ne, "nquad": wl.nquad, "precision": precision},
         "rel_err_vs_oracle": errors, "fp64": fp64, "roofline": roof, "cpu_baseline": cpu,
         "streaming_pcie": streaming, "jacobian": jac, "with_positron_scattering": positron,
+        "fused_forward_backward": fused,
     }
     print(json.dumps(line), flush=True)
 

@@ -136,9 +136,27 @@ int vtx_rates_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzone
  *     p = 1: c0 w_j [-Phi_p_0, Phi_a_0 - Phi_p_0, -Phi_p_1, Phi_a_1 - Phi_p_1](i, j)
  *   A process left out of opts->processes gives zero blocks. Same precision rules as the
  *   forward. jac (device memory, 192 ne^2 bytes per zone) is overwritten; T, eta_e as above.
+ * f, eta, chi: all NULL, or all given; then the same call also writes eta, chi for f (the
+ *   residual and its Jacobian at one zone state, from the same kernel values, bit-identical
+ *   to vtx_rates_forward).
  */
 int vtx_rates_jacobian(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
-                       const double* T, const double* eta_e, double* jac, void* hip_stream);
+                       const double* T, const double* eta_e, const double* f,
+                       double* eta, double* chi, double* jac, void* hip_stream);
+
+/*
+ * Forward and backward in one pass: eta, chi as vtx_rates_forward and g_T, g_eta_e, g_f as
+ * vtx_rates_backward (bit-identical to it), for callers that hold the upstream gradients
+ * g_eta, g_chi before the forward values, e.g. a Newton-Krylov solve that needs a residual
+ * and a transposed Jacobian product at one state. The backward recomputes the kernels
+ * anyway, so eta, chi cost one extra contraction. eta, chi agree with vtx_rates_forward to
+ * rounding (the kernels come from the backward's quadrature loop).
+ */
+int vtx_rates_forward_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
+                               const double* T, const double* eta_e, const double* f,
+                               const double* g_eta, const double* g_chi,
+                               double* eta, double* chi,
+                               double* g_T, double* g_eta_e, double* g_f, void* hip_stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* vtx_strerror(int code);

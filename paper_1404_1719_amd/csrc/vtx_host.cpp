@@ -470,15 +470,34 @@ int vtx_rates_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzone
 }
 
 int vtx_rates_jacobian(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
-                       const double* eta_e, double* jac, void* hip_stream) {
+                       const double* eta_e, const double* f, double* eta, double* chi, double* jac,
+                       void* hip_stream) {
   int rc = vtx::check_args(grid, opts, nzones);
   if (rc != VTX_OK) return rc;
   if (nzones == 0) return VTX_OK;
   if (!T || !eta_e || !jac) return VTX_EINVAL;
+  const bool outs = f || eta || chi;
+  if (outs && !(f && eta && chi)) return VTX_EINVAL;   // all three or none
   vtx::DevPlan P;
   rc = vtx::get_plan(grid, opts, &P);
   if (rc != VTX_OK) return rc;
-  const hipError_t e = vtx::launch_jacobian(P, nzones, T, eta_e, jac, (hipStream_t)hip_stream);
+  const hipError_t e = vtx::launch_jacobian(P, nzones, T, eta_e, f, eta, chi, jac, (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+
+int vtx_rates_forward_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
+                               const double* eta_e, const double* f, const double* g_eta, const double* g_chi,
+                               double* eta, double* chi, double* g_T, double* g_eta_e, double* g_f,
+                               void* hip_stream) {
+  int rc = vtx::check_args(grid, opts, nzones);
+  if (rc != VTX_OK) return rc;
+  if (nzones == 0) return VTX_OK;
+  if (!T || !eta_e || !f || !g_eta || !g_chi || !eta || !chi || !g_T || !g_eta_e || !g_f) return VTX_EINVAL;
+  vtx::DevPlan P;
+  rc = vtx::get_plan(grid, opts, &P);
+  if (rc != VTX_OK) return rc;
+  const hipError_t e = vtx::launch_forward_backward(P, nzones, T, eta_e, f, g_eta, g_chi, eta, chi, g_T, g_eta_e,
+                                                    g_f, (hipStream_t)hip_stream);
   return e == hipSuccess ? VTX_OK : VTX_EHIP;
 }
 

@@ -67,8 +67,11 @@ struct DevPlan {
 
 hipError_t launch_forward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e,
                           const double* f, double* eta, double* chi, hipStream_t s);
-hipError_t launch_jacobian(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, double* jac,
-                           hipStream_t s);
+hipError_t launch_jacobian(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                           double* eta, double* chi, double* jac, hipStream_t s);
+hipError_t launch_forward_backward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e,
+                                   const double* f, const double* g_eta, const double* g_chi, double* eta,
+                                   double* chi, double* g_T, double* g_eta_e, double* g_f, hipStream_t s);
 hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e,
                            const double* f, const double* g_eta, const double* g_chi,
                            double* g_T, double* g_eta_e, double* g_f, hipStream_t s);

@@ -670,73 +670,19 @@ __device__ void zone_jacobian(const DevPlan& P, const Zone& Z, const double* sme
   }
 }
 
-// Forward of one zone: task values into LDS, then either the contraction with f into eta, chi
-// or (JAC) the explicit Jacobian blocks, which need no f.
-// Scattering task at position pos of the zone's task order: its four values into its slot.
-template <typename R>
-__device__ __forceinline__ void scattering_fwd(const DevPlan& P, const R* tab, const Zone& Z, double* slots,
-                                               int pos) {
-  const int t = P.task_order[Z.k * P.ntn + pos];
-  const Q4 q = task_forward<R, false>(P, tab, Z, t);
-  double* o = slots + 4 * t;
-  o[0] = q.a;
-  o[1] = q.b;
-  o[2] = q.c;
-  o[3] = q.d;
-}
-
-template <typename R, bool JAC, bool NPS>
-__device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* smem, int64_t z, int selm,
-                             const double* __restrict__ Tz, const double* __restrict__ etaz,
-                             const double* __restrict__ f, double* __restrict__ eta_out,
-                             double* __restrict__ chi_out, double* __restrict__ jac) {
+// Completion, species combination and contraction of a zone's task values (LDS, layout L)
+// with f (LDS, smem[0, 6 ne)) into eta, chi. One lane per (part, bin i) runs all three
+// species over a part of j, so each (i, j) pair's task values, detailed-balance factors and
+// weights are read and combined once; the parts (s_part, 12 npb ne doubles) are added in
+// order.
+template <bool NPS>
+__device__ __forceinline__ void zone_contract(const DevPlan& P, const Zone& Z, const double* smem, const Lay& L,
+                                              double* s_part, double* __restrict__ eta_out,
+                                              double* __restrict__ chi_out) {
   const int ne = P.ne, n2 = ne * ne;
-  const Lay L = layout<NPS>(P, 6 * ne);
   const bool do_nes = P.processes & VTX_NES, do_nps = NPS && (P.processes & VTX_NPS),
              do_pair = P.processes & VTX_PAIR;
-  // task counts: scattering tasks (i >= j) on electrons and on positrons, pair tasks (one per
-  // unordered pair {i, j})
-  const int ntn = do_nes ? P.ntn : 0, ntm = do_nps ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;
-  stage_zone_state(P, z, selm, Tz, etaz, zs);
-  __syncthreads();
-  const Zone& Z = zs[0];
-  if (!Z.valid) return;   // uniform: every lane reads the same zone state
-  if (!JAC)
-    for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
-  stage_factors(P, Z, smem + L.d);
-  const Units U = task_units(ntn, ntm, ntp);
-  const int lane = threadIdx.x & 63;
-  for (int u = U.first; u < U.nU; u += U.step) {
-    // scattering on electrons, then on positrons (the mirrored zone); one call site serves
-    // both, and without NPS the selection folds away
-    if (u < U.nN + U.nM) {
-      const bool mir = NPS && u >= U.nN;
-      const int pos = ((mir ? u - U.nN : u) << 6) + lane;
-      if (pos < (mir ? ntm : ntn)) scattering_fwd<R>(P, tab, zs[mir ? 1 : 0], smem + (mir ? L.m : L.q), pos);
-    } else {
-      const int pos = ((u - U.nN - U.nM) << 6) + lane;
-      if (pos < ntp) {
-        const int t = P.task_order[Z.k * P.ntn + pos], ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
-        const Q4 q = task_forward<R, true>(P, tab, Z, t);
-        double* o = smem + L.p + 2 * (i * ne + j);
-        o[0] = q.a;
-        o[1] = q.b;
-        o = smem + L.p + 2 * (j * ne + i);   // the same slot on the diagonal, same values
-        o[0] = q.c;
-        o[1] = q.d;
-      }
-    }
-  }
-  __syncthreads();
-  if (JAC) {
-    zone_jacobian<NPS>(P, Z, smem, jac);
-    return;
-  }
-  // completion, species combination and contraction: one lane per (part, bin i) runs all
-  // three species over a part of j, so each (i, j) pair's task values, detailed-balance
-  // factors and weights are read and combined once; the parts are added in order
-  const int npb = bin_parts(ne);
-  double* s_part = smem + L.d + 2 * n2;   // [part][i][species][eta0, chi0, eta1, chi1]
+  const int npb = bin_parts(ne);   // s_part: [part][i][species][eta0, chi0, eta1, chi1]
   for (int r = threadIdx.x; r < npb * ne; r += blockDim.x) {
     const int part = r / ne, i = r - part * ne;
     const int j0 = part * ne / npb, j1 = (part + 1) * ne / npb;
@@ -815,6 +761,72 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
     eta_out[out + ne] = e1;
     chi_out[out + ne] = c1;
   }
+}
+
+// Scattering task at position pos of the zone's task order: its four values into its slot.
+template <typename R>
+__device__ __forceinline__ void scattering_fwd(const DevPlan& P, const R* tab, const Zone& Z, double* slots,
+                                               int pos) {
+  const int t = P.task_order[Z.k * P.ntn + pos];
+  const Q4 q = task_forward<R, false>(P, tab, Z, t);
+  double* o = slots + 4 * t;
+  o[0] = q.a;
+  o[1] = q.b;
+  o[2] = q.c;
+  o[3] = q.d;
+}
+
+// Forward of one zone: task values into LDS, then the contraction with f into eta, chi, or
+// (JAC) the explicit Jacobian blocks, which need no f, and the contraction as well when
+// eta_out is given.
+template <typename R, bool JAC, bool NPS>
+__device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* smem, int64_t z, int selm,
+                             const double* __restrict__ Tz, const double* __restrict__ etaz,
+                             const double* __restrict__ f, double* __restrict__ eta_out,
+                             double* __restrict__ chi_out, double* __restrict__ jac) {
+  const int ne = P.ne, n2 = ne * ne;
+  const Lay L = layout<NPS>(P, 6 * ne);
+  const bool do_nes = P.processes & VTX_NES, do_nps = NPS && (P.processes & VTX_NPS),
+             do_pair = P.processes & VTX_PAIR;
+  // task counts: scattering tasks (i >= j) on electrons and on positrons, pair tasks (one per
+  // unordered pair {i, j})
+  const int ntn = do_nes ? P.ntn : 0, ntm = do_nps ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;
+  stage_zone_state(P, z, selm, Tz, etaz, zs);
+  __syncthreads();
+  const Zone& Z = zs[0];
+  if (!Z.valid) return;   // uniform: every lane reads the same zone state
+  if (!JAC || eta_out != nullptr)
+    for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
+  stage_factors(P, Z, smem + L.d);
+  const Units U = task_units(ntn, ntm, ntp);
+  const int lane = threadIdx.x & 63;
+  for (int u = U.first; u < U.nU; u += U.step) {
+    // scattering on electrons, then on positrons (the mirrored zone); one call site serves
+    // both, and without NPS the selection folds away
+    if (u < U.nN + U.nM) {
+      const bool mir = NPS && u >= U.nN;
+      const int pos = ((mir ? u - U.nN : u) << 6) + lane;
+      if (pos < (mir ? ntm : ntn)) scattering_fwd<R>(P, tab, zs[mir ? 1 : 0], smem + (mir ? L.m : L.q), pos);
+    } else {
+      const int pos = ((u - U.nN - U.nM) << 6) + lane;
+      if (pos < ntp) {
+        const int t = P.task_order[Z.k * P.ntn + pos], ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
+        const Q4 q = task_forward<R, true>(P, tab, Z, t);
+        double* o = smem + L.p + 2 * (i * ne + j);
+        o[0] = q.a;
+        o[1] = q.b;
+        o = smem + L.p + 2 * (j * ne + i);   // the same slot on the diagonal, same values
+        o[0] = q.c;
+        o[1] = q.d;
+      }
+    }
+  }
+  __syncthreads();
+  if (JAC) {
+    zone_jacobian<NPS>(P, Z, smem, jac);
+    if (eta_out == nullptr) return;   // uniform: a kernel argument
+  }
+  zone_contract<NPS>(P, Z, smem, L, smem + L.d + 2 * n2, eta_out, chi_out);
 }
 
 // Dense pass: workgroup b takes zone b (if selected). Occupancy targets: four waves per SIMD
@@ -1265,12 +1277,15 @@ __device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, co
 // Task units of one zone, at most: 3 ceil(528/64) at 32 bins.
 constexpr int kMaxUnits = 32;
 
-template <typename R, bool NPS>
+// Backward of one zone; FUSED also contracts the recomputed task values with f into eta, chi
+// (forward and backward in one pass).
+template <typename R, bool NPS, bool FUSED>
 __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* red, double* smem, int64_t z,
                               int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
                               const double* __restrict__ f, const double* __restrict__ g_eta,
                               const double* __restrict__ g_chi, double* __restrict__ gT_out,
-                              double* __restrict__ gE_out, double* __restrict__ gf_out) {
+                              double* __restrict__ gE_out, double* __restrict__ gf_out, double* __restrict__ eta_out,
+                              double* __restrict__ chi_out) {
   const int ne = P.ne, n2 = ne * ne;
   const bool do_nes = P.processes & VTX_NES, do_nps = NPS && (P.processes & VTX_NPS),
              do_pair = P.processes & VTX_PAIR;
@@ -1402,31 +1417,39 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
     gf_out[zo + (2 * sg) * ne + j] = a0;
     gf_out[zo + (2 * sg + 1) * ne + j] = a1;
   }
+  if (FUSED) {
+    // the task values and f are still in LDS; the contraction parts reuse the g_f parts and
+    // the per-lane slots behind them, once every lane has read its g_f parts
+    __syncthreads();
+    zone_contract<NPS>(P, Z, smem, L, smem + L.d + 2 * n2, eta_out, chi_out);
+  }
 }
 
 // Occupancy targets: three waves per SIMD for the FP32 backward (at most 168 VGPRs), two
 // for the FP64 one.
-template <typename R, bool NPS>
+template <typename R, bool NPS, bool FUSED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
 void rates_backward_kernel(
     DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
     const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
-    double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out) {
+    double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out,
+    double* __restrict__ eta_out, double* __restrict__ chi_out) {
   __shared__ R tab[kTabLen];
   __shared__ Zone zs[2];
   __shared__ double red[2 * kMaxUnits];
   extern __shared__ double smem[];
   stage_tab<R>(P, tab);
   const int64_t z = blockIdx.x;
-  zone_backward<R, NPS>(P, tab, zs, red, smem, z < nz ? z : -1, selm, Tz, etaz, f, g_eta, g_chi, gT_out, gE_out,
-                   gf_out);
+  zone_backward<R, NPS, FUSED>(P, tab, zs, red, smem, z < nz ? z : -1, selm, Tz, etaz, f, g_eta, g_chi, gT_out,
+                               gE_out, gf_out, eta_out, chi_out);
 }
 
-template <bool NPS>
+template <bool NPS, bool FUSED>
 __global__ __launch_bounds__(kBlock) void rates_backward_sparse(
     DevPlan P, int64_t nz, const double* __restrict__ Tz, const double* __restrict__ etaz,
     const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
-    double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out) {
+    double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out,
+    double* __restrict__ eta_out, double* __restrict__ chi_out) {
   __shared__ double tab[kTabLen];
   __shared__ Zone zs[2];
   __shared__ double red[2 * kMaxUnits];
@@ -1442,8 +1465,8 @@ __global__ __launch_bounds__(kBlock) void rates_backward_sparse(
     __syncthreads();
     const int n = count;
     for (int c = 0; c < n; ++c) {
-      zone_backward<double, NPS>(P, tab, zs, red, smem, base + list[c], kSelAll, Tz, etaz, f, g_eta, g_chi, gT_out,
-                            gE_out, gf_out);
+      zone_backward<double, NPS, FUSED>(P, tab, zs, red, smem, base + list[c], kSelAll, Tz, etaz, f, g_eta, g_chi,
+                                        gT_out, gE_out, gf_out, eta_out, chi_out);
       __syncthreads();
     }
     __syncthreads();   // every lane has read count before the next window resets it
@@ -1458,9 +1481,13 @@ int task_values(const DevPlan& P) {
 size_t zone_lds_fwd(const DevPlan& P) {
   return sizeof(double) * (6 * P.ne + task_values(P) + 2 * P.ne * P.ne + 48 * P.ne);
 }
-// The backward adds 13 values per lane of the bulk type (elem bytes) for the pair tasks.
-size_t zone_lds_bwd(const DevPlan& P, size_t elem) {
-  return sizeof(double) * (18 * P.ne + task_values(P) + 2 * P.ne * P.ne + 24 * P.ne) + 13 * kBlock * elem;
+// The backward adds 13 values per lane of the bulk type (elem bytes) for the pair tasks; the
+// fused forward + backward reuses them for the forward's contraction parts (48 ne doubles).
+size_t zone_lds_bwd(const DevPlan& P, size_t elem, bool fused) {
+  const size_t head = sizeof(double) * (18 * P.ne + task_values(P) + 2 * P.ne * P.ne);
+  const size_t bwd = head + sizeof(double) * 24 * P.ne + 13 * kBlock * elem;
+  const size_t fwd = head + sizeof(double) * 48 * P.ne;
+  return fused && fwd > bwd ? fwd : bwd;
 }
 
 // Dynamic LDS beyond the 64 KiB default must be requested per kernel.
@@ -1509,36 +1536,41 @@ hipError_t forward_slice(const DevPlan& P, int64_t nz, const double* T, const do
                                  : forward_slice_t<false>(P, nz, T, eta_e, f, eta, chi, jac, s);
 }
 
-template <bool NPS>
+template <bool NPS, bool FUSED>
 hipError_t backward_slice_t(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
                             const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
-                            hipStream_t s) {
-  const size_t lds32 = zone_lds_bwd(P, sizeof(float)), lds64 = zone_lds_bwd(P, sizeof(double));
+                            double* eta, double* chi, hipStream_t s) {
+  const size_t lds32 = zone_lds_bwd(P, sizeof(float), FUSED), lds64 = zone_lds_bwd(P, sizeof(double), FUSED);
   const dim3 grid((unsigned)nz), block(kBlock);
   hipError_t e;
   if (P.precision == VTX_MIXED) {
-    auto bulk = rates_backward_kernel<float, NPS>;
-    auto sparse = rates_backward_sparse<NPS>;
+    auto bulk = rates_backward_kernel<float, NPS, FUSED>;
+    auto sparse = rates_backward_sparse<NPS, FUSED>;
     if ((e = allow_lds(bulk, lds32)) != hipSuccess) return e;
-    hipLaunchKernelGGL(bulk, grid, block, lds32, s, P, nz, kSelBulk, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f);
+    hipLaunchKernelGGL(bulk, grid, block, lds32, s, P, nz, kSelBulk, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f,
+                       eta, chi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = allow_lds(sparse, lds64)) != hipSuccess) return e;
     hipLaunchKernelGGL(sparse, dim3(sparse_grid(nz)), block, lds64, s, P, nz, T, eta_e, f, g_eta, g_chi, g_T,
-                       g_eta_e, g_f);
+                       g_eta_e, g_f, eta, chi);
   } else {
-    auto dense = rates_backward_kernel<double, NPS>;
+    auto dense = rates_backward_kernel<double, NPS, FUSED>;
     if ((e = allow_lds(dense, lds64)) != hipSuccess) return e;
-    hipLaunchKernelGGL(dense, grid, block, lds64, s, P, nz, kSelAll, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f);
+    hipLaunchKernelGGL(dense, grid, block, lds64, s, P, nz, kSelAll, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f,
+                       eta, chi);
   }
   return hipGetLastError();
 }
 
 hipError_t backward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
                           const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
-                          hipStream_t s) {
-  return (P.processes & VTX_NPS)
-             ? backward_slice_t<true>(P, nz, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, s)
-             : backward_slice_t<false>(P, nz, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, s);
+                          double* eta, double* chi, hipStream_t s) {
+  const bool nps = P.processes & VTX_NPS;
+  if (eta)
+    return nps ? backward_slice_t<true, true>(P, nz, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s)
+               : backward_slice_t<false, true>(P, nz, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s);
+  return nps ? backward_slice_t<true, false>(P, nz, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s)
+             : backward_slice_t<false, false>(P, nz, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s);
 }
 
 }  // namespace
@@ -1555,12 +1587,14 @@ hipError_t launch_forward(const DevPlan& P, int64_t nz, const double* T, const d
   return hipSuccess;
 }
 
-hipError_t launch_jacobian(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, double* jac,
-                           hipStream_t s) {
-  const int64_t js = 24 * P.ne * P.ne;
+hipError_t launch_jacobian(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                           double* eta, double* chi, double* jac, hipStream_t s) {
+  const int64_t js = 24 * P.ne * P.ne, zs = 6 * P.ne;
   for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
     const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
-    const hipError_t e = forward_slice(P, n, T + z0, eta_e + z0, nullptr, nullptr, nullptr, jac + z0 * js, s);
+    const hipError_t e = eta ? forward_slice(P, n, T + z0, eta_e + z0, f + z0 * zs, eta + z0 * zs, chi + z0 * zs,
+                                             jac + z0 * js, s)
+                             : forward_slice(P, n, T + z0, eta_e + z0, nullptr, nullptr, nullptr, jac + z0 * js, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1573,7 +1607,20 @@ hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const 
   for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
     const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
     const hipError_t e = backward_slice(P, n, T + z0, eta_e + z0, f + z0 * zs, g_eta + z0 * zs, g_chi + z0 * zs,
-                                        g_T + z0, g_eta_e + z0, g_f + z0 * zs, s);
+                                        g_T + z0, g_eta_e + z0, g_f + z0 * zs, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_forward_backward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e,
+                                   const double* f, const double* g_eta, const double* g_chi, double* eta,
+                                   double* chi, double* g_T, double* g_eta_e, double* g_f, hipStream_t s) {
+  const int64_t zs = 6 * P.ne;
+  for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
+    const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
+    const hipError_t e = backward_slice(P, n, T + z0, eta_e + z0, f + z0 * zs, g_eta + z0 * zs, g_chi + z0 * zs,
+                                        g_T + z0, g_eta_e + z0, g_f + z0 * zs, eta + z0 * zs, chi + z0 * zs, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -52,8 +52,10 @@ def library():
     lib.vtx_rates_backward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64,
                                        vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.vtx_rates_backward.restype = ctypes.c_int
-    lib.vtx_rates_jacobian.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp]
+    lib.vtx_rates_jacobian.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp, vp, vp, vp]
     lib.vtx_rates_jacobian.restype = ctypes.c_int
+    lib.vtx_rates_forward_backward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64] + [vp] * 11
+    lib.vtx_rates_forward_backward.restype = ctypes.c_int
     lib.vtx_strerror.argtypes = [ctypes.c_int]
     lib.vtx_strerror.restype = ctypes.c_char_p
     lib.vtx_abi_version.argtypes = []
@@ -165,18 +167,47 @@ def backward(grid: GridHandle, opts: Opts, T, eta_e, f, g_eta, g_chi, g_T=None, 
     return g_T, g_eta_e, g_f
 
 
-def jacobian(grid: GridHandle, opts: Opts, T, eta_e, jac=None, stream=None):
-    """Explicit blocks jac[nz, 3, 2, 4, ne, ne] = d(eta, chi)/df (layout in include/vtx_rates.h)."""
+def jacobian(grid: GridHandle, opts: Opts, T, eta_e, jac=None, stream=None, f=None):
+    """Explicit blocks jac[nz, 3, 2, 4, ne, ne] = d(eta, chi)/df (layout in include/vtx_rates.h).
+    With f given, returns (jac, eta, chi) from the same call."""
     import torch
     nz = T.shape[0]
     shp = (nz, 3, 2, 4, grid.ne, grid.ne)
+    fs = (nz, 3, 2, grid.ne)
     if jac is None:
         jac = torch.empty(shp, dtype=torch.float64, device=T.device)
+    eta = chi = None
+    pf = pe = pc = None
+    if f is not None:
+        eta = torch.empty(fs, dtype=torch.float64, device=T.device)
+        chi = torch.empty(fs, dtype=torch.float64, device=T.device)
+        pf, pe, pc = _dev_ptr(f, "f", fs), _dev_ptr(eta, "eta", fs), _dev_ptr(chi, "chi", fs)
     rc = library().vtx_rates_jacobian(ctypes.byref(grid.c), ctypes.byref(opts), nz, _dev_ptr(T, "T", (nz,)),
-                                      _dev_ptr(eta_e, "eta_e", (nz,)), _dev_ptr(jac, "jac", shp),
+                                      _dev_ptr(eta_e, "eta_e", (nz,)), pf, pe, pc, _dev_ptr(jac, "jac", shp),
                                       _stream_handle(stream))
     _check(rc, "vtx_rates_jacobian")
-    return jac
+    return jac if f is None else (jac, eta, chi)
+
+
+def forward_backward(grid: GridHandle, opts: Opts, T, eta_e, f, g_eta, g_chi, out=None, stream=None):
+    """(eta, chi, g_T, g_eta_e, g_f) in one pass (vtx_rates_forward_backward)."""
+    import torch
+    nz = T.shape[0]
+    shp = (nz, 3, 2, grid.ne)
+    if out is None:
+        out = (torch.empty(shp, dtype=torch.float64, device=T.device),
+               torch.empty(shp, dtype=torch.float64, device=T.device),
+               torch.empty((nz,), dtype=torch.float64, device=T.device),
+               torch.empty((nz,), dtype=torch.float64, device=T.device),
+               torch.empty(shp, dtype=torch.float64, device=T.device))
+    eta, chi, gT, gE, gf = out
+    rc = library().vtx_rates_forward_backward(
+        ctypes.byref(grid.c), ctypes.byref(opts), nz, _dev_ptr(T, "T", (nz,)), _dev_ptr(eta_e, "eta_e", (nz,)),
+        _dev_ptr(f, "f", shp), _dev_ptr(g_eta, "g_eta", shp), _dev_ptr(g_chi, "g_chi", shp),
+        _dev_ptr(eta, "eta", shp), _dev_ptr(chi, "chi", shp), _dev_ptr(gT, "g_T", (nz,)),
+        _dev_ptr(gE, "g_eta_e", (nz,)), _dev_ptr(gf, "g_f", shp), _stream_handle(stream))
+    _check(rc, "vtx_rates_forward_backward")
+    return out
 
 
 def gauss_rule(kind: int, n: int):

@@ -52,9 +52,15 @@ def _call_bwd(grid, opts, nz, ptr=1):
     return lib.vtx_rates_backward(ctypes.byref(grid.c), ctypes.byref(opts), nz, p, p, p, p, p, p, p, p, None)
 
 
-def _call_jac(grid, opts, nz, ptr=1):
+def _call_jac(grid, opts, nz, ptr=1, outs=False):
     p = ctypes.c_void_p(ptr) if ptr else None
-    return lib.vtx_rates_jacobian(ctypes.byref(grid.c), ctypes.byref(opts), nz, p, p, p, None)
+    q = p if outs else None
+    return lib.vtx_rates_jacobian(ctypes.byref(grid.c), ctypes.byref(opts), nz, p, p, q, q, q, p, None)
+
+
+def _call_fb(grid, opts, nz, ptr=1):
+    p = ctypes.c_void_p(ptr) if ptr else None
+    return lib.vtx_rates_forward_backward(ctypes.byref(grid.c), ctypes.byref(opts), nz, *([p] * 11), None)
 
 
 def test_invalid_arguments():
@@ -69,6 +75,12 @@ def test_invalid_arguments():
     assert _call_jac(g, o, 4, ptr=0) == vtx.VTX_EINVAL
     assert _call_jac(g, o, -1) == vtx.VTX_EINVAL
     assert _call_jac(g, o, 0) == vtx.VTX_OK
+    p1 = ctypes.c_void_p(1)   # f given without eta, chi
+    assert lib.vtx_rates_jacobian(ctypes.byref(g.c), ctypes.byref(o), 4, p1, p1, p1, None, None, p1,
+                                  None) == vtx.VTX_EINVAL
+    assert _call_fb(g, o, 4, ptr=0) == vtx.VTX_EINVAL
+    assert _call_fb(g, o, -1) == vtx.VTX_EINVAL
+    assert _call_fb(g, o, 0) == vtx.VTX_OK
     for field, bad in [("nquad", 6), ("nquad", 50), ("nquad", 68), ("rule", 2), ("precision", 3),
                        ("processes", 0), ("processes", 8), ("sin2w", float("nan"))]:
         ob = vtx.make_opts()
@@ -95,6 +107,8 @@ def test_no_device_is_reported():
     assert _call_fwd(vtx.GridHandle(eps, w), vtx.make_opts(), 4) == vtx.VTX_EDEVICE
     assert _call_bwd(vtx.GridHandle(eps, w), vtx.make_opts(), 4) == vtx.VTX_EDEVICE
     assert _call_jac(vtx.GridHandle(eps, w), vtx.make_opts(), 4) == vtx.VTX_EDEVICE
+    assert _call_jac(vtx.GridHandle(eps, w), vtx.make_opts(), 4, outs=True) == vtx.VTX_EDEVICE
+    assert _call_fb(vtx.GridHandle(eps, w), vtx.make_opts(), 4) == vtx.VTX_EDEVICE
 
 
 def test_fault_injection_reports_hip_error(monkeypatch):

@@ -175,3 +175,19 @@ def test_large_chunk_sampled():
                   orates.jacobian(sub.eps, sub.w, sub.T, sub.eta_e, o, absolute=True)).max()
     say(f"    sampled {len(idx)} zones, max rel err {err:.2e}")
     assert np.all(np.isfinite(J)) and err <= MIXED_TOL
+
+
+@pytest.mark.parametrize("precision,processes", [("fp64", 3), ("mixed", 3), ("mixed", 7)])
+def test_jacobian_with_outputs(precision, processes):
+    """The Jacobian call given f also returns eta, chi: equal bit for bit to the forward, and
+    the blocks equal to the Jacobian-only call."""
+    inp = synth.make_inputs("medium", nzones=11)
+    inp.eta_e[:2] = [-4.0, 70.0]          # a mirrored task order; the FP64 pass when mixed
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, 48, "panel", processes)
+    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
+    J0 = vtx.jacobian(grid, opts, T, E)
+    J1, e1, c1 = vtx.jacobian(grid, opts, T, E, f=f)
+    e0, c0 = vtx.forward(grid, opts, T, E, f)
+    torch.cuda.synchronize()
+    assert torch.equal(J0, J1) and torch.equal(e0, e1) and torch.equal(c0, c1)

@@ -378,3 +378,30 @@ def test_launch_slicing_over_2_22_zones():
     torch.cuda.synchronize()
     for a, b in zip(full, [t.cpu().numpy() for t in (e1, c1) + tuple(g1)]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision,processes", [("fp64", 3), ("mixed", 3), ("mixed", 7), ("fp64", 7)])
+def test_forward_backward_fused(precision, processes):
+    """vtx_rates_forward_backward: gradients bit for bit those of the backward; eta, chi within
+    rounding of the forward (the kernels come from the backward's quadrature loop) and within
+    the bars of the oracle."""
+    inp = synth.make_inputs("medium", nzones=14)
+    inp.eta_e[:3] = [-6.0, 20.0, 66.0]     # the last takes the FP64 pass when mixed
+    ge, gc = synth.random_gradients(14, inp.eps.shape[0], 15)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, 48, "panel", processes)
+    T, E, f, Ge, Gc = (to_dev(a) for a in (inp.T, inp.eta_e, inp.f, ge, gc))
+    say(f"[gpu] fused forward+backward {precision} processes={processes}")
+    eta, chi, gT, gE, gf = vtx.forward_backward(grid, opts, T, E, f, Ge, Gc)
+    e0, c0 = vtx.forward(grid, opts, T, E, f)
+    b = vtx.backward(grid, opts, T, E, f, Ge, Gc)
+    torch.cuda.synchronize()
+    for x, y in zip((gT, gE, gf), b):
+        assert torch.equal(x, y)
+    re, rc, ae, ac = oracle_forward(inp, 48, "panel", processes)
+    e, c = eta.cpu().numpy(), chi.cpu().numpy()
+    close = max(rel_err(e, e0.cpu().numpy(), ae).max(), rel_err(c, c0.cpu().numpy(), ac).max())
+    err = max(rel_err(e, re, ae).max(), rel_err(c, rc, ac).max())
+    say(f"    vs forward {close:.2e}, vs oracle {err:.2e}")
+    assert close <= (1e-12 if precision == "fp64" else 1e-5)
+    assert err <= (FP64_TOL if precision == "fp64" else MIXED_TOL)
