@@ -435,6 +435,11 @@ def main():
     value = units / t_step
     t_fwd, t_bwd, zl = run.launch_times()
     errors = None if args.no_errors else sampled_errors(inp, run.eta, run.chi, wl)
+    streaming = None
+    if args.stream_steps > 0:
+        print(f"[bench] streaming from pinned host memory: {args.stream_steps} steps", file=sys.stderr, flush=True)
+        streaming = streaming_leg(run, units, args.stream_steps, 1)
+    # after the streaming leg: it compares its outputs with this run's separate-call ones
     fused = None
     if args.fused_steps > 0:
         print(f"[bench] fused forward+backward: {args.fused_steps} steps", file=sys.stderr, flush=True)
@@ -442,10 +447,6 @@ def main():
         fused = {"value": units / tf, "unit": "zone*(eps,eps')/s", "ms_per_step": tf * 1e3,
                  "note": "vtx_rates_forward_backward: one call per chunk computes eta, chi and the VJP; "
                          "for callers holding g_eta, g_chi before the forward values"}
-    streaming = None
-    if args.stream_steps > 0:
-        print(f"[bench] streaming from pinned host memory: {args.stream_steps} steps", file=sys.stderr, flush=True)
-        streaming = streaming_leg(run, units, args.stream_steps, 1)
     del run
     torch.cuda.empty_cache()
 
