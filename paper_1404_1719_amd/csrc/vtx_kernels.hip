@@ -342,6 +342,14 @@ __device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, c
   return Es;
 }
 
+// A group of zero width whose end points do not move with T or eta_e (a clamped or coinciding
+// breakpoint) adds exactly nothing to the task's values or derivatives. A wave skips its node
+// loop when that holds on every lane, which leaves every result as it was.
+__device__ __forceinline__ bool wave_skips(const GroupDesc& G) {
+  const bool dead = !G.lag && G.hi.v == G.lo.v && G.hi.dT == G.lo.dT && G.hi.dE == G.lo.dE;
+  return __all(dead);
+}
+
 // The variant a wave runs for a group: the lanes' common mode, else the general one. The
 // general loop reproduces the low and high loops bit for bit on lanes of those modes
 // (explicit fma, exact zeros), so results never depend on which lanes share a wave.
@@ -492,6 +500,7 @@ __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const
     const Tri zero = {0.0, 0.0, 0.0};
     const Tri lo = g == 0 ? zero : group_hi<PAIR>(K, Bk, g - 1);
     const GroupDesc G = describe<PAIR>(P, K, Bk, g, lo, group_hi<PAIR>(K, Bk, g));
+    if (wave_skips(G)) continue;
     Loop<R> L;
     const double Es = make_loop<R>(K, G, Z, L);
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0};
@@ -1181,6 +1190,7 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
     const Tri hi = group_hi<PAIR>(K, Bk, g);
     const GroupDesc G = describe<PAIR>(P, K, Bk, g, lo, hi);
     lo = hi;
+    if (wave_skips(G)) continue;
     Loop<R> L;
     const double Es = make_loop<R>(K, G, Z, L);
     if (PAIR) {
