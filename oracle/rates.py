@@ -135,17 +135,32 @@ def pair_quadrature(eps, T, mu, opts, absolute=False):
     return np.stack(out, axis=-1).reshape(T.shape[0], ne, ne, 2)
 
 
-def zone_kernels(eps, T, eta_e, opts, absolute=False):
-    """S-split kernels after completion: dict of arrays [z, i, j, S, l] (S index 0 = I)."""
+def task_quadratures(eps, T, eta_e, opts, absolute=False):
+    """Steps 1 and 3 only: the quadratures before completion, dict with "nes" / "nps"
+    q[z, t, S, l] (tasks t = (i >= j)) and "pair" A[z, i, j, l]."""
     eps = np.asarray(eps, dtype=float)
     T = np.asarray(T)
     mu = np.asarray(eta_e) * T
-    ne = eps.shape[0]
-    nz = T.shape[0]
     out = {}
     for bit, name, m in ((PROC_NES, "nes", mu), (PROC_NPS, "nps", -mu)):
         if opts.processes & bit:
-            q = scattering_quadrature(eps, T, m, opts, absolute)
+            out[name] = scattering_quadrature(eps, T, m, opts, absolute)
+    if opts.processes & PROC_PAIR:
+        out["pair"] = pair_quadrature(eps, T, mu, opts, absolute)
+    return out
+
+
+def complete(eps, T, quad):
+    """Steps 2 and 3's completion from the quadratures of ``task_quadratures``: S-split
+    kernels after completion, dict of arrays [z, i, j, S, l] (S index 0 = I)."""
+    eps = np.asarray(eps, dtype=float)
+    T = np.asarray(T)
+    ne = eps.shape[0]
+    out = {}
+    for name in ("nes", "nps"):
+        if name in quad:
+            q = quad[name]
+            nz = q.shape[0]
             ii, jj = nes_tasks(ne)
             full = np.zeros((nz, ne, ne, 2, 2), dtype=q.dtype)
             full[:, ii, jj] = q
@@ -156,13 +171,18 @@ def zone_kernels(eps, T, eta_e, opts, absolute=False):
             phi_out = np.where(upper[None, :, :, None, None], up[..., None, None] * trans, full)
             out[name + "_out"] = phi_out
             out[name + "_in"] = np.swapaxes(phi_out, 1, 2)
-    if opts.processes & PROC_PAIR:
-        A = pair_quadrature(eps, T, mu, opts, absolute)
+    if "pair" in quad:
+        A = quad["pair"]
         phi_a = np.stack([A, np.swapaxes(A, 1, 2)], axis=-2)  # [z, i, j, S, l]
         prod = np.exp(-(eps[None, :, None] + eps[None, None, :]) / T[:, None, None])
         out["pair_a"] = phi_a
         out["pair_p"] = prod[..., None, None] * phi_a
     return out
+
+
+def zone_kernels(eps, T, eta_e, opts, absolute=False):
+    """S-split kernels after completion: dict of arrays [z, i, j, S, l] (S index 0 = I)."""
+    return complete(eps, T, task_quadratures(eps, T, eta_e, opts, absolute))
 
 
 def _species(kern, beta):
