@@ -12,6 +12,10 @@ Export layout of one zone's quadratures (the order in which the library writes t
   scattering on positrons likewise (4 ntn, when PROC_NPS), pair A[i][j][l] (2 ne^2).
 Lattice: node (a, b), a < nt, b < nh, at ln T = lnT0 + a dlnT, eta_e = eta0 + b deta; its
 row in the table is a nh + b.
+Interpolation variables: the layout holds each (task, S) as the pair (l = 0, l = 1), adjacent.
+Phi_0 is positive and varies exponentially with 1/T and eta_e; |Phi_1| <= Phi_0 because
+|P_1| <= 1 under a nonnegative rate. A pair (x0, x1) is interpolated as (ln x0, x1/x0) (x0 <= 0,
+only from underflow, enters as (ln 1e-300, 0)) and mapped back by x0 = exp(y0), x1 = y1 x0.
 Interpolation: bilinear in s = (ln T - lnT0)/dlnT and r = (eta_e - eta0)/deta on the cell
 a = clip(floor(s), 0, nt - 2), b = clip(floor(r), 0, nh - 2), with u = s - a, v = r - b
 (outside the lattice this extrapolates linearly from the edge cell).
@@ -90,7 +94,25 @@ def build(eps, lat, opts, chunk=32):
     return np.concatenate(rows)
 
 
-def interpolate(table, lat, T, eta_e):
+def to_interp_vars(x):
+    """(x0, x1) pairs -> (ln x0, x1 / x0)."""
+    x0, x1 = x[..., 0::2], x[..., 1::2]
+    pos = x0 > 0
+    y = np.empty_like(x)
+    y[..., 0::2] = np.log(np.where(pos, x0, 1e-300))
+    y[..., 1::2] = np.where(pos, x1 / np.where(pos, x0, 1.0), 0.0)
+    return y
+
+
+def from_interp_vars(y):
+    x = np.empty_like(y)
+    x0 = np.exp(y[..., 0::2])
+    x[..., 0::2] = x0
+    x[..., 1::2] = y[..., 1::2] * x0
+    return x
+
+
+def bilinear(table, lat, T, eta_e):
     """Bilinear interpolation of the table rows at zone states (T, eta_e): [z, values]."""
     s = (np.log(np.asarray(T, dtype=float)) - lat.lnT0) / lat.dlnT
     r = (np.asarray(eta_e, dtype=float) - lat.eta0) / lat.deta
@@ -103,6 +125,11 @@ def interpolate(table, lat, T, eta_e):
     t01 = table[a * lat.nh + b + 1]
     t11 = table[(a + 1) * lat.nh + b + 1]
     return (1 - u) * (1 - v) * t00 + u * (1 - v) * t10 + (1 - u) * v * t01 + u * v * t11
+
+
+def interpolate(table, lat, T, eta_e):
+    """Task values at zone states (T, eta_e), interpolated in (ln x0, x1/x0): [z, values]."""
+    return from_interp_vars(bilinear(to_interp_vars(table), lat, T, eta_e))
 
 
 def forward(eps, w, lat, table, T, eta_e, f, opts=rates.Options()):

@@ -132,11 +132,11 @@ def test_positron_scattering_with_electron_potential(monkeypatch):
 def test_interpolation_with_swapped_fractions(monkeypatch):
     import oracle.tabulated as tab
     import test_oracle_tabulated as pins_tab
-    orig = tab.interpolate
+    orig = tab.bilinear
 
     def bad(table, lat, T, eta_e):
         flip = tab.Lattice(lat.nt, lat.nh, lat.lnT0, lat.dlnT * 1.0000001, lat.eta0, lat.deta)
         return orig(table, flip, T, eta_e)
-    monkeypatch.setattr(tab, "interpolate", bad)
+    monkeypatch.setattr(tab, "bilinear", bad)
     with pytest.raises(AssertionError):
         pins_tab.test_exact_on_bilinear_data()

@@ -34,19 +34,27 @@ def test_nodes_reproduce_the_direct_rates():
 
 
 def test_exact_on_bilinear_data():
+    """Data bilinear in the lattice coordinates are reproduced exactly by ``bilinear``; pairs
+    with ln x0 and x1/x0 bilinear (exponential dependence) exactly by ``interpolate``."""
     lat = tabulated.Lattice(nt=5, nh=7, lnT0=-0.5, dlnT=0.3, eta0=-2.0, deta=1.5)
     rng = np.random.default_rng(3)
-    al, be, ga, de = rng.normal(size=(4, 9))
+    al, be, ga, de = rng.normal(size=(4, 10))
     a, b = np.meshgrid(np.arange(lat.nt), np.arange(lat.nh), indexing="ij")
     s, r = a.ravel()[:, None], b.ravel()[:, None]
-    table = al + be * s + ga * r + de * s * r
+    lin = al + be * s + ga * r + de * s * r
     T = np.exp(rng.uniform(-1.5, 2.0, 50))          # inside and outside the lattice
     eta = rng.uniform(-5.0, 12.0, 50)
-    got = tabulated.interpolate(table, lat, T, eta)
     s = ((np.log(T) - lat.lnT0) / lat.dlnT)[:, None]
     r = ((eta - lat.eta0) / lat.deta)[:, None]
     ref = al + be * s + ga * r + de * s * r
-    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
+    assert np.allclose(tabulated.bilinear(lin, lat, T, eta), ref, rtol=1e-12, atol=1e-12)
+    table = np.empty_like(lin)
+    table[:, 0::2] = np.exp(lin[:, 0::2])
+    table[:, 1::2] = lin[:, 1::2] * table[:, 0::2]
+    got = tabulated.interpolate(table, lat, T, eta)
+    x0 = np.exp(ref[:, 0::2])
+    assert np.allclose(got[:, 0::2], x0, rtol=1e-12, atol=0)
+    assert np.allclose(got[:, 1::2], ref[:, 1::2] * x0, rtol=1e-12, atol=1e-300)
 
 
 def test_second_order_convergence():
