@@ -388,6 +388,82 @@ def jacobian_leg(inp, wl, precision, launches):
             "hbm_frac": written / (t * 1e-3) / 8e12, "traffic": traffic_from_profiles(tag), "kernel": tag}
 
 
+def tabulated_leg(inp, wl, precision, launches, t_direct_ms):
+    """Tabulated comparison point: task values on a (ln T, eta_e) lattice over the workload's
+    range (built by the library), interpolated per zone over one chunk, against the direct
+    forward. Errors: against the FP64 oracle's direct rates on sampled zones, with the A10
+    floor of the direct path; and over every zone of the chunk for the l = 0 outputs (which do
+    not cancel), against the library's direct forward, |y_tab - y| / max(|y|, 1e-3 max over the
+    bins of the same output)."""
+    import math
+    import torch
+    from paper_1404_1719_amd import vtx
+    nz = wl.nzones // wl.chunks
+    dev = torch.device("cuda:0")
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+    tmin, tmax = float(inp.T.min()), float(inp.T.max())
+    emin, emax = float(inp.eta_e.min()), float(inp.eta_e.max())
+    dlnT, deta = 0.1, 0.25
+    nt = int(math.ceil((math.log(tmax) - math.log(tmin)) / dlnT)) + 1
+    nh = int(math.ceil((emax - emin) / deta)) + 1
+    lat = vtx.Lattice(nt, nh, math.log(tmin), dlnT, emin, deta)
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream())
+    T = torch.from_numpy(inp.T[:nz]).to(dev)
+    E = torch.from_numpy(inp.eta_e[:nz]).to(dev)
+    f = torch.from_numpy(inp.f[:nz]).to(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    with torch.cuda.stream(s):
+        table = vtx.build_table(grid, opts, lat, stream=s)   # first build loads its kernel
+        ev[0].record(s)
+        vtx.build_table(grid, opts, lat, stream=s)
+        ev[1].record(s)
+        eta, chi = vtx.forward_interp(grid, opts, lat, table, T, E, f, stream=s)
+        ms = []
+        for _ in range(launches):
+            e2 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e2[0].record(s)
+            vtx.forward_interp(grid, opts, lat, table, T, E, f, eta, chi, stream=s)
+            e2[1].record(s)
+            ms.append(e2)
+        e0, c0 = vtx.forward(grid, opts, T, E, f, stream=s)
+    s.synchronize()
+    t = float(np.mean([a.elapsed_time(b) for a, b in ms]))
+
+    def err(y, r):
+        y, r = y[:, :, 0], r[:, :, 0]
+        d = (y - r).abs() / torch.maximum(r.abs(), 1e-3 * r.abs().amax(dim=-1, keepdim=True))
+        return {"max": d.max().item(), "median": d.median().item()}
+
+    from oracle import rates as orates
+    sub_idx = synth.sample_zones(synth.subset(inp, np.arange(nz)), 6, seed=12)
+    it = torch.from_numpy(sub_idx).to(dev)
+    te, tc = eta.index_select(0, it).cpu().numpy(), chi.index_select(0, it).cpu().numpy()
+    sub = synth.subset(inp, sub_idx)
+    re, rc, ae, ac = orates.forward_with_scale(sub.eps, sub.w, sub.T, sub.eta_e, sub.f,
+                                               orates.Options(nquad=wl.nquad, rule=wl.rule))
+
+    def a10(y, r, a):
+        return float(np.max(np.abs(y - r) / np.maximum(np.maximum(np.abs(r), 1e-3 * a), 1e-290)))
+
+    sampled = {"eta0": a10(te[:, :, 0], re[:, :, 0], ae[:, :, 0]), "eta1": a10(te[:, :, 1], re[:, :, 1], ae[:, :, 1]),
+               "chi0": a10(tc[:, :, 0], rc[:, :, 0], ac[:, :, 0]), "chi1": a10(tc[:, :, 1], rc[:, :, 1], ac[:, :, 1]),
+               "zones": len(sub_idx)}
+
+    nv = vtx.task_values(wl.ne, 3)
+    out = {"lattice": f"{nt} x {nh} nodes, d ln T = {dlnT}, d eta_e = {deta}, over the workload's range",
+           "table_bytes": table.numel() * 8, "build_ms": ev[0].elapsed_time(ev[1]),
+           "zones_per_launch": nz, "interp_launch_ms": t, "direct_forward_launch_ms": t_direct_ms,
+           "bytes_read_per_launch": nz * (4 * nv * 8 + 16 + 1008), "bytes_written_per_launch": nz * 2016,
+           "rel_err_vs_oracle_sampled": sampled,
+           "l0_err_vs_direct_all_zones": {"eta0": err(eta, e0), "chi0": err(chi, c0)}}
+    out["read_GBps"] = out["bytes_read_per_launch"] / (t * 1e-3) / 1e9
+    del table, eta, chi, e0, c0
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +478,8 @@ def main():
                     help="steps of the pinned-host streaming run, PCIe included (0: skip)")
     ap.add_argument("--fused-steps", type=int, default=2,
                     help="steps with forward and backward fused in one call per chunk (0: skip)")
+    ap.add_argument("--tabulated-launches", type=int, default=3,
+                    help="timed launches of the tabulated comparison over one chunk (0: skip)")
     ap.add_argument("--positron-steps", type=int, default=2,
                     help="steps of the run with neutrino-positron scattering added (0: skip)")
     ap.add_argument("--jacobian-launches", type=int, default=3,
@@ -483,6 +561,11 @@ def main():
         del runp
         torch.cuda.empty_cache()
 
+    tabulated = None
+    if args.tabulated_launches > 0:
+        print(f"[bench] tabulated kernels: {args.tabulated_launches} launches", file=sys.stderr, flush=True)
+        tabulated = tabulated_leg(inp, wl, precision, args.tabulated_launches, t_fwd)
+
     jac = None
     if args.jacobian_launches > 0:
         print(f"[bench] explicit Jacobian: {args.jacobian_launches} launches", file=sys.stderr, flush=True)
@@ -503,7 +586,7 @@ def main():
                    "zones": wl.nzones, "ne": wl.ne, "nquad": wl.nquad, "precision": precision},
         "rel_err_vs_oracle": errors, "fp64": fp64, "roofline": roof, "cpu_baseline": cpu,
         "streaming_pcie": streaming, "jacobian": jac, "with_positron_scattering": positron,
-        "fused_forward_backward": fused,
+        "fused_forward_backward": fused, "tabulated": tabulated,
     }
     print(json.dumps(line), flush=True)
 

@@ -158,6 +158,51 @@ int vtx_rates_forward_backward(const vtx_grid* grid, const vtx_opts* opts, int64
                                double* eta, double* chi,
                                double* g_T, double* g_eta_e, double* g_f, void* hip_stream);
 
+/*
+ * Tabulated kernels (a production alternative, kept as a comparison point): the quadratures
+ * of each zone are interpolated from a table over a regular lattice of zone states instead of
+ * being evaluated. Completion and contraction still take the zone's own T and f, so detailed
+ * balance stays exact; the interpolation error sits in the quadratures alone.
+ *
+ * Task values of one zone (doubles, packed over the processes asked for), the quadratures
+ * before completion, prefactor G_F^2/(pi eps_i eps_j) included:
+ *   VTX_NES:  q[t][S][l], t = i (i + 1)/2 + j for i >= j, (S, l) = (I,0), (I,1), (II,0), (II,1)
+ *   VTX_NPS:  the same on positrons
+ *   VTX_PAIR: A[i][j][l] = Phi_a,I,l(i, j) for all i, j
+ * vtx_task_values gives their count per zone.
+ */
+typedef struct {
+  int32_t nt, nh;      /* lattice nodes along ln T and eta_e, >= 2 each */
+  double lnT0, dlnT;   /* node a at ln T = lnT0 + a dlnT (dlnT > 0), T in MeV */
+  double eta0, deta;   /* node b at eta_e = eta0 + b deta (deta > 0) */
+} vtx_lattice;
+
+int64_t vtx_task_values(int32_t ne, uint32_t processes);
+
+/* Task values tasks[nz][vtx_task_values(ne, processes)] of nzones zone states (device
+ * memory). */
+int vtx_rates_tasks(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
+                    const double* T, const double* eta_e, double* tasks, void* hip_stream);
+
+/* The same in interpolation variables: each adjacent (l = 0, l = 1) pair (x0, x1) of the
+ * layout as (ln x0, x1/x0) (x0 <= 0, only from underflow, as (ln 1e-300, 0)); Phi_0 is
+ * positive and exponential in 1/T and eta_e, and |Phi_1| <= Phi_0. Run over the lattice
+ * states (row a nh + b) it builds the table of vtx_rates_forward_interp. */
+int vtx_rates_table_rows(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
+                         const double* T, const double* eta_e, double* rows, void* hip_stream);
+
+/* eta, chi with the zone's task values interpolated bilinearly from table[nt nh][values]
+ * (device memory, rows of vtx_rates_table_rows): s = (ln T - lnT0)/dlnT, r = (eta_e - eta0)/deta, cell
+ * a = clip(floor(s), 0, nt - 2), b = clip(floor(r), 0, nh - 2), fractions u = s - a,
+ * v = r - b, weights (1-u)(1-v), u(1-v), (1-u) v, u v on t[a][b], t[a+1][b], t[a][b+1],
+ * t[a+1][b+1] (linear extrapolation outside the lattice), then each pair mapped back by
+ * x0 = exp(y0), x1 = y1 x0. FP64 throughout; opts->processes must be the table's; table is
+ * 16-byte aligned (VTX_EINVAL otherwise). */
+int vtx_rates_forward_interp(const vtx_grid* grid, const vtx_opts* opts, const vtx_lattice* lattice,
+                             const double* table, int64_t nzones, const double* T,
+                             const double* eta_e, const double* f, double* eta, double* chi,
+                             void* hip_stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* vtx_strerror(int code);
 

@@ -14,8 +14,8 @@ Lattice: node (a, b), a < nt, b < nh, at ln T = lnT0 + a dlnT, eta_e = eta0 + b 
 row in the table is a nh + b.
 Interpolation variables: the layout holds each (task, S) as the pair (l = 0, l = 1), adjacent.
 Phi_0 is positive and varies exponentially with 1/T and eta_e; |Phi_1| <= Phi_0 because
-|P_1| <= 1 under a nonnegative rate. A pair (x0, x1) is interpolated as (ln x0, x1/x0) (x0 <= 0,
-only from underflow, enters as (ln 1e-300, 0)) and mapped back by x0 = exp(y0), x1 = y1 x0.
+|P_1| <= 1 under a nonnegative rate. The table stores a pair (x0, x1) as (ln x0, x1/x0) (x0 <= 0,
+only from underflow, as (ln 1e-300, 0)); interpolated rows map back by x0 = exp(y0), x1 = y1 x0.
 Interpolation: bilinear in s = (ln T - lnT0)/dlnT and r = (eta_e - eta0)/deta on the cell
 a = clip(floor(s), 0, nt - 2), b = clip(floor(r), 0, nh - 2), with u = s - a, v = r - b
 (outside the lattice this extrapolates linearly from the edge cell).
@@ -87,11 +87,12 @@ def lattice_states(lat):
 
 
 def build(eps, lat, opts, chunk=32):
-    """The table [nt nh, values]: the quadratures at every lattice node."""
+    """The table [nt nh, values]: the quadratures at every lattice node, in interpolation
+    variables."""
     T, eta = lattice_states(lat)
     rows = [pack(rates.task_quadratures(eps, T[k:k + chunk], eta[k:k + chunk], opts), len(eps))
             for k in range(0, T.shape[0], chunk)]
-    return np.concatenate(rows)
+    return to_interp_vars(np.concatenate(rows))
 
 
 def to_interp_vars(x):
@@ -128,8 +129,8 @@ def bilinear(table, lat, T, eta_e):
 
 
 def interpolate(table, lat, T, eta_e):
-    """Task values at zone states (T, eta_e), interpolated in (ln x0, x1/x0): [z, values]."""
-    return from_interp_vars(bilinear(to_interp_vars(table), lat, T, eta_e))
+    """Task values at zone states (T, eta_e) from a table in interpolation variables."""
+    return from_interp_vars(bilinear(table, lat, T, eta_e))
 
 
 def forward(eps, w, lat, table, T, eta_e, f, opts=rates.Options()):

@@ -501,6 +501,56 @@ int vtx_rates_forward_backward(const vtx_grid* grid, const vtx_opts* opts, int64
   return e == hipSuccess ? VTX_OK : VTX_EHIP;
 }
 
+int64_t vtx_task_values(int32_t ne, uint32_t processes) {
+  if (ne < 1 || ne > vtx::kMaxNE || processes == 0 || (processes & ~7u) != 0) return 0;
+  return vtx::task_values(ne, processes);
+}
+
+namespace {
+int rates_tasks(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T, const double* eta_e,
+                double* tasks, bool rows, void* hip_stream) {
+  int rc = vtx::check_args(grid, opts, nzones);
+  if (rc != VTX_OK) return rc;
+  if (nzones == 0) return VTX_OK;
+  if (!T || !eta_e || !tasks) return VTX_EINVAL;
+  vtx::DevPlan P;
+  rc = vtx::get_plan(grid, opts, &P);
+  if (rc != VTX_OK) return rc;
+  const hipError_t e = vtx::launch_tasks(P, nzones, T, eta_e, tasks, rows, (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+}  // namespace
+
+int vtx_rates_tasks(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
+                    const double* eta_e, double* tasks, void* hip_stream) {
+  return rates_tasks(grid, opts, nzones, T, eta_e, tasks, false, hip_stream);
+}
+
+int vtx_rates_table_rows(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
+                         const double* eta_e, double* rows, void* hip_stream) {
+  return rates_tasks(grid, opts, nzones, T, eta_e, rows, true, hip_stream);
+}
+
+int vtx_rates_forward_interp(const vtx_grid* grid, const vtx_opts* opts, const vtx_lattice* lat,
+                             const double* table, int64_t nzones, const double* T, const double* eta_e,
+                             const double* f, double* eta, double* chi, void* hip_stream) {
+  int rc = vtx::check_args(grid, opts, nzones);
+  if (rc != VTX_OK) return rc;
+  if (!lat || lat->nt < 2 || lat->nh < 2 || !(lat->dlnT > 0.0) || !(lat->deta > 0.0) ||
+      !std::isfinite(lat->lnT0) || !std::isfinite(lat->eta0) || !std::isfinite(lat->dlnT) ||
+      !std::isfinite(lat->deta))
+    return VTX_EINVAL;
+  if (nzones == 0) return VTX_OK;
+  if (!table || !T || !eta_e || !f || !eta || !chi) return VTX_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(table) & 15) != 0) return VTX_EINVAL;   // rows are read in pairs
+  vtx::DevPlan P;
+  rc = vtx::get_plan(grid, opts, &P);
+  if (rc != VTX_OK) return rc;
+  const hipError_t e =
+      vtx::launch_interp(P, *lat, table, nzones, T, eta_e, f, eta, chi, (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+
 const char* vtx_strerror(int code) {
   switch (code) {
     case VTX_OK: return "ok";

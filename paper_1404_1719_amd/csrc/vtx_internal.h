@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/vtx_rates.h"
+
 namespace vtx {
 
 constexpr int kMaxNE = 32;
@@ -69,6 +71,11 @@ hipError_t launch_forward(const DevPlan& P, int64_t nz, const double* T, const d
                           const double* f, double* eta, double* chi, hipStream_t s);
 hipError_t launch_jacobian(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
                            double* eta, double* chi, double* jac, hipStream_t s);
+int64_t task_values(int ne, unsigned processes);   // doubles per zone of the packed task values
+hipError_t launch_tasks(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, double* tasks,
+                        bool rows, hipStream_t s);
+hipError_t launch_interp(const DevPlan& P, const vtx_lattice& lat, const double* table, int64_t nz, const double* T,
+                         const double* eta_e, const double* f, double* eta, double* chi, hipStream_t s);
 hipError_t launch_forward_backward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e,
                                    const double* f, const double* g_eta, const double* g_chi, double* eta,
                                    double* chi, double* g_T, double* g_eta_e, double* g_f, hipStream_t s);

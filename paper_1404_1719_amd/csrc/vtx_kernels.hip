@@ -785,10 +785,49 @@ __device__ __forceinline__ void scattering_fwd(const DevPlan& P, const R* tab, c
   o[3] = q.d;
 }
 
+// Outputs of the forward kernels: eta, chi; the explicit Jacobian blocks (and eta, chi when
+// eta_out is given); the task values themselves, packed (see export_tasks); or those in the
+// interpolation variables of a table row.
+constexpr int kOutRates = 0, kOutJac = 1, kOutTasks = 2, kOutTable = 3;
+
+// Interpolation variables of a table row: each (task, S) pair (l = 0, l = 1), adjacent in the
+// layout, as (ln x0, x1 / x0); x0 is positive and exponential in 1/T and eta_e, and
+// |x1| <= x0 (|P_1| <= 1). x0 <= 0, only from underflow, is stored as (ln 1e-300, 0).
+__device__ __forceinline__ void to_interp_vars(double x0, double x1, double& y0, double& y1) {
+  const bool pos = x0 > 0.0;
+  y0 = log(pos ? x0 : 1e-300);
+  y1 = pos ? x1 / x0 : 0.0;
+}
+
+// A zone's task values from LDS to out[z][values], packed over the processes asked for:
+// scattering [4 ntn] | positron scattering [4 ntn] | pair [2 ne^2] (the slot order of LDS);
+// ROWS writes them in interpolation variables.
+template <bool NPS, bool ROWS>
+__device__ void export_tasks(const DevPlan& P, const Zone& Z, const double* smem, const Lay& L,
+                             double* __restrict__ out) {
+  const bool do_nes = P.processes & VTX_NES, do_nps = NPS && (P.processes & VTX_NPS),
+             do_pair = P.processes & VTX_PAIR;
+  const int nv = (do_nes ? 4 * P.ntn : 0) + (do_nps ? 4 * P.ntn : 0) + (do_pair ? 2 * P.ntp : 0);
+  double* o = out + Z.z * (int64_t)nv;
+  int off = 0;
+  for (int k = 0; k < 3; ++k) {
+    const bool on = k == 0 ? do_nes : (k == 1 ? do_nps : do_pair);
+    if (!on) continue;
+    const int len = k == 2 ? 2 * P.ntp : 4 * P.ntn, src = k == 0 ? L.q : (k == 1 ? L.m : L.p);
+    for (int r = threadIdx.x; r < len / 2; r += blockDim.x) {
+      double y0 = smem[src + 2 * r], y1 = smem[src + 2 * r + 1];
+      if (ROWS) to_interp_vars(y0, y1, y0, y1);
+      o[off + 2 * r] = y0;
+      o[off + 2 * r + 1] = y1;
+    }
+    off += len;
+  }
+}
+
 // Forward of one zone: task values into LDS, then the contraction with f into eta, chi, or
-// (JAC) the explicit Jacobian blocks, which need no f, and the contraction as well when
-// eta_out is given.
-template <typename R, bool JAC, bool NPS>
+// the explicit Jacobian blocks, which need no f (and the contraction as well when eta_out
+// is given), or the task values themselves.
+template <typename R, int OUT, bool NPS>
 __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* smem, int64_t z, int selm,
                              const double* __restrict__ Tz, const double* __restrict__ etaz,
                              const double* __restrict__ f, double* __restrict__ eta_out,
@@ -804,7 +843,7 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   __syncthreads();
   const Zone& Z = zs[0];
   if (!Z.valid) return;   // uniform: every lane reads the same zone state
-  if (!JAC || eta_out != nullptr)
+  if (OUT == kOutRates || eta_out != nullptr)
     for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
   stage_factors(P, Z, smem + L.d);
   const Units U = task_units(ntn, ntm, ntp);
@@ -831,7 +870,11 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
     }
   }
   __syncthreads();
-  if (JAC) {
+  if (OUT == kOutTasks || OUT == kOutTable) {
+    export_tasks<NPS, OUT == kOutTable>(P, Z, smem, L, jac);
+    return;
+  }
+  if (OUT == kOutJac) {
     zone_jacobian<NPS>(P, Z, smem, jac);
     if (eta_out == nullptr) return;   // uniform: a kernel argument
   }
@@ -840,7 +883,7 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
 
 // Dense pass: workgroup b takes zone b (if selected). Occupancy targets: four waves per SIMD
 // for FP32 (at most 128 VGPRs), three for FP64.
-template <typename R, bool JAC, bool NPS>
+template <typename R, int OUT, bool NPS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 3)))
 void rates_forward_kernel(DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz,
                           const double* __restrict__ etaz, const double* __restrict__ f,
@@ -850,12 +893,12 @@ void rates_forward_kernel(DevPlan P, int64_t nz, int selm, const double* __restr
   extern __shared__ double smem[];
   stage_tab<R>(P, tab);
   const int64_t z = blockIdx.x;
-  zone_forward<R, JAC, NPS>(P, tab, zs, smem, z < nz ? z : -1, selm, Tz, etaz, f, eta_out, chi_out, jac);
+  zone_forward<R, OUT, NPS>(P, tab, zs, smem, z < nz ? z : -1, selm, Tz, etaz, f, eta_out, chi_out, jac);
 }
 
 // Sparse FP64 pass: workgroups scan windows of blockDim zones and run the zones with
 // |eta_e| above the threshold, one at a time. The scan order does not change any result.
-template <bool JAC, bool NPS>
+template <int OUT, bool NPS>
 __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_t nz, const double* __restrict__ Tz,
                                                                   const double* __restrict__ etaz,
                                                                   const double* __restrict__ f,
@@ -876,7 +919,7 @@ __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_
     __syncthreads();
     const int n = count;
     for (int c = 0; c < n; ++c) {
-      zone_forward<double, JAC, NPS>(P, tab, zs, smem, base + list[c], kSelAll, Tz, etaz, f, eta_out, chi_out,
+      zone_forward<double, OUT, NPS>(P, tab, zs, smem, base + list[c], kSelAll, Tz, etaz, f, eta_out, chi_out,
                                      jac);
       __syncthreads();
     }
@@ -884,6 +927,67 @@ __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_
   }
 }
 
+
+// Interpolated forward: a zone's task values interpolated bilinearly from a table of task
+// values on a regular lattice of zone states in (ln T, eta_e) (rows in the export layout, in
+// interpolation variables), then completed and contracted with the zone's own T and f like
+// the forward. Interpolation and contraction run in FP64 whatever precision built the table.
+template <bool NPS>
+__global__ __launch_bounds__(kBlock) void rates_interp_kernel(DevPlan P, vtx_lattice lat,
+                                                                 const double* __restrict__ table, int64_t nz,
+                                                                 const double* __restrict__ Tz,
+                                                                 const double* __restrict__ etaz,
+                                                                 const double* __restrict__ f,
+                                                                 double* __restrict__ eta_out,
+                                                                 double* __restrict__ chi_out) {
+  __shared__ Zone zs[2];
+  extern __shared__ double smem[];
+  const int64_t z = blockIdx.x;
+  stage_zone_state(P, z < nz ? z : -1, kSelAll, Tz, etaz, zs);
+  __syncthreads();
+  const Zone& Z = zs[0];
+  if (!Z.valid) return;   // uniform
+  const int ne = P.ne, n2 = ne * ne;
+  const Lay L = layout<NPS>(P, 6 * ne);
+  const bool do_nes = P.processes & VTX_NES, do_nps = NPS && (P.processes & VTX_NPS),
+             do_pair = P.processes & VTX_PAIR;
+  const int nv = (do_nes ? 4 * P.ntn : 0) + (do_nps ? 4 * P.ntn : 0) + (do_pair ? 2 * P.ntp : 0);
+  for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
+  stage_factors(P, Z, smem + L.d);
+  // the cell (a, b) and the fractions (u, v); outside the lattice the edge cell extrapolates
+  const double s = (log(Z.T) - lat.lnT0) / lat.dlnT, rr = (Z.eta - lat.eta0) / lat.deta;
+  const double af = fmin(fmax(floor(s), 0.0), double(lat.nt - 2)), bf = fmin(fmax(floor(rr), 0.0), double(lat.nh - 2));
+  const int a = int(af), b = int(bf);
+  const double u = s - af, v = rr - bf;
+  const double c00 = (1.0 - u) * (1.0 - v), c10 = u * (1.0 - v), c01 = (1.0 - u) * v, c11 = u * v;
+  const double* t00 = table + ((int64_t)a * lat.nh + b) * nv;
+  const double* t10 = table + ((int64_t)(a + 1) * lat.nh + b) * nv;
+  const double* t01 = t00 + nv;
+  const double* t11 = t10 + nv;
+  // rows hold interpolation variables (ln x0, x1 / x0) per (task, S) pair; back by
+  // x0 = exp(y0), x1 = y1 x0. Bilinear in them is exact for exponential dependence.
+  int off = 0;
+  for (int k = 0; k < 3; ++k) {
+    const bool on = k == 0 ? do_nes : (k == 1 ? do_nps : do_pair);
+    if (!on) continue;
+    const int len = k == 2 ? 2 * P.ntp : 4 * P.ntn, dst = k == 0 ? L.q : (k == 1 ? L.m : L.p);
+    for (int r = threadIdx.x; r < len / 2; r += blockDim.x) {
+      const int q = off + 2 * r;
+      const double2 a00 = *reinterpret_cast<const double2*>(t00 + q);
+      const double2 a10 = *reinterpret_cast<const double2*>(t10 + q);
+      const double2 a01 = *reinterpret_cast<const double2*>(t01 + q);
+      const double2 a11 = *reinterpret_cast<const double2*>(t11 + q);
+      const double y0 = c00 * a00.x + c10 * a10.x + c01 * a01.x + c11 * a11.x;
+      const double y1 = c00 * a00.y + c10 * a10.y + c01 * a01.y + c11 * a11.y;
+      const double x0 = exp(y0);
+      smem[dst + 2 * r] = x0;
+      smem[dst + 2 * r + 1] = y1 * x0;
+    }
+    off += len;
+  }
+  __syncthreads();
+  zone_contract<NPS>(P, Z, smem, L, smem + L.d + 2 * n2, eta_out, chi_out);
+}
 
 // ---------------------------------------------------------------------------------------
 // Backward (vector-Jacobian product). Recomputes every task's kernel values and, in the
@@ -1520,20 +1624,29 @@ constexpr int64_t kSliceZones = int64_t(1) << 22;
 
 template <bool NPS>
 hipError_t forward_slice_t(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
-                           double* eta, double* chi, double* jac, hipStream_t s) {
+                           double* eta, double* chi, double* jac, int out, hipStream_t s) {
   const size_t lds = zone_lds_fwd(P);
   const dim3 grid((unsigned)nz), block(kBlock);
   hipError_t e;
   if (P.precision == VTX_MIXED) {
-    auto bulk = jac ? rates_forward_kernel<float, true, NPS> : rates_forward_kernel<float, false, NPS>;
-    auto sparse = jac ? rates_forward_sparse<true, NPS> : rates_forward_sparse<false, NPS>;
+    auto bulk = out == kOutJac     ? rates_forward_kernel<float, kOutJac, NPS>
+                : out == kOutTasks ? rates_forward_kernel<float, kOutTasks, NPS>
+                : out == kOutTable ? rates_forward_kernel<float, kOutTable, NPS>
+                                   : rates_forward_kernel<float, kOutRates, NPS>;
+    auto sparse = out == kOutJac     ? rates_forward_sparse<kOutJac, NPS>
+                  : out == kOutTasks ? rates_forward_sparse<kOutTasks, NPS>
+                  : out == kOutTable ? rates_forward_sparse<kOutTable, NPS>
+                                     : rates_forward_sparse<kOutRates, NPS>;
     if ((e = allow_lds(bulk, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(bulk, grid, block, lds, s, P, nz, kSelBulk, T, eta_e, f, eta, chi, jac);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = allow_lds(sparse, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(sparse, dim3(sparse_grid(nz)), block, lds, s, P, nz, T, eta_e, f, eta, chi, jac);
   } else {
-    auto dense = jac ? rates_forward_kernel<double, true, NPS> : rates_forward_kernel<double, false, NPS>;
+    auto dense = out == kOutJac     ? rates_forward_kernel<double, kOutJac, NPS>
+                 : out == kOutTasks ? rates_forward_kernel<double, kOutTasks, NPS>
+                 : out == kOutTable ? rates_forward_kernel<double, kOutTable, NPS>
+                                    : rates_forward_kernel<double, kOutRates, NPS>;
     if ((e = allow_lds(dense, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(dense, grid, block, lds, s, P, nz, kSelAll, T, eta_e, f, eta, chi, jac);
   }
@@ -1541,9 +1654,21 @@ hipError_t forward_slice_t(const DevPlan& P, int64_t nz, const double* T, const 
 }
 
 hipError_t forward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
-                         double* eta, double* chi, double* jac, hipStream_t s) {
-  return (P.processes & VTX_NPS) ? forward_slice_t<true>(P, nz, T, eta_e, f, eta, chi, jac, s)
-                                 : forward_slice_t<false>(P, nz, T, eta_e, f, eta, chi, jac, s);
+                         double* eta, double* chi, double* jac, int out, hipStream_t s) {
+  return (P.processes & VTX_NPS) ? forward_slice_t<true>(P, nz, T, eta_e, f, eta, chi, jac, out, s)
+                                 : forward_slice_t<false>(P, nz, T, eta_e, f, eta, chi, jac, out, s);
+}
+
+template <bool NPS>
+hipError_t interp_slice_t(const DevPlan& P, const vtx_lattice& lat, const double* table, int64_t nz,
+                          const double* T, const double* eta_e, const double* f, double* eta, double* chi,
+                          hipStream_t s) {
+  const size_t lds = zone_lds_fwd(P);
+  hipError_t e;
+  if ((e = allow_lds(rates_interp_kernel<NPS>, lds)) != hipSuccess) return e;
+  hipLaunchKernelGGL(rates_interp_kernel<NPS>, dim3((unsigned)nz), dim3(kBlock), lds, s, P, lat, table, nz, T,
+                     eta_e, f, eta, chi);
+  return hipGetLastError();
 }
 
 template <bool NPS, bool FUSED>
@@ -1591,7 +1716,7 @@ hipError_t launch_forward(const DevPlan& P, int64_t nz, const double* T, const d
   for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
     const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
     const hipError_t e = forward_slice(P, n, T + z0, eta_e + z0, f + z0 * zs, eta + z0 * zs, chi + z0 * zs,
-                                       nullptr, s);
+                                       nullptr, kOutRates, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1603,8 +1728,42 @@ hipError_t launch_jacobian(const DevPlan& P, int64_t nz, const double* T, const 
   for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
     const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
     const hipError_t e = eta ? forward_slice(P, n, T + z0, eta_e + z0, f + z0 * zs, eta + z0 * zs, chi + z0 * zs,
-                                             jac + z0 * js, s)
-                             : forward_slice(P, n, T + z0, eta_e + z0, nullptr, nullptr, nullptr, jac + z0 * js, s);
+                                             jac + z0 * js, kOutJac, s)
+                             : forward_slice(P, n, T + z0, eta_e + z0, nullptr, nullptr, nullptr, jac + z0 * js,
+                                             kOutJac, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int64_t task_values(int ne, unsigned processes) {
+  const int64_t ntn = int64_t(ne) * (ne + 1) / 2;
+  return ((processes & VTX_NES) ? 4 * ntn : 0) + ((processes & VTX_NPS) ? 4 * ntn : 0) +
+         ((processes & VTX_PAIR) ? 2 * int64_t(ne) * ne : 0);
+}
+
+hipError_t launch_tasks(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, double* tasks,
+                        bool rows, hipStream_t s) {
+  const int64_t nv = task_values(P.ne, P.processes);
+  for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
+    const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
+    const hipError_t e = forward_slice(P, n, T + z0, eta_e + z0, nullptr, nullptr, nullptr, tasks + z0 * nv,
+                                       rows ? kOutTable : kOutTasks, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_interp(const DevPlan& P, const vtx_lattice& lat, const double* table, int64_t nz, const double* T,
+                         const double* eta_e, const double* f, double* eta, double* chi, hipStream_t s) {
+  const int64_t zs = 6 * P.ne;
+  for (int64_t z0 = 0; z0 < nz; z0 += kSliceZones) {
+    const int64_t n = nz - z0 < kSliceZones ? nz - z0 : kSliceZones;
+    const hipError_t e = (P.processes & VTX_NPS)
+                             ? interp_slice_t<true>(P, lat, table, n, T + z0, eta_e + z0, f + z0 * zs, eta + z0 * zs,
+                                                    chi + z0 * zs, s)
+                             : interp_slice_t<false>(P, lat, table, n, T + z0, eta_e + z0, f + z0 * zs,
+                                                     eta + z0 * zs, chi + z0 * zs, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

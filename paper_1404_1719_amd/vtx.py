@@ -33,6 +33,11 @@ class Opts(ctypes.Structure):
                 ("processes", ctypes.c_uint32), ("sin2w", ctypes.c_double), ("eta_fp64", ctypes.c_double)]
 
 
+class Lattice(ctypes.Structure):
+    _fields_ = [("nt", ctypes.c_int32), ("nh", ctypes.c_int32), ("lnT0", ctypes.c_double),
+                ("dlnT", ctypes.c_double), ("eta0", ctypes.c_double), ("deta", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -56,6 +61,15 @@ def library():
     lib.vtx_rates_jacobian.restype = ctypes.c_int
     lib.vtx_rates_forward_backward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64] + [vp] * 11
     lib.vtx_rates_forward_backward.restype = ctypes.c_int
+    lib.vtx_task_values.argtypes = [ctypes.c_int32, ctypes.c_uint32]
+    lib.vtx_task_values.restype = ctypes.c_int64
+    lib.vtx_rates_tasks.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp]
+    lib.vtx_rates_tasks.restype = ctypes.c_int
+    lib.vtx_rates_table_rows.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp]
+    lib.vtx_rates_table_rows.restype = ctypes.c_int
+    lib.vtx_rates_forward_interp.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), ctypes.POINTER(Lattice),
+                                             vp, i64, vp, vp, vp, vp, vp, vp]
+    lib.vtx_rates_forward_interp.restype = ctypes.c_int
     lib.vtx_strerror.argtypes = [ctypes.c_int]
     lib.vtx_strerror.restype = ctypes.c_char_p
     lib.vtx_abi_version.argtypes = []
@@ -208,6 +222,62 @@ def forward_backward(grid: GridHandle, opts: Opts, T, eta_e, f, g_eta, g_chi, ou
         _dev_ptr(gE, "g_eta_e", (nz,)), _dev_ptr(gf, "g_f", shp), _stream_handle(stream))
     _check(rc, "vtx_rates_forward_backward")
     return out
+
+
+def task_values(ne: int, processes: int) -> int:
+    """Doubles per zone of the packed task values."""
+    return int(library().vtx_task_values(ne, processes))
+
+
+def tasks(grid: GridHandle, opts: Opts, T, eta_e, out=None, stream=None, rows=False):
+    """Task values [nz, task_values(ne, processes)] (the quadratures before completion); rows:
+    in the interpolation variables of a table row (vtx_rates_table_rows)."""
+    import torch
+    nz = T.shape[0]
+    shp = (nz, task_values(grid.ne, opts.processes))
+    if out is None:
+        out = torch.empty(shp, dtype=torch.float64, device=T.device)
+    fn = library().vtx_rates_table_rows if rows else library().vtx_rates_tasks
+    rc = fn(ctypes.byref(grid.c), ctypes.byref(opts), nz, _dev_ptr(T, "T", (nz,)), _dev_ptr(eta_e, "eta_e", (nz,)),
+            _dev_ptr(out, "tasks", shp), _stream_handle(stream))
+    _check(rc, "vtx_rates_table_rows" if rows else "vtx_rates_tasks")
+    return out
+
+
+def lattice_states(lat: Lattice, device):
+    """Zone states (T, eta_e) of the lattice nodes, row a nh + b (CUDA float64)."""
+    import torch
+    a = torch.arange(lat.nt, dtype=torch.float64, device=device).repeat_interleave(lat.nh)
+    b = torch.arange(lat.nh, dtype=torch.float64, device=device).repeat(lat.nt)
+    return torch.exp(lat.lnT0 + a * lat.dlnT), lat.eta0 + b * lat.deta
+
+
+def build_table(grid: GridHandle, opts: Opts, lat: Lattice, stream=None):
+    """The table of task values over the lattice (vtx_rates_tasks at the lattice states)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    with torch.cuda.stream(s):
+        T, E = lattice_states(lat, "cuda")
+        return tasks(grid, opts, T.contiguous(), E.contiguous(), stream=s, rows=True)
+
+
+def forward_interp(grid: GridHandle, opts: Opts, lat: Lattice, table, T, eta_e, f, eta=None, chi=None,
+                   stream=None):
+    """eta, chi from task values interpolated from the table (vtx_rates_forward_interp)."""
+    import torch
+    nz = T.shape[0]
+    shp = (nz, 3, 2, grid.ne)
+    if eta is None:
+        eta = torch.empty(shp, dtype=torch.float64, device=T.device)
+    if chi is None:
+        chi = torch.empty(shp, dtype=torch.float64, device=T.device)
+    tshape = (lat.nt * lat.nh, task_values(grid.ne, opts.processes))
+    rc = library().vtx_rates_forward_interp(
+        ctypes.byref(grid.c), ctypes.byref(opts), ctypes.byref(lat), _dev_ptr(table, "table", tshape), nz,
+        _dev_ptr(T, "T", (nz,)), _dev_ptr(eta_e, "eta_e", (nz,)), _dev_ptr(f, "f", shp), _dev_ptr(eta, "eta", shp),
+        _dev_ptr(chi, "chi", shp), _stream_handle(stream))
+    _check(rc, "vtx_rates_forward_interp")
+    return eta, chi
 
 
 def gauss_rule(kind: int, n: int):

@@ -63,6 +63,14 @@ def _call_fb(grid, opts, nz, ptr=1):
     return lib.vtx_rates_forward_backward(ctypes.byref(grid.c), ctypes.byref(opts), nz, *([p] * 11), None)
 
 
+def test_task_value_counts_match_the_oracle_layout():
+    from oracle import rates, tabulated
+    for ne in (1, 12, 21, 32):
+        for proc in range(1, 8):
+            assert lib.vtx_task_values(ne, proc) == tabulated.values_per_zone(ne, rates.Options(processes=proc))
+    assert lib.vtx_task_values(0, 3) == 0 and lib.vtx_task_values(21, 8) == 0
+
+
 def test_invalid_arguments():
     eps, w = synth.energy_grid(21, 2.0, 380.0)
     g = vtx.GridHandle(eps, w)
@@ -81,6 +89,22 @@ def test_invalid_arguments():
     assert _call_fb(g, o, 4, ptr=0) == vtx.VTX_EINVAL
     assert _call_fb(g, o, -1) == vtx.VTX_EINVAL
     assert _call_fb(g, o, 0) == vtx.VTX_OK
+    p1 = ctypes.c_void_p(1)
+    assert lib.vtx_rates_tasks(ctypes.byref(g.c), ctypes.byref(o), 4, p1, p1, None, None) == vtx.VTX_EINVAL
+    assert lib.vtx_rates_tasks(ctypes.byref(g.c), ctypes.byref(o), 0, None, None, None, None) == vtx.VTX_OK
+    lat = vtx.Lattice(4, 5, 0.0, 0.1, 0.0, 0.5)
+    args = [p1] * 6
+    for bad in (vtx.Lattice(1, 5, 0.0, 0.1, 0.0, 0.5), vtx.Lattice(4, 5, 0.0, 0.0, 0.0, 0.5),
+                vtx.Lattice(4, 5, 0.0, 0.1, 0.0, -1.0), vtx.Lattice(4, 5, float("nan"), 0.1, 0.0, 0.5)):
+        assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(bad), p1, 4, *args,
+                                            None) == vtx.VTX_EINVAL
+    assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), None, p1, 4, *args,
+                                        None) == vtx.VTX_EINVAL
+    assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(lat), None, 4, *args,
+                                        None) == vtx.VTX_EINVAL
+    assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(lat),
+                                        ctypes.c_void_p(8), 4, *args, None) == vtx.VTX_EINVAL   # misaligned
+    assert lib.vtx_rates_table_rows(ctypes.byref(g.c), ctypes.byref(o), 4, p1, p1, None, None) == vtx.VTX_EINVAL
     for field, bad in [("nquad", 6), ("nquad", 50), ("nquad", 68), ("rule", 2), ("precision", 3),
                        ("processes", 0), ("processes", 8), ("sin2w", float("nan"))]:
         ob = vtx.make_opts()

@@ -48,9 +48,11 @@ def test_exact_on_bilinear_data():
     r = ((eta - lat.eta0) / lat.deta)[:, None]
     ref = al + be * s + ga * r + de * s * r
     assert np.allclose(tabulated.bilinear(lin, lat, T, eta), ref, rtol=1e-12, atol=1e-12)
-    table = np.empty_like(lin)
-    table[:, 0::2] = np.exp(lin[:, 0::2])
-    table[:, 1::2] = lin[:, 1::2] * table[:, 0::2]
+    raw = np.empty_like(lin)
+    raw[:, 0::2] = np.exp(lin[:, 0::2])
+    raw[:, 1::2] = lin[:, 1::2] * raw[:, 0::2]
+    table = tabulated.to_interp_vars(raw)
+    assert np.allclose(table, lin, rtol=1e-12, atol=1e-12)
     got = tabulated.interpolate(table, lat, T, eta)
     x0 = np.exp(ref[:, 0::2])
     assert np.allclose(got[:, 0::2], x0, rtol=1e-12, atol=0)
