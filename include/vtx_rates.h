@@ -196,10 +196,11 @@ int vtx_rates_table_rows(const vtx_grid* grid, const vtx_opts* opts, int64_t nzo
  * a = clip(floor(s), 0, nt - 2), b = clip(floor(r), 0, nh - 2), fractions u = s - a,
  * v = r - b, weights (1-u)(1-v), u(1-v), (1-u) v, u v on t[a][b], t[a+1][b], t[a][b+1],
  * t[a+1][b+1] (linear extrapolation outside the lattice), then each pair mapped back by
- * x0 = exp(y0), x1 = y1 x0. FP64 throughout; opts->processes must be the table's; table is
- * 16-byte aligned (VTX_EINVAL otherwise). */
+ * x0 = exp(y0), x1 = y1 x0. FP64 throughout. table_len is the table's length in doubles; it
+ * must equal nt nh vtx_task_values(ne, opts->processes) (the table's processes), and table
+ * must be 16-byte aligned (VTX_EINVAL otherwise). */
 int vtx_rates_forward_interp(const vtx_grid* grid, const vtx_opts* opts, const vtx_lattice* lattice,
-                             const double* table, int64_t nzones, const double* T,
+                             const double* table, int64_t table_len, int64_t nzones, const double* T,
                              const double* eta_e, const double* f, double* eta, double* chi,
                              void* hip_stream);
 

@@ -532,7 +532,8 @@ int vtx_rates_table_rows(const vtx_grid* grid, const vtx_opts* opts, int64_t nzo
 }
 
 int vtx_rates_forward_interp(const vtx_grid* grid, const vtx_opts* opts, const vtx_lattice* lat,
-                             const double* table, int64_t nzones, const double* T, const double* eta_e,
+                             const double* table, int64_t table_len, int64_t nzones, const double* T,
+                             const double* eta_e,
                              const double* f, double* eta, double* chi, void* hip_stream) {
   int rc = vtx::check_args(grid, opts, nzones);
   if (rc != VTX_OK) return rc;
@@ -540,6 +541,7 @@ int vtx_rates_forward_interp(const vtx_grid* grid, const vtx_opts* opts, const v
       !std::isfinite(lat->lnT0) || !std::isfinite(lat->eta0) || !std::isfinite(lat->dlnT) ||
       !std::isfinite(lat->deta))
     return VTX_EINVAL;
+  if (table_len != int64_t(lat->nt) * lat->nh * vtx::task_values(grid->ne, opts->processes)) return VTX_EINVAL;
   if (nzones == 0) return VTX_OK;
   if (!table || !T || !eta_e || !f || !eta || !chi) return VTX_EINVAL;
   if ((reinterpret_cast<uintptr_t>(table) & 15) != 0) return VTX_EINVAL;   // rows are read in pairs

@@ -68,7 +68,7 @@ def library():
     lib.vtx_rates_table_rows.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp]
     lib.vtx_rates_table_rows.restype = ctypes.c_int
     lib.vtx_rates_forward_interp.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), ctypes.POINTER(Lattice),
-                                             vp, i64, vp, vp, vp, vp, vp, vp]
+                                             vp, i64, i64, vp, vp, vp, vp, vp, vp]
     lib.vtx_rates_forward_interp.restype = ctypes.c_int
     lib.vtx_strerror.argtypes = [ctypes.c_int]
     lib.vtx_strerror.restype = ctypes.c_char_p
@@ -273,7 +273,8 @@ def forward_interp(grid: GridHandle, opts: Opts, lat: Lattice, table, T, eta_e, 
         chi = torch.empty(shp, dtype=torch.float64, device=T.device)
     tshape = (lat.nt * lat.nh, task_values(grid.ne, opts.processes))
     rc = library().vtx_rates_forward_interp(
-        ctypes.byref(grid.c), ctypes.byref(opts), ctypes.byref(lat), _dev_ptr(table, "table", tshape), nz,
+        ctypes.byref(grid.c), ctypes.byref(opts), ctypes.byref(lat), _dev_ptr(table, "table", tshape),
+        tshape[0] * tshape[1], nz,
         _dev_ptr(T, "T", (nz,)), _dev_ptr(eta_e, "eta_e", (nz,)), _dev_ptr(f, "f", shp), _dev_ptr(eta, "eta", shp),
         _dev_ptr(chi, "chi", shp), _stream_handle(stream))
     _check(rc, "vtx_rates_forward_interp")

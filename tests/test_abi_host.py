@@ -94,16 +94,21 @@ def test_invalid_arguments():
     assert lib.vtx_rates_tasks(ctypes.byref(g.c), ctypes.byref(o), 0, None, None, None, None) == vtx.VTX_OK
     lat = vtx.Lattice(4, 5, 0.0, 0.1, 0.0, 0.5)
     args = [p1] * 6
+    n_ok = 4 * 5 * lib.vtx_task_values(21, 3)
     for bad in (vtx.Lattice(1, 5, 0.0, 0.1, 0.0, 0.5), vtx.Lattice(4, 5, 0.0, 0.0, 0.0, 0.5),
                 vtx.Lattice(4, 5, 0.0, 0.1, 0.0, -1.0), vtx.Lattice(4, 5, float("nan"), 0.1, 0.0, 0.5)):
-        assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(bad), p1, 4, *args,
-                                            None) == vtx.VTX_EINVAL
-    assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), None, p1, 4, *args,
+        assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(bad), p1, n_ok, 4,
+                                            *args, None) == vtx.VTX_EINVAL
+    assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), None, p1, n_ok, 4, *args,
                                         None) == vtx.VTX_EINVAL
-    assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(lat), None, 4, *args,
-                                        None) == vtx.VTX_EINVAL
+    assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(lat), None, n_ok, 4,
+                                        *args, None) == vtx.VTX_EINVAL
     assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(lat),
-                                        ctypes.c_void_p(8), 4, *args, None) == vtx.VTX_EINVAL   # misaligned
+                                        ctypes.c_void_p(8), n_ok, 4, *args, None) == vtx.VTX_EINVAL  # misaligned
+    # a table of another process mask (or length) is refused before any launch
+    for n_bad in (n_ok - 2, 4 * 5 * lib.vtx_task_values(21, 7), 0):
+        assert lib.vtx_rates_forward_interp(ctypes.byref(g.c), ctypes.byref(o), ctypes.byref(lat), p1, n_bad, 4,
+                                            *args, None) == vtx.VTX_EINVAL
     assert lib.vtx_rates_table_rows(ctypes.byref(g.c), ctypes.byref(o), 4, p1, p1, None, None) == vtx.VTX_EINVAL
     for field, bad in [("nquad", 6), ("nquad", 50), ("nquad", 68), ("rule", 2), ("precision", 3),
                        ("processes", 0), ("processes", 8), ("sin2w", float("nan"))]:
