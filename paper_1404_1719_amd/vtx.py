@@ -48,7 +48,14 @@ def library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} (run python -m paper_1404_1719_amd.build_lib)")
+    # torch first: its HIP runtime is the one the device pointers and streams belong to, and the
+    # library binds to an already loaded runtime by soname. Loaded first, the library would pull
+    # in a second runtime whose devices, pointers and streams are not torch's.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise RuntimeError(f"more than one HIP runtime is loaded in this process: {runtimes}")
     vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
     lib.vtx_opts_default.argtypes = [ctypes.POINTER(Opts)]
     lib.vtx_opts_default.restype = None
@@ -84,6 +91,15 @@ def library():
     lib.vtx_task_coefficients.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as fh:
+            return sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln and ln.split()[-1].startswith("/")})
+    except OSError:
+        return []
 
 
 def declared_functions():

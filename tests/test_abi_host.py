@@ -16,6 +16,8 @@ import pytest
 from oracle.angular import h_nes, h_pair
 from paper_1404_1719_amd import synth, vtx
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 lib = vtx.library()
 
 
@@ -194,3 +196,18 @@ def test_hpoly_tables_match_oracle():
                 # floor: 1e-12 of the piece's peak, which is of order (a b)^2 / max(a, b)
                 scale = np.abs(h_pair(0, S, a, b, Ep)) + 1e-3 * (a * b) ** 2 / max(a, b)
                 assert np.all(np.abs(got - ref) <= 1e-9 * scale), (a, b, comp)
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before anything imports torch must not pull in a second HIP
+    runtime: device pointers and streams come from torch's."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1404_1719_amd import vtx\n"
+            "vtx.library()\n"
+            "import torch\n"
+            "print(len(vtx._hip_runtimes()))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
