@@ -67,6 +67,19 @@ def traffic_from_profiles(kernel_tag):
     return rec.get("hbm_bytes_per_launch")
 
 
+def valu_issue_from_profiles(kernel_tag):
+    """Measured VALU issue rate (instructions x 4 cycles / SIMD cycles) from a committed
+    rocprofv3 SQ-counter summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", f"valu_{kernel_tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return {"valu_issue_frac": rec["valu_issue_frac"], "valu_instr_per_zone": rec["valu_instr_per_zone"]}
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """Oracle forward + backward on a bounded zone sample, spread over the host cores."""
     from concurrent.futures import ProcessPoolExecutor
@@ -536,6 +549,7 @@ def main():
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[precision], "traffic": traffic_from_profiles(tag),
             "kernel": tag, "launch_ms": dom_ms, "zones_per_launch": zl,
+            "valu_issue": valu_issue_from_profiles(tag),
             "fwd_launch_ms": t_fwd, "bwd_launch_ms": t_bwd}
 
     fp64 = None
