@@ -439,3 +439,42 @@ def test_graph_capture_and_replay():
             vtx.forward(grid, opts, T, E, f)                     # eager work between replays
             torch.cuda.synchronize()
         say(f"[gpu] graph capture {prec}: 3 replays equal to eager")
+
+
+@pytest.mark.parametrize("precision,tol,gtol", [("fp64", FP64_TOL, FP64_TOL), ("mixed", MIXED_TOL, 1e-3)])
+def test_largest_grid_all_entry_points(precision, tol, gtol):
+    """32 bins, 64 nodes, all three processes (the largest LDS footprint): forward, backward,
+    the fused call, the Jacobian with outputs and the task export against the oracle."""
+    from oracle import tabulated as otab
+    eps, w = synth.energy_grid(32, 1.0, 400.0)
+    T, eta_e, f = synth.draw_zones(3, 32, eps, (1.0, 40.0), (-5.0, 50.0), (-2.0, 12.0), 0.05, 83)
+    inp = synth.ZoneInputs(eps, w, T, eta_e, f)
+    ge, gc = synth.random_gradients(3, 32, 17)
+    grid = vtx.GridHandle(eps, w)
+    opts = vtx.make_opts(precision, 64, "panel", 7)
+    oo = orates.Options(nquad=64, rule="panel", processes=7)
+    Td, Ed, fd, Ged, Gcd = (to_dev(a) for a in (T, eta_e, f, ge, gc))
+    say(f"[gpu] ne=32 n=64 all processes {precision}")
+    e, c = vtx.forward(grid, opts, Td, Ed, fd)
+    re, rc, ae, ac = orates.forward_with_scale(eps, w, T, eta_e, f, oo)
+    assert max(rel_err(e.cpu().numpy(), re, ae).max(), rel_err(c.cpu().numpy(), rc, ac).max()) <= tol
+    gT, gE, gf = vtx.backward(grid, opts, Td, Ed, fd, Ged, Gcd)
+    rT, rE, rf = ograd.vjp(eps, w, T, eta_e, f, ge, gc, oo)
+    gerr = max(grad_err(gT.cpu().numpy(), rT).max(), grad_err(gE.cpu().numpy(), rE).max(),
+               grad_err(gf.cpu().numpy(), rf).max())
+    say(f"    backward rel err {gerr:.2e}")
+    assert gerr <= gtol
+    e2, c2, gT2, gE2, gf2 = vtx.forward_backward(grid, opts, Td, Ed, fd, Ged, Gcd)
+    assert torch.equal(gT2, gT) and torch.equal(gE2, gE) and torch.equal(gf2, gf)
+    assert max(rel_err(e2.cpu().numpy(), re, ae).max(), rel_err(c2.cpu().numpy(), rc, ac).max()) <= tol
+    J, e3, c3 = vtx.jacobian(grid, opts, Td, Ed, f=fd)
+    assert torch.equal(e3, e) and torch.equal(c3, c)
+    Jr = orates.jacobian(eps, w, T, eta_e, oo)
+    Ja = orates.jacobian(eps, w, T, eta_e, oo, absolute=True)
+    jerr = (np.abs(J.cpu().numpy() - Jr) / np.maximum(np.maximum(np.abs(Jr), Ja), 1e-290)).max()
+    say(f"    jacobian rel err {jerr:.2e}")
+    assert jerr <= tol
+    q = vtx.tasks(grid, opts, Td, Ed).cpu().numpy()
+    qr = otab.pack(orates.task_quadratures(eps, T, eta_e, oo), 32)
+    qa = otab.pack(orates.task_quadratures(eps, T, eta_e, oo, absolute=True), 32)
+    assert (np.abs(q - qr) / np.maximum(np.maximum(np.abs(qr), qa), 1e-290)).max() <= tol
