@@ -164,8 +164,10 @@ def complete(eps, T, quad):
             ii, jj = nes_tasks(ne)
             full = np.zeros((nz, ne, ne, 2, 2), dtype=q.dtype)
             full[:, ii, jj] = q
-            # up-scatter j > i from the down-scatter task (j, i): exp(-(eps_j - eps_i)/T)
-            up = np.exp(-(eps[None, None, :] - eps[None, :, None]) / T[:, None, None])  # [z, i, j]
+            # up-scatter j > i from the down-scatter task (j, i): exp(-(eps_j - eps_i)/T); the
+            # factor is formed for j > i only (elsewhere it would overflow at small T, unused)
+            gap = np.maximum(eps[None, None, :] - eps[None, :, None], 0.0)
+            up = np.exp(-gap / T[:, None, None])  # [z, i, j]
             upper = np.triu(np.ones((ne, ne), dtype=bool), 1)
             trans = np.swapaxes(full, 1, 2)
             phi_out = np.where(upper[None, :, :, None, None], up[..., None, None] * trans, full)
