@@ -478,3 +478,23 @@ def test_largest_grid_all_entry_points(precision, tol, gtol):
     qr = otab.pack(orates.task_quadratures(eps, T, eta_e, oo), 32)
     qa = otab.pack(orates.task_quadratures(eps, T, eta_e, oo, absolute=True), 32)
     assert (np.abs(q - qr) / np.maximum(np.maximum(np.abs(qr), qa), 1e-290)).max() <= tol
+
+
+def test_input_domain_extremes():
+    """|eta_e| up to 700 and T from 0.05 to 300 MeV (beyond every workload's range): finite
+    outputs and gradients within the bars, both paths."""
+    inp = synth.make_inputs("medium", nzones=12)
+    inp.eta_e[:] = [-700.0, -200.0, -65.0, 65.0, 200.0, 700.0, 0.0, 30.0, 60.0, -60.0, 10.0, 64.0]
+    inp.T[:] = [0.2, 5.0, 100.0, 0.1, 2.0, 0.5, 150.0, 0.05, 0.05, 0.3, 300.0, 0.5]
+    ge, gc = synth.random_gradients(12, inp.eps.shape[0], 18)
+    re, rc, ae, ac = oracle_forward(inp, 48, "panel")
+    rT, rE, rf = ograd.vjp(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, ge, gc, orates.Options(nquad=48, rule="panel"))
+    for prec, tol, gtol in (("fp64", FP64_TOL, FP64_TOL), ("mixed", MIXED_TOL, 1e-3)):
+        e, c = gpu_forward(inp, prec, 48, "panel")
+        gT, gE, gf = gpu_backward(inp, ge, gc, prec, 48, "panel")
+        for a in (e, c, gT, gE, gf):
+            assert np.all(np.isfinite(a))
+        err = max(rel_err(e, re, ae).max(), rel_err(c, rc, ac).max())
+        gerr = max(grad_err(gT, rT).max(), grad_err(gE, rE).max(), grad_err(gf, rf).max())
+        say(f"[gpu] domain extremes {prec}: forward {err:.2e}, backward {gerr:.2e}")
+        assert err <= tol and gerr <= gtol
