@@ -881,10 +881,11 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   zone_contract<NPS>(P, Z, smem, L, smem + L.d + 2 * n2, eta_out, chi_out);
 }
 
-// Dense pass: workgroup b takes zone b (if selected). Occupancy targets: four waves per SIMD
-// for FP32 (at most 128 VGPRs), three for FP64.
+// Dense pass: workgroup b takes zone b (if selected). Occupancy targets: five waves per SIMD
+// for FP32 (at most 102 VGPRs; five one-zone workgroups of 31 KB fill the 160 KB of LDS at
+// 21 bins), three for FP64 (four would spill).
 template <typename R, int OUT, bool NPS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 3)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 3)))
 void rates_forward_kernel(DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz,
                           const double* __restrict__ etaz, const double* __restrict__ f,
                           double* __restrict__ eta_out, double* __restrict__ chi_out, double* __restrict__ jac) {
@@ -933,7 +934,7 @@ __global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_
 // interpolation variables), then completed and contracted with the zone's own T and f like
 // the forward. Interpolation and contraction run in FP64 whatever precision built the table.
 template <bool NPS>
-__global__ __launch_bounds__(kBlock) void rates_interp_kernel(DevPlan P, vtx_lattice lat,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void rates_interp_kernel(DevPlan P, vtx_lattice lat,
                                                                  const double* __restrict__ table, int64_t nz,
                                                                  const double* __restrict__ Tz,
                                                                  const double* __restrict__ etaz,
