@@ -56,19 +56,15 @@ __device__ __forceinline__ double beta_of(const DevPlan& P, int s, int S) {
 template <typename R> struct Num;
 template <> struct Num<double> {
   static constexpr double zscale = 1.0;
-  static constexpr double zmin = -700.0;   // keeps exp(-z) finite where a ratio needs it
   __device__ static __forceinline__ double exp_neg(double z) { return exp(-z); }
   __device__ static __forceinline__ double recip(double x) { return 1.0 / x; }
   __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
-  __device__ static __forceinline__ double max(double a, double b) { return fmax(a, b); }
 };
 template <> struct Num<float> {
   static constexpr double zscale = kLog2e;
-  static constexpr float zmin = -126.0f;
   __device__ static __forceinline__ float exp_neg(float z) { return __builtin_amdgcn_exp2f(-z); }
   __device__ static __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
   __device__ static __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-  __device__ static __forceinline__ float max(float a, float b) { return fmaxf(a, b); }
 };
 
 // A breakpoint: value and its derivatives along T (eta_e fixed) and along eta_e (T fixed).
@@ -382,13 +378,15 @@ __device__ __forceinline__ void node_fwd(const Loop<R>& L, R xu, R x1, R x2, R w
     wh = lo ? R(0) : wB;
   }
   if (MODE != kHigh) {
+    // p q_j with the common factors taken first: three products serve the five moments
     const R v = R(1) - ul, u2 = ul * ul, v2 = v * v, uv = ul * v;
     const R p = wB * (u2 * ul);
-    M[0] = N::fma(p, v2 * v2, M[0]);
-    M[1] = N::fma(p, uv * v2, M[1]);
-    M[2] = N::fma(p, uv * uv, M[2]);
-    M[3] = N::fma(p, uv * u2, M[3]);
-    M[4] = N::fma(p, u2 * u2, M[4]);
+    const R pv2 = p * v2, puv = p * uv, pu2 = p * u2;
+    M[0] = N::fma(pv2, v2, M[0]);
+    M[1] = N::fma(pv2, uv, M[1]);
+    M[2] = N::fma(puv, uv, M[2]);
+    M[3] = N::fma(puv, u2, M[3]);
+    M[4] = N::fma(pu2, u2, M[4]);
   }
   if (MODE != kLow) {
     H[0] = H[0] + wh;
@@ -1138,16 +1136,33 @@ __device__ __forceinline__ void make_adj_poly_r(const R lo[5], const R hi[3], Ad
   Q.dh[1] = R(2) * hi[2];
 }
 
+// Sum over a group's nodes of x0 (node weight x blocking factor x adjoint-weighted angular
+// weight): the adjoint coefficients applied to the group's moments, since x0 = p H_low + wh H_high
+// node by node.
+template <typename R>
+__device__ __forceinline__ R adjoint_sum(const AdjPoly<R>& Q, const R M[5], const R H[3]) {
+  using N = Num<R>;
+  R s = Q.hh[0] * H[0];
+  s = N::fma(Q.hh[1], H[1], s);
+  s = N::fma(Q.hh[2], H[2], s);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) s = N::fma(Q.hl[k], M[k], s);
+  return s;
+}
+
+// S[1..6] collect x0 and its u-derivative term weighted by the blocking factor's
+// logarithmic derivatives (r1, r2) and the end weights (pa, pb); S[0] = adjoint_sum afterwards.
 template <typename R, int MODE>
 __device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, R xu, R x1, R x2, R w, R pa, R pb,
                                          R M[5], R H[3], R S[7]) {
   using N = Num<R>;
   const R u = N::fma(L.u1, xu, L.u0);
   const R z1 = N::fma(L.a1, x1, L.a0), z2 = N::fma(L.b1, x2, L.b0);
-  const R a = N::exp_neg(N::max(z1, R(N::zmin))), b = N::exp_neg(N::max(z2, R(N::zmin)));
-  const R i1 = N::recip(R(1) + a), i2 = N::recip(R(1) + b);
+  // sigma(z) = i and sigma(-z) = 1 - i = r. Where exp(-z) overflows to +inf, i = 0 and
+  // r = 1 are the limits, so no argument needs a clamp.
+  const R i1 = N::recip(R(1) + N::exp_neg(z1)), i2 = N::recip(R(1) + N::exp_neg(z2));
   const R wB = w * (i1 * i2);
-  const R r1 = a * i1, r2 = b * i2;
+  const R r1 = R(1) - i1, r2 = R(1) - i2;
   R ul = u, wh = wB;
   if (MODE == kGen) {
     const bool lo = u < L.split;
@@ -1158,7 +1173,7 @@ __device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, 
   if (MODE != kHigh) {
     const R v = R(1) - ul, u2 = ul * ul, v2 = v * v, uv = ul * v;
     const R q0 = v2 * v2, q1 = uv * v2, q2 = uv * uv, q3 = uv * u2, q4 = u2 * u2;
-    const R p = wB * (u2 * ul);
+    const R w2 = wB * u2, p = w2 * ul;
     M[0] = N::fma(p, q0, M[0]);
     M[1] = N::fma(p, q1, M[1]);
     M[2] = N::fma(p, q2, M[2]);
@@ -1167,7 +1182,7 @@ __device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, 
     const R hq = N::fma(Q.hl[4], q4, N::fma(Q.hl[3], q3, N::fma(Q.hl[2], q2, N::fma(Q.hl[1], q1, Q.hl[0] * q0))));
     const R dq = N::fma(Q.dl[4], q4, N::fma(Q.dl[3], q3, N::fma(Q.dl[2], q2, N::fma(Q.dl[1], q1, Q.dl[0] * q0))));
     x0 = p * hq;
-    yu = (wB * u2) * dq;
+    yu = w2 * dq;
   }
   if (MODE != kLow) {
     H[0] = H[0] + wh;
@@ -1183,7 +1198,6 @@ __device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, 
       yu = N::fma(wh, dh, yu);
     }
   }
-  S[0] = S[0] + x0;
   const R y1 = x0 * r1, y2 = x0 * r2;
   S[1] = N::fma(y1, pa, S[1]);
   S[2] = N::fma(y1, pb, S[2]);
@@ -1310,6 +1324,7 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
     }
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0}, S[7] = {0, 0, 0, 0, 0, 0, 0};
     run_nodes_bwd<R>(G.mode, L, Q, P.m4, tab, M, H, S);
+    S[0] = adjoint_sum<R>(Q, M, H);
     add_group<R>(G, Es, M, H, Sl);
     group_grad<R>(K, G, Z, Es, S, gT, gE);
   }
