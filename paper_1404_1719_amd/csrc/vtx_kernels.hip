@@ -369,6 +369,8 @@ __device__ __forceinline__ void node_fwd(const Loop<R>& L, R xu, R x1, R x2, R w
   using N = Num<R>;
   const R u = N::fma(L.u1, xu, L.u0);
   const R z1 = N::fma(L.a1, x1, L.a0), z2 = N::fma(L.b1, x2, L.b0);
+  // exp(-z) may overflow to +inf in a tail while the other factor is 1: the product of the
+  // two sums then stays +inf (never inf x 0), and the blocking factor 0
   const R a = N::exp_neg(z1), b = N::exp_neg(z2);
   const R wB = w * N::recip((R(1) + a) * (R(1) + b));
   R ul = u, wh = wB;
@@ -378,14 +380,14 @@ __device__ __forceinline__ void node_fwd(const Loop<R>& L, R xu, R x1, R x2, R w
     wh = lo ? R(0) : wB;
   }
   if (MODE != kHigh) {
-    // p q_j with the common factors taken first: three products serve the five moments
+    // p q_j with the common factors taken first: p v^2 and p u^2 serve the five moments
     const R v = R(1) - ul, u2 = ul * ul, v2 = v * v, uv = ul * v;
     const R p = wB * (u2 * ul);
-    const R pv2 = p * v2, puv = p * uv, pu2 = p * u2;
+    const R pv2 = p * v2, pu2 = p * u2;
     M[0] = N::fma(pv2, v2, M[0]);
     M[1] = N::fma(pv2, uv, M[1]);
-    M[2] = N::fma(puv, uv, M[2]);
-    M[3] = N::fma(puv, u2, M[3]);
+    M[2] = N::fma(pv2, u2, M[2]);
+    M[3] = N::fma(pu2, uv, M[3]);
     M[4] = N::fma(pu2, u2, M[4]);
   }
   if (MODE != kLow) {
