@@ -51,13 +51,44 @@ __device__ __forceinline__ double beta_of(const DevPlan& P, int s, int S) {
   return s == 0 ? b0 : (s == 1 ? b1 : b2);
 }
 
-// Arithmetic of the bulk type. The FP32 path carries the Fermi-Dirac arguments pre-scaled
-// by log2(e), so exp(-z) is one hardware exp2.
+// 2^x in FP64: x = n + f with n = rint(x), |f| <= 1/2, and 2^f = e^t, t = f ln 2 (|t| < 0.35),
+// from its Taylor series to degree 12 (truncation error below 2e-16 relative, about 3 ulp in
+// all); 2^n enters through ldexp. x is clamped to +-2100 first, beyond which 2^x rounds to 0
+// or +inf anyway, so infinite arguments give those limits too.
+__device__ __forceinline__ double exp2_fp64(double x) {
+  constexpr double kLn2 = 0.6931471805599453;
+  constexpr double kInvFact[13] = {1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664,
+                                   0.008333333333333333, 0.001388888888888889, 0.0001984126984126984,
+                                   2.48015873015873e-05, 2.7557319223985893e-06, 2.755731922398589e-07,
+                                   2.505210838544172e-08, 2.08767569878681e-09};
+  const double xc = fmin(fmax(x, -2100.0), 2100.0);
+  const double n = rint(xc);
+  const double t = (xc - n) * kLn2;
+  double p = kInvFact[12];
+#pragma unroll
+  for (int k = 11; k >= 0; --k) p = __builtin_fma(p, t, kInvFact[k]);
+  return ldexp(p, int(n));
+}
+
+// 1/x for the blocking denominators (x >= 1, or +inf): the hardware estimate refined by two
+// Newton steps, e = 1 - x r, r += r e (about 1 ulp). x is capped at 2^1000, so +inf gives
+// 2^-1000 rather than inf x 0 = NaN in the refinement.
+__device__ __forceinline__ double recip_ge1(double x) {
+  const double xc = fmin(x, 0x1p1000);
+  double r = __builtin_amdgcn_rcp(xc);
+  double e = __builtin_fma(-xc, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-xc, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Arithmetic of the bulk type. Both paths carry the Fermi-Dirac arguments pre-scaled by
+// log2(e), so exp(-z) is an exp2: one hardware instruction in FP32, exp2_fp64 in FP64.
 template <typename R> struct Num;
 template <> struct Num<double> {
-  static constexpr double zscale = 1.0;
-  __device__ static __forceinline__ double exp_neg(double z) { return exp(-z); }
-  __device__ static __forceinline__ double recip(double x) { return 1.0 / x; }
+  static constexpr double zscale = kLog2e;
+  __device__ static __forceinline__ double exp_neg(double z) { return exp2_fp64(-z); }
+  __device__ static __forceinline__ double recip(double x) { return recip_ge1(x); }
   __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 };
 template <> struct Num<float> {
