@@ -1,6 +1,8 @@
 """Angular weights H of the neutrino-electron scattering and pair kernels (oracle).
 
-Test infrastructure only. Definition (massless e+-, momenta q, q' of the two neutrinos,
+Test infrastructure only. The paper names these interaction rates as a component of the
+model's transport sources (Sect. 2.1) and prints no formula for them; what follows is the
+standard weak-interaction matrix element for massless e+- reduced to one angle. Definition (massless e+-, momenta q, q' of the two neutrinos,
 eps = |q|, eps' = |q'|, x = cos angle(q, q'), P_l Legendre polynomials):
 
   H_l^S(eps, eps', E) = 1/(eps eps') * Integral dk P_l(x(k)) <M^S>_phi(k, E)

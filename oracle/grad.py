@@ -1,5 +1,8 @@
 """Reverse-mode products of the rates (oracle; test infrastructure only).
 
+The rates enter the Newton-Raphson solve of the implicit ray-by-ray transport step
+(Sect. 2.1), which needs their derivatives with respect to the matter state and to f.
+
 Given upstream gradients g_eta, g_chi [z, s, m, i], returns
   g_T[z]     = d/dT   sum(g_eta * eta + g_chi * chi)  at fixed eta_e,
   g_eta_e[z] = d/deta_e of the same at fixed T,
