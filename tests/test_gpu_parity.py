@@ -10,6 +10,7 @@ Full-size workloads run in one launch over every zone, exactly as the benchmark 
 them, and sampled zones (always including the min-T, max-T and max-eta_e zones) are
 compared with the oracle zone by zone.
 """
+import functools
 import sys
 
 import numpy as np
@@ -94,10 +95,15 @@ def test_single_process(processes):
     check_forward(inp, "mixed", 48, "panel", MIXED_TOL, processes, label="medium-8")
 
 
+@functools.lru_cache(maxsize=1)
+def _full_inputs(name):
+    say(f"[gpu] full-size {name}: drawing {synth.WORKLOADS[name].nzones} zones")
+    return synth.make_inputs(name)
+
+
 def _full_then_sample(name, count, precision):
     wl = synth.WORKLOADS[name]
-    say(f"[gpu] full-size {name}: drawing {wl.nzones} zones")
-    inp = synth.make_inputs(name)
+    inp = _full_inputs(name)
     grid = vtx.GridHandle(inp.eps, inp.w)
     opts = vtx.make_opts(precision, wl.nquad, wl.rule)
     T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
@@ -126,6 +132,63 @@ def test_medium_full_size_sampled(precision, tol):
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
 def test_large_full_size_sampled(precision, tol):
     assert _full_then_sample("large", 24, precision) <= tol
+
+
+@functools.lru_cache(maxsize=1)
+def _large_backward_reference(count):
+    """Sampled zones of the large workload, their upstream gradients (drawn on the device for
+    every zone, seeded) and the oracle's reverse-mode products for them."""
+    wl = synth.WORKLOADS["large"]
+    inp = _full_inputs("large")
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(synth.SEED_BASE + 4000)
+    shp = tuple(inp.f.shape)
+    ge = torch.randn(shp, dtype=torch.float64, device=DEV, generator=gen)
+    gc = torch.randn(shp, dtype=torch.float64, device=DEV, generator=gen)
+    idx = synth.sample_zones(inp, count)
+    it = torch.from_numpy(idx).to(DEV)
+    g_eta, g_chi = (x.index_select(0, it).cpu().numpy() for x in (ge, gc))
+    del ge, gc
+    torch.cuda.empty_cache()
+    sub = synth.subset(inp, idx)
+    say(f"[gpu] large backward: oracle for {len(idx)} sampled zones")
+    ref = ograd.vjp(sub.eps, sub.w, sub.T, sub.eta_e, sub.f, g_eta, g_chi,
+                    orates.Options(nquad=wl.nquad, rule=wl.rule))
+    return idx, ref
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_backward_large_full_size_sampled(precision, tol):
+    """The backward over the whole large workload in the launches the benchmark times (8 chunks
+    of 307,200 zones), upstream gradients drawn on the device; sampled zones (the min-T, max-T
+    and max-eta_e zones among them) against the oracle's reverse-mode products."""
+    wl = synth.WORKLOADS["large"]
+    idx, (rT, rE, rf) = _large_backward_reference(12)
+    inp = _full_inputs("large")
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(synth.SEED_BASE + 4000)
+    ge = torch.randn(tuple(f.shape), dtype=torch.float64, device=DEV, generator=gen)
+    gc = torch.randn(tuple(f.shape), dtype=torch.float64, device=DEV, generator=gen)
+    gT = torch.empty(T.shape, dtype=torch.float64, device=DEV)
+    gE = torch.empty_like(gT)
+    gf = torch.empty_like(f)
+    bounds = np.linspace(0, T.shape[0], 9).astype(np.int64)
+    say(f"[gpu] large backward {precision}: 8 launches of {bounds[1]} zones")
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        vtx.backward(grid, opts, T[a:b], E[a:b], f[a:b], ge[a:b], gc[a:b], gT[a:b], gE[a:b], gf[a:b])
+    torch.cuda.synchronize()
+    it = torch.from_numpy(idx).to(DEV)
+    got = [x.index_select(0, it).cpu().numpy() for x in (gT, gE, gf)]
+    del T, E, f, ge, gc, gT, gE, gf
+    torch.cuda.empty_cache()
+    for g in got:
+        assert np.all(np.isfinite(g))
+    eT, eE, ef = grad_err(got[0], rT).max(), grad_err(got[1], rE).max(), grad_err(got[2], rf).max()
+    say(f"    rel err g_T {eT:.2e} g_eta_e {eE:.2e} g_f {ef:.2e}")
+    assert max(eT, eE, ef) <= tol
 
 
 def test_edge_cases():
@@ -192,7 +255,7 @@ def grad_err(g, ref):
 
 @pytest.mark.parametrize("name,nq,rule,nz", [("small", 32, "laguerre", 6), ("medium", 48, "panel", 6),
                                              ("large", 64, "panel", 4)])
-@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 1e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
 def test_backward_vs_oracle(name, nq, rule, nz, precision, tol):
     inp = synth.make_inputs(name, nzones=nz)
     ge, gc = synth.random_gradients(nz, inp.eps.shape[0], 3)
@@ -281,7 +344,9 @@ def test_mixed_fp64_pass():
     gm = gpu_backward(inp, ge, gc, "mixed", 48, "panel", eta_fp64=thr)
     for a, b in zip(gm, g64):
         assert np.array_equal(a[big], b[big])
-        assert grad_err(a[small], b[small]).max() <= 1e-3
+        gerr = grad_err(a[small], b[small]).max()
+        say(f"    FP32-pass zones, gradients against the FP64 path: {gerr:.2e}")
+        assert gerr <= MIXED_TOL
 
 
 def test_backward_batch_independent():
@@ -310,7 +375,7 @@ def test_positron_scattering_forward():
     check_forward(small, "fp64", 32, "laguerre", FP64_TOL, processes=7, label="small/laguerre")
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 1e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
 def test_positron_scattering_backward(precision, tol):
     inp = synth.make_inputs("medium", nzones=6)
     inp.eta_e[:3] = [-8.0, 0.5, 30.0]
@@ -441,7 +506,7 @@ def test_graph_capture_and_replay():
         say(f"[gpu] graph capture {prec}: 3 replays equal to eager")
 
 
-@pytest.mark.parametrize("precision,tol,gtol", [("fp64", FP64_TOL, FP64_TOL), ("mixed", MIXED_TOL, 1e-3)])
+@pytest.mark.parametrize("precision,tol,gtol", [("fp64", FP64_TOL, FP64_TOL), ("mixed", MIXED_TOL, MIXED_TOL)])
 def test_largest_grid_all_entry_points(precision, tol, gtol):
     """32 bins, 64 nodes, all three processes (the largest LDS footprint): forward, backward,
     the fused call, the Jacobian with outputs and the task export against the oracle."""
@@ -489,7 +554,7 @@ def test_input_domain_extremes():
     ge, gc = synth.random_gradients(12, inp.eps.shape[0], 18)
     re, rc, ae, ac = oracle_forward(inp, 48, "panel")
     rT, rE, rf = ograd.vjp(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, ge, gc, orates.Options(nquad=48, rule="panel"))
-    for prec, tol, gtol in (("fp64", FP64_TOL, FP64_TOL), ("mixed", MIXED_TOL, 1e-3)):
+    for prec, tol, gtol in (("fp64", FP64_TOL, FP64_TOL), ("mixed", MIXED_TOL, MIXED_TOL)):
         e, c = gpu_forward(inp, prec, 48, "panel")
         gT, gE, gf = gpu_backward(inp, ge, gc, prec, 48, "panel")
         for a in (e, c, gT, gE, gf):
