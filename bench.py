@@ -114,24 +114,36 @@ def _oracle_chunk(arg):
     return len(idx)
 
 
-def sampled_errors(inp, eta, chi, wl, count=6):
-    """Max relative error per output on sampled zones vs the FP64 oracle (same rule)."""
+def sampled_errors(inp, run, wl, count=6):
+    """Max relative error per output on sampled zones vs the FP64 oracle (same rule): the
+    forward's four outputs, and the backward's g_T, g_eta_e, g_f against the oracle's
+    reverse-mode products for the run's own upstream gradients (floor: 1e-3 x the mean
+    magnitude of the field, as g_f = K^T g sums terms of both signs)."""
     import torch
+    from oracle import grad as ograd
     from oracle import rates as orates
     idx = synth.sample_zones(inp, count, seed=11)
-    it = torch.from_numpy(idx).to(eta.device)
-    e = eta.index_select(0, it).cpu().numpy()
-    c = chi.index_select(0, it).cpu().numpy()
+    it = torch.from_numpy(idx).to(run.eta.device)
+
+    def pick(t):
+        return t.index_select(0, it).cpu().numpy()
+
+    e, c, ge, gc = pick(run.eta), pick(run.chi), pick(run.g_eta), pick(run.g_chi)
+    gT, gE, gf = pick(run.gT), pick(run.gE), pick(run.gf)
     sub = synth.subset(inp, idx)
-    re, rc, ae, ac = orates.forward_with_scale(sub.eps, sub.w, sub.T, sub.eta_e, sub.f,
-                                               orates.Options(nquad=wl.nquad, rule=wl.rule))
+    opts = orates.Options(nquad=wl.nquad, rule=wl.rule)
+    re, rc, ae, ac = orates.forward_with_scale(sub.eps, sub.w, sub.T, sub.eta_e, sub.f, opts)
+    rT, rE, rf = ograd.vjp(sub.eps, sub.w, sub.T, sub.eta_e, sub.f, ge, gc, opts)
 
     def err(y, r, a):
         return float(np.max(np.abs(y - r) / np.maximum(np.maximum(np.abs(r), 1e-3 * a), 1e-290)))
 
+    def gerr(g, r):
+        return float(np.max(np.abs(g - r) / np.maximum(np.abs(r), 1e-3 * np.mean(np.abs(r)) + 1e-300)))
+
     return {"eta0": err(e[:, :, 0], re[:, :, 0], ae[:, :, 0]), "eta1": err(e[:, :, 1], re[:, :, 1], ae[:, :, 1]),
             "chi0": err(c[:, :, 0], rc[:, :, 0], ac[:, :, 0]), "chi1": err(c[:, :, 1], rc[:, :, 1], ac[:, :, 1]),
-            "zones": len(idx)}
+            "g_T": gerr(gT, rT), "g_eta_e": gerr(gE, rE), "g_f": gerr(gf, rf), "zones": len(idx)}
 
 
 class Runner:
@@ -525,7 +537,7 @@ def main():
     units = wl.nzones * wl.ne * wl.ne
     value = units / t_step
     t_fwd, t_bwd, zl = run.launch_times()
-    errors = None if args.no_errors else sampled_errors(inp, run.eta, run.chi, wl)
+    errors = None if args.no_errors else sampled_errors(inp, run, wl)
     streaming = None
     if args.stream_steps > 0:
         print(f"[bench] streaming from pinned host memory: {args.stream_steps} steps", file=sys.stderr, flush=True)
@@ -557,7 +569,7 @@ def main():
         print(f"[bench] fp64 comparison: {args.fp64_steps} steps", file=sys.stderr, flush=True)
         run64 = Runner(inp, wl, "fp64", wl.chunks)
         t64 = run64.timed(args.fp64_steps, 1)
-        e64 = None if args.no_errors else sampled_errors(inp, run64.eta, run64.chi, wl)
+        e64 = None if args.no_errors else sampled_errors(inp, run64, wl)
         del run64
         torch.cuda.empty_cache()
         fp64 = {"value": units / t64, "ms_per_step": t64 * 1e3, "speedup_mixed_over_fp64": t64 / t_step,
