@@ -40,7 +40,10 @@ def exp2(x, c):
     p = c[-1]
     for k in range(len(c) - 2, -1, -1):
         p = _fma(p, t, c[k])
-    return math.ldexp(p, int(n)) if n < 1024 else math.inf
+    try:
+        return math.ldexp(p, int(n))
+    except OverflowError:
+        return math.inf
 
 
 def worst_error(c, samples=20000, seed=2):
