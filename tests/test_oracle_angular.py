@@ -3,7 +3,9 @@
 * brute force: explicit four-vectors for the neutrinos and the electron, the azimuthal
   average taken numerically on a uniform phi grid (exact for the degree-2 trigonometric
   polynomials involved), the kinematic range found numerically (|cos alpha| <= 1), and the
-  momentum-transfer integral done by adaptive quadrature in x = cos(q, q');
+  momentum-transfer integral done by adaptive quadrature in x = cos(q, q'); l = 0 and 1, on
+  both of the oracle's routes (exact Laurent terms, and the direct integrand on short
+  momentum-transfer intervals);
 * closed-form l = 0 pieces for eps > eps' (independent symbolic integration);
 * time reversal H^N(eps', eps, E + eps - eps') = H^N(eps, eps', E) and pair transposition
   H^{P,II}(eps, eps', E) = H^{P,I}(eps', eps, E).
@@ -115,9 +117,14 @@ def brute_h(avg, l, S, e, ep, E, pole):
 CASES_NES = [(20.0, 10.0, 5.0), (20.0, 10.0, 15.0), (10.0, 20.0, 15.0), (7.0, 7.0, 3.0), (3.0, 40.0, 45.0),
              (33.0, 4.5, 80.0)]
 CASES_PAIR = [(20.0, 10.0, 5.0), (20.0, 10.0, 15.0), (20.0, 10.0, 25.0), (6.0, 6.0, 4.0), (3.0, 50.0, 30.0)]
+# Short momentum-transfer intervals (k1 - k0 <= k0), where the oracle integrates the directly
+# evaluated integrand instead of the exact Laurent terms: E / eps' = 0.015, eps' / eps = 0.015,
+# eps << eps' just above threshold; pair with eps' << eps and with E near either end.
+CASES_NES_SHORT = [(20.0, 10.0, 0.15), (100.0, 1.5, 30.0), (1.5, 100.0, 98.7)]
+CASES_PAIR_SHORT = [(100.0, 1.5, 30.0), (20.0, 10.0, 0.3), (20.0, 10.0, 29.7)]
 
 
-@pytest.mark.parametrize("e,ep,E", CASES_NES)
+@pytest.mark.parametrize("e,ep,E", CASES_NES + CASES_NES_SHORT)
 @pytest.mark.parametrize("l", [0, 1])
 @pytest.mark.parametrize("S", [1, 2])
 def test_nes_vs_brute_force(e, ep, E, l, S):
@@ -127,7 +134,7 @@ def test_nes_vs_brute_force(e, ep, E, l, S):
     assert abs(got - ref) <= 5e-8 * scale, (got, ref)
 
 
-@pytest.mark.parametrize("e,ep,E", CASES_PAIR)
+@pytest.mark.parametrize("e,ep,E", CASES_PAIR + CASES_PAIR_SHORT)
 @pytest.mark.parametrize("l", [0, 1])
 @pytest.mark.parametrize("S", [1, 2])
 def test_pair_vs_brute_force(e, ep, E, l, S):

@@ -140,3 +140,68 @@ def test_interpolation_with_swapped_fractions(monkeypatch):
     monkeypatch.setattr(tab, "bilinear", bad)
     with pytest.raises(AssertionError):
         pins_tab.test_exact_on_bilinear_data()
+
+
+def _cv_flipped_couplings(sin2w=phys.SIN2W):
+    """nu_e with the nu_mu vector coupling C_V = -1/2 + 2 s_W (a dropped charged-current term)."""
+    cv = -0.5 + 2.0 * sin2w
+    b_e = ((cv + 0.5) ** 2, (cv - 0.5) ** 2)
+    good = _GOOD_COUPLINGS(sin2w)
+    return (b_e, (b_e[1], b_e[0]), good[2])
+
+
+_GOOD_COUPLINGS = phys.couplings
+
+
+def _unaveraged_nux(sin2w=phys.SIN2W):
+    """nu_x as nu_mu alone (no average over particle and antiparticle)."""
+    good = _GOOD_COUPLINGS(sin2w)
+    cv = -0.5 + 2.0 * sin2w
+    return (good[0], good[1], ((cv - 0.5) ** 2, (cv + 0.5) ** 2))
+
+
+@pytest.mark.parametrize("bad", [_cv_flipped_couplings, _unaveraged_nux])
+def test_wrong_couplings_trip_the_textbook_pins(monkeypatch, bad):
+    import test_oracle_spot_values as pins_spot
+    monkeypatch.setattr(phys, "couplings", bad)
+    with pytest.raises(AssertionError):
+        pins_spot.test_couplings_give_the_textbook_species_rates(0.2312)
+    with pytest.raises(AssertionError):
+        pins_spot.test_contraction_combines_species_with_the_textbook_couplings()
+
+
+def test_wrong_azimuthal_half_trips_the_spot_values(monkeypatch):
+    import test_oracle_spot_values as pins_spot
+
+    def bad(e, ep, E, ca, cb, cbp, sbsb, sign):
+        return ang.__dict__["_orig"](e, ep, E, ca, cb, cbp, sbsb * 2.0, sign)
+    monkeypatch.setitem(ang.__dict__, "_orig", ang._phi_average)
+    monkeypatch.setattr(ang, "_phi_average", bad)
+    with pytest.raises(AssertionError):
+        pins_spot.test_spot_values_of_the_angular_weights()
+
+
+def test_short_interval_route_slips(monkeypatch):
+    """The direct-integrand route of short momentum-transfer intervals: too few Gauss points,
+    or 1 - x without its factor 1/2, must fail the brute-force pins of the short cases."""
+    e, ep, E = pins_ang.CASES_NES_SHORT[1]
+    x2, w2 = np.polynomial.legendre.leggauss(2)
+    monkeypatch.setattr(ang, "_GL_X", x2)
+    monkeypatch.setattr(ang, "_GL_W", w2)
+    assert _brute_fails(1, 1, e, ep, E, ang.h_nes, pins_ang.brute_nes_avg, 1.0)
+    e, ep, E = pins_ang.CASES_PAIR_SHORT[0]
+    assert _brute_fails(1, 2, e, ep, E, ang.h_pair, pins_ang.brute_pair_avg, -1.0)
+    monkeypatch.undo()
+    orig = ang._nes_direct
+
+    def bad(l, S, e, ep, E, k):
+        # the Legendre factor of l = 1 with 1 - x = Q^2/(e e') instead of Q^2/(2 e e')
+        val0 = orig(0, S, e, ep, E, k)
+        if l == 0:
+            return val0
+        om = e - ep
+        x_bad = 1 - (k * k - om * om) / (e * ep)
+        return x_bad * val0
+    monkeypatch.setattr(ang, "_nes_direct", bad)
+    e, ep, E = pins_ang.CASES_NES_SHORT[0]
+    assert _brute_fails(1, 1, e, ep, E, ang.h_nes, pins_ang.brute_nes_avg, 1.0)
