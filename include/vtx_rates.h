@@ -68,12 +68,14 @@ enum vtx_status {
 
 enum vtx_precision {
   VTX_FP64 = 0,   /* every step in FP64 */
-  VTX_MIXED = 1   /* FP32 quadrature bulk (nodes, Fermi-Dirac factors, angular-weight
+  VTX_MIXED = 1   /* FP32 quadrature bulk (node coordinates, Fermi-Dirac factors, angular-weight
                      moments and their accumulation); FP64 angular-weight contraction,
                      detailed-balance factors and the per-zone contraction. Zones with
-                     |eta_e| > eta_fp64 are computed entirely in FP64 (a second, sparse
-                     pass), since their blocking factors reach exp(-|eta_e|) and FP32 ends
-                     near exp(-87) */
+                     |eta_e| > eta_fp64 take their Fermi-Dirac factors in FP64 (FP32 moments).
+                     Zones with |eta_e| > 64 run entirely in FP64, whatever eta_fp64: a task's
+                     whole integrand can then sit near exp(-|eta_e|), and FP32 ends near
+                     exp(-87). The zones of each class are computed by their own pass over the
+                     call's zones */
 };
 
 enum vtx_rule { VTX_RULE_LAGUERRE = 0, VTX_RULE_PANEL = 1 };
@@ -97,10 +99,11 @@ typedef struct {
   int32_t rule;        /* vtx_rule */
   uint32_t processes;  /* bitmask of vtx_process, nonzero (default VTX_NES | VTX_PAIR) */
   double sin2w;        /* weak mixing angle sin^2(theta_W), default 0.2312 */
-  double eta_fp64;     /* mixed precision: zones with |eta_e| > eta_fp64 run in FP64 (default 64) */
+  double eta_fp64;     /* mixed precision: zones with |eta_e| > eta_fp64 take FP64 Fermi-Dirac
+                          factors (default 30) */
 } vtx_opts;
 
-/* Fill *opts with the defaults: FP64, 48 nodes, PANEL, both processes, 0.2312, 64. */
+/* Fill *opts with the defaults: FP64, 48 nodes, PANEL, both processes, 0.2312, 30. */
 void vtx_opts_default(vtx_opts* opts);
 
 /*

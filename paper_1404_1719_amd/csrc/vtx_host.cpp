@@ -438,7 +438,7 @@ void vtx_opts_default(vtx_opts* o) {
   o->rule = VTX_RULE_PANEL;
   o->processes = VTX_NES | VTX_PAIR;
   o->sin2w = 0.2312;
-  o->eta_fp64 = 64.0;
+  o->eta_fp64 = 30.0;
 }
 
 int vtx_rates_forward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,

@@ -13,9 +13,10 @@
 // combination and the contraction with f run from LDS, and the only HBM writes are eta/chi
 // (or the gradients). The work is VALU bound with no dense contraction, so MFMA has no role.
 //
-// Mixed precision runs the bulk in FP32; zones with |eta_e| above a threshold (where
-// exp(-|eta_e|)-sized blocking factors approach the end of the FP32 range) are computed
-// entirely in FP64 by a second, sparse pass that scans the zones and takes only those.
+// Mixed precision runs the bulk in FP32 (node coordinates, Fermi-Dirac factors, angular-weight
+// moments and their accumulation) with FP64 contractions and detailed-balance factors; zones
+// with |eta_e| above a threshold take their Fermi-Dirac factors in FP64 (a second pass over
+// the zones with the same node loops, the blocking factor from one FP64 exponential).
 #include <hip/hip_runtime.h>
 
 #include "../../include/vtx_rates.h"
@@ -51,18 +52,18 @@ __device__ __forceinline__ double beta_of(const DevPlan& P, int s, int S) {
   return s == 0 ? b0 : (s == 1 ? b1 : b2);
 }
 
-// 2^x in FP64: x = n + f with n = rint(x), |f| <= 1/2, and 2^f = e^t, t = f ln 2 (|t| < 0.35),
-// from the degree-10 Chebyshev interpolant of e^t on [-ln2/2, ln2/2] in monomial form (derived
-// by gen/exp2_coeffs.py; worst relative error of the whole evaluation 4.2e-16); 2^n enters
-// through ldexp. x is clamped to +-2100 first, beyond which 2^x rounds to 0 or +inf anyway, so
-// infinite arguments give those limits too.
+// 2^x in FP64 for x <= 1000 (callers cap larger arguments): x = n + f with n = rint(x),
+// |f| <= 1/2, and 2^f = e^t, t = f ln 2 (|t| < 0.35), from the degree-10 Chebyshev interpolant of
+// e^t on [-ln2/2, ln2/2] in monomial form (derived by gen/exp2_coeffs.py; worst relative error
+// of the whole evaluation 4.2e-16); 2^n enters through ldexp. x is clamped below at -2100,
+// beyond which 2^x rounds to 0 anyway, so -inf gives 0 too.
 __device__ __forceinline__ double exp2_fp64(double x) {
   constexpr double kLn2 = 0.6931471805599453;
   constexpr double kExpPoly[11] = {1.0, 1.0000000000000067, 0.5000000000000006, 0.16666666666554406,
                                    0.04166666666657314, 0.008333333385667782, 0.0013888888932488599,
                                    0.00019841170270440067, 2.4801504346997686e-05, 2.764018079620985e-06,
                                    2.7626357241447223e-07};
-  const double xc = fmin(fmax(x, -2100.0), 2100.0);
+  const double xc = fmax(x, -2100.0);
   const double n = rint(xc);
   const double t = (xc - n) * kLn2;
   double p = kExpPoly[10];
@@ -71,33 +72,85 @@ __device__ __forceinline__ double exp2_fp64(double x) {
   return ldexp(p, int(n));
 }
 
-// 1/x for the blocking denominators (x >= 1, or +inf): the hardware estimate refined by two
-// Newton steps, e = 1 - x r, r += r e (about 1 ulp). x is capped at 2^1000, so +inf gives
-// 2^-1000 rather than inf x 0 = NaN in the refinement.
-__device__ __forceinline__ double recip_ge1(double x) {
-  const double xc = fmin(x, 0x1p1000);
-  double r = __builtin_amdgcn_rcp(xc);
-  double e = __builtin_fma(-xc, r, 1.0);
+// 1/x for x in [1, 2^1010]: the hardware estimate refined by two Newton steps, e = 1 - x r,
+// r += r e (about 1 ulp).
+__device__ __forceinline__ double recip_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
   r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-xc, r, 1.0);
+  e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
 }
 
-// Arithmetic of the bulk type. Both paths carry the Fermi-Dirac arguments pre-scaled by
-// log2(e), so exp(-z) is an exp2: one hardware instruction in FP32, exp2_fp64 in FP64.
+// Precision of a kernel: R, the bulk type (piece variable, node weights, angular-weight moments
+// and their accumulation), and F, the type of the Fermi-Dirac arguments and blocking factors.
+// The mixed path runs Fp32 on zones of moderate degeneracy and Fd64 (Fermi-Dirac factors in
+// FP64, the rest as Fp32) on zones with |eta_e| above its threshold; the FP64 path runs Fp64.
+struct Fp32 {
+  using R = float;
+  using F = float;
+};
+struct Fd64 {
+  using R = float;
+  using F = double;
+};
+struct Fp64 {
+  using R = double;
+  using F = double;
+};
+
+// Arithmetic of a type. The Fermi-Dirac arguments are carried pre-scaled by log2(e), so
+// exp(-z) is an exp2.
 template <typename R> struct Num;
 template <> struct Num<double> {
-  static constexpr double zscale = kLog2e;
-  __device__ static __forceinline__ double exp_neg(double z) { return exp2_fp64(-z); }
-  __device__ static __forceinline__ double recip(double x) { return recip_ge1(x); }
   __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 };
 template <> struct Num<float> {
-  static constexpr double zscale = kLog2e;
-  __device__ static __forceinline__ float exp_neg(float z) { return __builtin_amdgcn_exp2f(-z); }
-  __device__ static __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
   __device__ static __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 };
+
+// Blocking factor B = sigma(z1) sigma(z2), sigma(z) = 1 / (1 + 2^-z), and (backward) the
+// logarithmic derivatives r = 1 - sigma(z) of its two factors.
+//
+// FP32: two hardware exp2 and one reciprocal (two in the backward). Where 2^-z overflows to
+// +inf the sums stay +inf (never inf x 0), so B = 0, sigma = 0 and r = 1 are the limits.
+//
+// FP64 (one exponential): the two arguments sum to the task constant K = D log2(e) / T >= 0
+// (scattering D = eps_i - eps_j, pair D = eps_i + eps_j), so the smaller one, t, is at most K/2,
+// and the other factor's 2^-(K - t) equals C a with a = 2^t and C = 2^-K (a task constant):
+//   B = a / ((1 + a)(1 + C a)),  1 - sigma(t) = 1 / (1 + a),  1 - sigma(K - t) = C a / (1 + C a),
+// all from one reciprocal. C a <= 1, and t is capped at 1000, where both factors are 1 to FP64
+// precision (the other argument is then at least as large), so the denominator stays finite;
+// a very negative t gives a = 0 and B = 0. Where C underflows (K above 1074), C a <= 2^(-K/2)
+// and the second factor is 1 to FP64 precision.
+__device__ __forceinline__ float blocking_fwd(float z1, float z2, float) {
+  const float a = __builtin_amdgcn_exp2f(-z1), b = __builtin_amdgcn_exp2f(-z2);
+  return __builtin_amdgcn_rcpf((1.0f + a) * (1.0f + b));
+}
+__device__ __forceinline__ double blocking_fwd(double z1, double z2, double C) {
+  const double a = exp2_fp64(fmin(fmin(z1, z2), 1000.0));
+  return a * recip_pos((1.0 + a) * __builtin_fma(C, a, 1.0));
+}
+
+template <typename R>
+__device__ __forceinline__ void blocking_bwd(float z1, float z2, float, R& B, R& r1, R& r2) {
+  const float i1 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z1));
+  const float i2 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z2));
+  B = i1 * i2;
+  r1 = 1.0f - i1;
+  r2 = 1.0f - i2;
+}
+template <typename R>
+__device__ __forceinline__ void blocking_bwd(double z1, double z2, double C, R& B, R& r1, R& r2) {
+  const bool first = z1 <= z2;
+  const double a = exp2_fp64(fmin(first ? z1 : z2, 1000.0));
+  const double ca = C * a, d1 = 1.0 + a, d2 = 1.0 + ca;
+  const double q = recip_pos(d1 * d2);
+  B = R(a * q);
+  const R rt = R(d2 * q), ro = R(ca * (d1 * q));
+  r1 = first ? rt : ro;
+  r2 = first ? ro : rt;
+}
 
 // A breakpoint: value and its derivatives along T (eta_e fixed) and along eta_e (T fixed).
 struct Tri {
@@ -122,8 +175,10 @@ struct Zone {
   int k;       // #{eps_j < mu_e}: selects the task order
 };
 
-template <typename R> __device__ void stage_tab(const DevPlan& P, R* tab);
-template <> __device__ void stage_tab<double>(const DevPlan& P, double* tab) {
+// Node tables of a kernel in LDS: the bulk type's (piece variable, weights) and, where the
+// Fermi-Dirac type differs, a second one in that type for the Fermi-Dirac arguments. Both
+// have the same layout, so a map's offset serves either.
+__device__ __forceinline__ void fill_tab(const DevPlan& P, double* tab) {
   for (int k = threadIdx.x; k < P.m4; k += blockDim.x) {
     const double4 n = P.leg64[k];
     tab[kOffX + k] = n.x;
@@ -137,7 +192,7 @@ template <> __device__ void stage_tab<double>(const DevPlan& P, double* tab) {
     tab[kOffOne + k] = 1.0;
   }
 }
-template <> __device__ void stage_tab<float>(const DevPlan& P, float* tab) {
+__device__ __forceinline__ void fill_tab(const DevPlan& P, float* tab) {
   for (int k = threadIdx.x; k < P.m4; k += blockDim.x) {
     const float4 n = P.leg32[k];
     tab[kOffX + k] = n.x;
@@ -149,6 +204,34 @@ template <> __device__ void stage_tab<float>(const DevPlan& P, float* tab) {
     tab[kOffGX + k] = n.x;
     tab[kOffGW + k] = n.z;
     tab[kOffOne + k] = 1.0f;
+  }
+}
+
+template <typename Pr>
+struct Tabs {
+  const typename Pr::R* r;   // piece variable, weights, end weights
+  const typename Pr::F* f;   // Fermi-Dirac arguments
+};
+
+// LDS bytes of a kernel's node tables.
+template <typename Pr>
+constexpr int tab_bytes() {
+  return kTabLen * (int)(sizeof(typename Pr::R) +
+                         (sizeof(typename Pr::R) == sizeof(typename Pr::F) ? 0 : sizeof(typename Pr::F)));
+}
+
+template <typename Pr>
+__device__ __forceinline__ Tabs<Pr> stage_tabs(const DevPlan& P, double* raw) {
+  using R = typename Pr::R;
+  using F = typename Pr::F;
+  R* tr = reinterpret_cast<R*>(raw);
+  fill_tab(P, tr);
+  if constexpr (sizeof(R) == sizeof(F)) {
+    return {tr, reinterpret_cast<const F*>(tr)};
+  } else {
+    F* tf = reinterpret_cast<F*>(raw + (kTabLen * sizeof(R) + 7) / 8);
+    fill_tab(P, tf);
+    return {tr, tf};
   }
 }
 
@@ -314,15 +397,20 @@ __device__ __forceinline__ EndV end_values(const Task& K, const GroupDesc& G, co
 // Node-loop parameters: value_k = c0 + c1 tab[off + k] per map; tab[ow + k] is the weight.
 // A Legendre map is anchored at the end where it is smaller in magnitude (reading x or
 // 1 - x), so that FP32 evaluation never subtracts two large numbers. Breakpoints sit on the
-// zeros of the Fermi-Dirac arguments, so inside a group each argument keeps its sign.
-template <typename R>
+// zeros of the Fermi-Dirac arguments, so inside a group each argument keeps its sign. The
+// Fermi-Dirac maps (a, b) are in the kernel's Fermi-Dirac type, with C = 2^-K the task constant
+// of the one-exponential FP64 blocking factor (unused in FP32).
+template <typename Pr>
 struct Loop {
-  R u0, u1, a0, a1, b0, b1, split;
+  using R = typename Pr::R;
+  using F = typename Pr::F;
+  R u0, u1, split;
+  F a0, a1, b0, b1, C;
   int ou, o1, o2, ow;
   int oa, ob;   // backward: weights of the group's two end points, 1 - x and x (tail: 1 and x)
 };
 
-// Anchored map from its end values (already in the bulk type): value = c0 + c1 x with x read
+// Anchored map from its end values (already in the map's type): value = c0 + c1 x with x read
 // from the column of x or 1 - x. The FP64 end values are rounded first, so c1 carries the
 // rounding of the larger end, as the node values themselves would.
 template <typename R>
@@ -335,22 +423,28 @@ __device__ __forceinline__ void anchor(R a, R b, R& c0, R& c1, int& off) {
 }
 
 // Returns the group's weight scale Es (nodes weigh Es w_k). The Fermi-Dirac arguments are
-// formed in the units of the bulk type's exponential (Num<R>::zscale).
-template <typename R>
-__device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, const Zone& Z, Loop<R>& L) {
-  const double zs = Num<R>::zscale, its = Z.invT * zs;
+// formed in units of log2(e), so that exp(-z) is an exp2.
+template <typename Pr>
+__device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, const Zone& Z, Loop<Pr>& L) {
+  using R = typename Pr::R;
+  using F = typename Pr::F;
+  const double zs = kLog2e, its = Z.invT * zs;
   const double dA = Z.mu - G.lo.v;
   const double uA = G.c ? (G.w - G.lo.v) * G.ub : G.lo.v * G.ub;
   const double z1A = K.sg * dA * its, z2A = (K.D - K.sg * dA) * its;
+  if constexpr (sizeof(F) == sizeof(double))
+    L.C = exp2_fp64(-(K.D * its));
+  else
+    L.C = F(0);
   double Es;
   if (G.lag) {
     Es = Z.T;
     L.u0 = R(uA);
     L.u1 = R((G.c ? -G.ub : G.ub) * Z.T);
-    L.a0 = R(z1A);
-    L.a1 = R(-K.sg * zs);
-    L.b0 = R(z2A);
-    L.b1 = R(K.sg * zs);
+    L.a0 = F(z1A);
+    L.a1 = F(-K.sg * zs);
+    L.b0 = F(z2A);
+    L.b1 = F(K.sg * zs);
     L.ou = L.o1 = L.o2 = kOffGX + G.toff;
     L.ow = kOffGW + G.toff;
     L.oa = kOffOne + G.toff;
@@ -360,8 +454,8 @@ __device__ __forceinline__ double make_loop(const Task& K, const GroupDesc& G, c
     const double dB = Z.mu - G.hi.v;
     const double uB = G.c ? (G.w - G.hi.v) * G.ub : G.hi.v * G.ub;
     anchor<R>(R(uA), R(uB), L.u0, L.u1, L.ou);
-    anchor<R>(R(z1A), R(K.sg * dB * its), L.a0, L.a1, L.o1);
-    anchor<R>(R(z2A), R((K.D - K.sg * dB) * its), L.b0, L.b1, L.o2);
+    anchor<F>(F(z1A), F(K.sg * dB * its), L.a0, L.a1, L.o1);
+    anchor<F>(F(z2A), F((K.D - K.sg * dB) * its), L.b0, L.b1, L.o2);
     L.ow = kOffW;
     L.oa = kOffY;
     L.ob = kOffX;
@@ -396,15 +490,16 @@ __device__ __forceinline__ int wave_mode(int m) {
 // k = 0..2. Both bases are nonnegative on their ranges, so the FP32 sums are free of
 // cancellation; sign changes of the l = 1 weights resolve in the FP64 contraction.
 
-template <typename R, int MODE>
-__device__ __forceinline__ void node_fwd(const Loop<R>& L, R xu, R x1, R x2, R w, R M[5], R H[3]) {
+template <typename Pr, int MODE>
+__device__ __forceinline__ void node_fwd(const Loop<Pr>& L, typename Pr::R xu, typename Pr::F x1,
+                                         typename Pr::F x2, typename Pr::R w, typename Pr::R M[5],
+                                         typename Pr::R H[3]) {
+  using R = typename Pr::R;
+  using F = typename Pr::F;
   using N = Num<R>;
   const R u = N::fma(L.u1, xu, L.u0);
-  const R z1 = N::fma(L.a1, x1, L.a0), z2 = N::fma(L.b1, x2, L.b0);
-  // exp(-z) may overflow to +inf in a tail while the other factor is 1: the product of the
-  // two sums then stays +inf (never inf x 0), and the blocking factor 0
-  const R a = N::exp_neg(z1), b = N::exp_neg(z2);
-  const R wB = w * N::recip((R(1) + a) * (R(1) + b));
+  const F z1 = Num<F>::fma(L.a1, x1, L.a0), z2 = Num<F>::fma(L.b1, x2, L.b0);
+  const R wB = w * R(blocking_fwd(z1, z2, L.C));
   R ul = u, wh = wB;
   if (MODE == kGen) {
     const bool lo = u < L.split;
@@ -429,22 +524,32 @@ __device__ __forceinline__ void node_fwd(const Loop<R>& L, R xu, R x1, R x2, R w
   }
 }
 
-template <typename R, int MODE>
-__device__ __forceinline__ void nodes_fwd(const Loop<R>& L, int m, const R* tab, R M[5], R H[3]) {
+// Nodes in flight per lane: four in FP32; two where the bulk is FP64, whose exp2 chains are
+// long and whose registers are twice as many.
+template <typename Pr, int MODE>
+__device__ __forceinline__ void nodes_fwd(const Loop<Pr>& L, int m, const Tabs<Pr>& tb, typename Pr::R M[5],
+                                          typename Pr::R H[3]) {
+  if constexpr (sizeof(typename Pr::R) == 8) {
+#pragma unroll 2
+    for (int k = 0; k < m; ++k)
+      node_fwd<Pr, MODE>(L, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], M, H);
+  } else {
 #pragma unroll 4
-  for (int k = 0; k < m; ++k)
-    node_fwd<R, MODE>(L, tab[L.ou + k], tab[L.o1 + k], tab[L.o2 + k], tab[L.ow + k], M, H);
+    for (int k = 0; k < m; ++k)
+      node_fwd<Pr, MODE>(L, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], M, H);
+  }
 }
 
-template <typename R>
-__device__ __forceinline__ void run_nodes_fwd(int mode, const Loop<R>& L, int m, const R* tab, R M[5], R H[3]) {
+template <typename Pr>
+__device__ __forceinline__ void run_nodes_fwd(int mode, const Loop<Pr>& L, int m, const Tabs<Pr>& tb,
+                                              typename Pr::R M[5], typename Pr::R H[3]) {
   const int wm = wave_mode(mode);
   if (wm == kLow)
-    nodes_fwd<R, kLow>(L, m, tab, M, H);
+    nodes_fwd<Pr, kLow>(L, m, tb, M, H);
   else if (wm == kHigh)
-    nodes_fwd<R, kHigh>(L, m, tab, M, H);
+    nodes_fwd<Pr, kHigh>(L, m, tb, M, H);
   else
-    nodes_fwd<R, kGen>(L, m, tab, M, H);
+    nodes_fwd<Pr, kGen>(L, m, tb, M, H);
 }
 
 // Moment slots of a task: slot 0 low (scattering; pair piece A), high (scattering; pair
@@ -522,8 +627,9 @@ __device__ __forceinline__ Q4 contract_task(const DevPlan& P, const Task& K, int
   return {q[0], q[1], q[2], q[3]};
 }
 
-template <typename R, bool PAIR>
-__device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const Zone& Z, int t) {
+template <typename Pr, bool PAIR>
+__device__ __forceinline__ Q4 task_forward(const DevPlan& P, const Tabs<Pr>& tb, const Zone& Z, int t) {
+  using R = typename Pr::R;
   const Task K = make_task<PAIR>(P, t);
   const Brk Bk = task_breakpoints<PAIR>(K, Z);
   Slots<R> S = {};
@@ -533,10 +639,10 @@ __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const
     const Tri lo = g == 0 ? zero : group_hi<PAIR>(K, Bk, g - 1);
     const GroupDesc G = describe<PAIR>(P, K, Bk, g, lo, group_hi<PAIR>(K, Bk, g));
     if (wave_skips(G)) continue;
-    Loop<R> L;
-    const double Es = make_loop<R>(K, G, Z, L);
+    Loop<Pr> L;
+    const double Es = make_loop<Pr>(K, G, Z, L);
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0};
-    run_nodes_fwd<R>(G.mode, L, P.m4, tab, M, H);
+    run_nodes_fwd<Pr>(G.mode, L, P.m4, tb, M, H);
     add_group<R>(G, Es, M, H, S);
   }
   return contract_task<R, PAIR>(P, K, t, S);
@@ -548,11 +654,25 @@ __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const R* tab, const
 // exp(-(eps_i + eps_j)/T) [ne^2] | contraction parts; the backward also holds g_eta, g_chi
 // [12 ne] after f.
 
-// Zone selection of a pass: every zone, or the zones the FP32 pass takes (|eta_e| not above
-// the threshold, which includes values that do not compare).
-constexpr int kSelAll = 0, kSelBulk = 1;
+// Zone selection of a pass. The FP64 path takes every zone. The mixed path splits them into
+// three classes by |eta_e|: up to its threshold (and values that do not compare) FP32
+// throughout; above it FP64 Fermi-Dirac factors with FP32 moments; above kFp32Range entirely
+// FP64. The last guards range, not accuracy: a task's whole integrand can sit near e^-|eta_e|
+// (pair annihilation with mu_e above eps_i + eps_j), and FP32 moments end near e^-87.
+constexpr int kSelAll = 0, kSelBulk = 1, kSelFd = 2, kSelHigh = 3;
+constexpr double kFp32Range = 64.0;
 
-__device__ void stage_zone_state(const DevPlan& P, int64_t z, int selm, const double* Tz, const double* etaz,
+__device__ __forceinline__ bool selected(const DevPlan& P, int selm, double eta) {
+  const double a = fabs(eta), lo = fmin(P.eta_fp64, kFp32Range);
+  switch (selm) {
+    case kSelBulk: return !(a > lo);
+    case kSelFd: return a > lo && a <= kFp32Range;
+    case kSelHigh: return a > kFp32Range;
+    default: return true;
+  }
+}
+
+__device__ void stage_zone_state(const DevPlan& P, int64_t z, const double* Tz, const double* etaz,
                                  Zone* zs) {   // zs[0]: the zone, zs[1]: its mirror
   if (threadIdx.x == 0) {
     Zone Z;
@@ -560,7 +680,6 @@ __device__ void stage_zone_state(const DevPlan& P, int64_t z, int selm, const do
     Z.valid = z >= 0;
     Z.T = Z.valid ? Tz[z] : 1.0;
     Z.eta = Z.valid ? etaz[z] : 0.0;
-    if (selm == kSelBulk && fabs(Z.eta) > P.eta_fp64) Z.valid = 0;
     Z.invT = 1.0 / Z.T;
     Z.mu = Z.eta * Z.T;
     Zone M = Z;
@@ -805,11 +924,11 @@ __device__ __forceinline__ void zone_contract(const DevPlan& P, const Zone& Z, c
 }
 
 // Scattering task at position pos of the zone's task order: its four values into its slot.
-template <typename R>
-__device__ __forceinline__ void scattering_fwd(const DevPlan& P, const R* tab, const Zone& Z, double* slots,
+template <typename Pr>
+__device__ __forceinline__ void scattering_fwd(const DevPlan& P, const Tabs<Pr>& tb, const Zone& Z, double* slots,
                                                int pos) {
   const int t = P.task_order[Z.k * P.ntn + pos];
-  const Q4 q = task_forward<R, false>(P, tab, Z, t);
+  const Q4 q = task_forward<Pr, false>(P, tb, Z, t);
   double* o = slots + 4 * t;
   o[0] = q.a;
   o[1] = q.b;
@@ -859,8 +978,8 @@ __device__ void export_tasks(const DevPlan& P, const Zone& Z, const double* smem
 // Forward of one zone: task values into LDS, then the contraction with f into eta, chi, or
 // the explicit Jacobian blocks, which need no f (and the contraction as well when eta_out
 // is given), or the task values themselves.
-template <typename R, int OUT, bool NPS>
-__device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* smem, int64_t z, int selm,
+template <typename Pr, int OUT, bool NPS>
+__device__ void zone_forward(const DevPlan& P, const Tabs<Pr>& tb, Zone* zs, double* smem, int64_t z,
                              const double* __restrict__ Tz, const double* __restrict__ etaz,
                              const double* __restrict__ f, double* __restrict__ eta_out,
                              double* __restrict__ chi_out, double* __restrict__ jac) {
@@ -871,10 +990,9 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   // task counts: scattering tasks (i >= j) on electrons and on positrons, pair tasks (one per
   // unordered pair {i, j})
   const int ntn = do_nes ? P.ntn : 0, ntm = do_nps ? P.ntn : 0, ntp = do_pair ? P.ntn : 0;
-  stage_zone_state(P, z, selm, Tz, etaz, zs);
+  stage_zone_state(P, z, Tz, etaz, zs);
   __syncthreads();
   const Zone& Z = zs[0];
-  if (!Z.valid) return;   // uniform: every lane reads the same zone state
   if (OUT == kOutRates || eta_out != nullptr)
     for (int r = threadIdx.x; r < 6 * ne; r += blockDim.x) smem[r] = f[Z.z * 6 * ne + r];
   stage_factors(P, Z, smem + L.d);
@@ -886,12 +1004,12 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
     if (u < U.nN + U.nM) {
       const bool mir = NPS && u >= U.nN;
       const int pos = ((mir ? u - U.nN : u) << 6) + lane;
-      if (pos < (mir ? ntm : ntn)) scattering_fwd<R>(P, tab, zs[mir ? 1 : 0], smem + (mir ? L.m : L.q), pos);
+      if (pos < (mir ? ntm : ntn)) scattering_fwd<Pr>(P, tb, zs[mir ? 1 : 0], smem + (mir ? L.m : L.q), pos);
     } else {
       const int pos = ((u - U.nN - U.nM) << 6) + lane;
       if (pos < ntp) {
         const int t = P.task_order[Z.k * P.ntn + pos], ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
-        const Q4 q = task_forward<R, true>(P, tab, Z, t);
+        const Q4 q = task_forward<Pr, true>(P, tb, Z, t);
         double* o = smem + L.p + 2 * (i * ne + j);
         o[0] = q.a;
         o[1] = q.b;
@@ -913,53 +1031,29 @@ __device__ void zone_forward(const DevPlan& P, const R* tab, Zone* zs, double* s
   zone_contract<NPS>(P, Z, smem, L, smem + L.d + 2 * n2, eta_out, chi_out);
 }
 
-// Dense pass: workgroup b takes zone b (if selected). Occupancy targets: five waves per SIMD
-// for FP32 (at most 102 VGPRs; five one-zone workgroups of 31 KB fill the 160 KB of LDS at
-// 21 bins), three for FP64 (four would spill).
-template <typename R, int OUT, bool NPS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 3)))
+// Workgroup b takes zone b, if the pass selects it. Occupancy targets (waves per SIMD): Fp32
+// five (at most 102 VGPRs; five one-zone workgroups of 31 KB fill the 160 KB of LDS at 21
+// bins), Fd64 and Fp64 three (four would spill); the FP64 export of task values for tables
+// (built once per lattice) two, where three would spill.
+template <typename Pr, int OUT>
+constexpr int fwd_waves() {
+  return sizeof(typename Pr::R) == 8 ? ((OUT == kOutTasks || OUT == kOutTable) ? 2 : 3)
+                                     : (sizeof(typename Pr::F) == 8 ? 3 : 5);
+}
+
+template <typename Pr, int OUT, bool NPS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fwd_waves<Pr, OUT>())))
 void rates_forward_kernel(DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz,
                           const double* __restrict__ etaz, const double* __restrict__ f,
                           double* __restrict__ eta_out, double* __restrict__ chi_out, double* __restrict__ jac) {
-  __shared__ R tab[kTabLen];
+  __shared__ double tab[(tab_bytes<Pr>() + 7) / 8];
   __shared__ Zone zs[2];
   extern __shared__ double smem[];
-  stage_tab<R>(P, tab);
   const int64_t z = blockIdx.x;
-  zone_forward<R, OUT, NPS>(P, tab, zs, smem, z < nz ? z : -1, selm, Tz, etaz, f, eta_out, chi_out, jac);
+  if (z >= nz || !selected(P, selm, etaz[z])) return;   // uniform: one zone per workgroup
+  const Tabs<Pr> tb = stage_tabs<Pr>(P, tab);
+  zone_forward<Pr, OUT, NPS>(P, tb, zs, smem, z, Tz, etaz, f, eta_out, chi_out, jac);
 }
-
-// Sparse FP64 pass: workgroups scan windows of blockDim zones and run the zones with
-// |eta_e| above the threshold, one at a time. The scan order does not change any result.
-template <int OUT, bool NPS>
-__global__ __launch_bounds__(kBlock) void rates_forward_sparse(DevPlan P, int64_t nz, const double* __restrict__ Tz,
-                                                                  const double* __restrict__ etaz,
-                                                                  const double* __restrict__ f,
-                                                                  double* __restrict__ eta_out,
-                                                                  double* __restrict__ chi_out,
-                                                                  double* __restrict__ jac) {
-  __shared__ double tab[kTabLen];
-  __shared__ Zone zs[2];
-  __shared__ int list[kBlock];
-  __shared__ int count;
-  extern __shared__ double smem[];
-  stage_tab<double>(P, tab);
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nz; base += (int64_t)gridDim.x * blockDim.x) {
-    if (threadIdx.x == 0) count = 0;
-    __syncthreads();
-    const int64_t z = base + threadIdx.x;
-    if (z < nz && fabs(etaz[z]) > P.eta_fp64) list[atomicAdd(&count, 1)] = (int)threadIdx.x;
-    __syncthreads();
-    const int n = count;
-    for (int c = 0; c < n; ++c) {
-      zone_forward<double, OUT, NPS>(P, tab, zs, smem, base + list[c], kSelAll, Tz, etaz, f, eta_out, chi_out,
-                                     jac);
-      __syncthreads();
-    }
-    __syncthreads();   // every lane has read count before the next window resets it
-  }
-}
-
 
 // Interpolated forward: a zone's task values interpolated bilinearly from a table of task
 // values on a regular lattice of zone states in (ln T, eta_e) (rows in the export layout, in
@@ -976,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   __shared__ Zone zs[2];
   extern __shared__ double smem[];
   const int64_t z = blockIdx.x;
-  stage_zone_state(P, z < nz ? z : -1, kSelAll, Tz, etaz, zs);
+  stage_zone_state(P, z < nz ? z : -1, Tz, etaz, zs);
   __syncthreads();
   const Zone& Z = zs[0];
   if (!Z.valid) return;   // uniform
@@ -1187,17 +1281,21 @@ __device__ __forceinline__ R adjoint_sum(const AdjPoly<R>& Q, const R M[5], cons
 // Per node, x0 = w B H (H the adjoint-weighted angular weight) and yu = w B dH/du. S[1..4]
 // collect x0 r1 and x0 r2 (r = d ln sigma / dz of each blocking factor) times the end weights
 // pa and pb; S[5..6] collect yu times pa and pb; S[0] = sum x0 is adjoint_sum afterwards.
-template <typename R, int MODE>
-__device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, R xu, R x1, R x2, R w, R pa, R pb,
-                                         R M[5], R H[3], R S[7]) {
+template <typename Pr, int MODE>
+__device__ __forceinline__ void node_bwd(const Loop<Pr>& L, const AdjPoly<typename Pr::R>& Q, typename Pr::R xu,
+                                         typename Pr::F x1, typename Pr::F x2, typename Pr::R w,
+                                         typename Pr::R pa, typename Pr::R pb, typename Pr::R M[5],
+                                         typename Pr::R H[3], typename Pr::R S[7]) {
+  using R = typename Pr::R;
+  using F = typename Pr::F;
   using N = Num<R>;
   const R u = N::fma(L.u1, xu, L.u0);
-  const R z1 = N::fma(L.a1, x1, L.a0), z2 = N::fma(L.b1, x2, L.b0);
-  // sigma(z) = i and sigma(-z) = 1 - i = r. Where exp(-z) overflows to +inf, i = 0 and
-  // r = 1 are the limits, so no argument needs a clamp.
-  const R i1 = N::recip(R(1) + N::exp_neg(z1)), i2 = N::recip(R(1) + N::exp_neg(z2));
-  const R wB = w * (i1 * i2);
-  const R r1 = R(1) - i1, r2 = R(1) - i2;
+  const F z1 = Num<F>::fma(L.a1, x1, L.a0), z2 = Num<F>::fma(L.b1, x2, L.b0);
+  // B = sigma(z1) sigma(z2) and r = 1 - sigma(z) of each factor; where exp(-z) overflows,
+  // sigma = 0 and r = 1 are the limits, so no argument needs a clamp
+  R B, r1, r2;
+  blocking_bwd<R>(z1, z2, L.C, B, r1, r2);
+  const R wB = w * B;
   R ul = u, wh = wB;
   if (MODE == kGen) {
     const bool lo = u < L.split;
@@ -1242,25 +1340,27 @@ __device__ __forceinline__ void node_bwd(const Loop<R>& L, const AdjPoly<R>& Q, 
   S[6] = N::fma(yu, pb, S[6]);
 }
 
-template <typename R, int MODE>
-__device__ __forceinline__ void nodes_bwd(const Loop<R>& L, const AdjPoly<R>& Q, int m, const R* tab, R M[5],
-                                          R H[3], R S[7]) {
+template <typename Pr, int MODE>
+__device__ __forceinline__ void nodes_bwd(const Loop<Pr>& L, const AdjPoly<typename Pr::R>& Q, int m,
+                                          const Tabs<Pr>& tb, typename Pr::R M[5], typename Pr::R H[3],
+                                          typename Pr::R S[7]) {
 #pragma unroll 2
   for (int k = 0; k < m; ++k)
-    node_bwd<R, MODE>(L, Q, tab[L.ou + k], tab[L.o1 + k], tab[L.o2 + k], tab[L.ow + k], tab[L.oa + k],
-                      tab[L.ob + k], M, H, S);
+    node_bwd<Pr, MODE>(L, Q, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], tb.r[L.oa + k],
+                       tb.r[L.ob + k], M, H, S);
 }
 
-template <typename R>
-__device__ __forceinline__ void run_nodes_bwd(int mode, const Loop<R>& L, const AdjPoly<R>& Q, int m, const R* tab,
-                                              R M[5], R H[3], R S[7]) {
+template <typename Pr>
+__device__ __forceinline__ void run_nodes_bwd(int mode, const Loop<Pr>& L, const AdjPoly<typename Pr::R>& Q, int m,
+                                              const Tabs<Pr>& tb, typename Pr::R M[5], typename Pr::R H[3],
+                                              typename Pr::R S[7]) {
   const int wm = wave_mode(mode);
   if (wm == kLow)
-    nodes_bwd<R, kLow>(L, Q, m, tab, M, H, S);
+    nodes_bwd<Pr, kLow>(L, Q, m, tb, M, H, S);
   else if (wm == kHigh)
-    nodes_bwd<R, kHigh>(L, Q, m, tab, M, H, S);
+    nodes_bwd<Pr, kHigh>(L, Q, m, tb, M, H, S);
   else
-    nodes_bwd<R, kGen>(L, Q, m, tab, M, H, S);
+    nodes_bwd<Pr, kGen>(L, Q, m, tb, M, H, S);
 }
 
 // Derivatives of the map values at a group end E (a breakpoint with its derivatives):
@@ -1306,9 +1406,10 @@ __device__ __forceinline__ void group_grad(const Task& K, const GroupDesc& G, co
 // (scattering: the four (S, l); pair: l = 0, 1 of both orientations). Returns the task
 // values q and adds d/dT, d/deta_e to gT, gE. lq: the lane's LDS slot (13 values, stride
 // kBlock) that holds a pair task's adjoint-weighted piece coefficients A[5] | B[3] | C[5].
-template <typename R, bool PAIR>
-__device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, const Zone& Z, int t, const Q4& adj,
-                                            R* lq, double& gT, double& gE) {
+template <typename Pr, bool PAIR>
+__device__ __forceinline__ Q4 task_backward(const DevPlan& P, const Tabs<Pr>& tb, const Zone& Z, int t, const Q4& adj,
+                                            typename Pr::R* lq, double& gT, double& gE) {
+  using R = typename Pr::R;
   const Task K = make_task<PAIR>(P, t);
   const Brk Bk = task_breakpoints<PAIR>(K, Z);
   Slots<R> Sl = {};
@@ -1345,8 +1446,8 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
     const GroupDesc G = describe<PAIR>(P, K, Bk, g, lo, hi);
     lo = hi;
     if (wave_skips(G)) continue;
-    Loop<R> L;
-    const double Es = make_loop<R>(K, G, Z, L);
+    Loop<Pr> L;
+    const double Es = make_loop<Pr>(K, G, Z, L);
     if (PAIR) {
       // the group's piece: A (slots 0-4), B (5-7) or C (8-12); the other part stays zero
       const R* pl = lq + (G.piece == 2 ? 8 : 0) * kBlock;
@@ -1358,7 +1459,7 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const R* tab, cons
       make_adj_poly_r<R>(lo, hi, Q);
     }
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0}, S[7] = {0, 0, 0, 0, 0, 0, 0};
-    run_nodes_bwd<R>(G.mode, L, Q, P.m4, tab, M, H, S);
+    run_nodes_bwd<Pr>(G.mode, L, Q, P.m4, tb, M, H, S);
     S[0] = adjoint_sum<R>(Q, M, H);
     add_group<R>(G, Es, M, H, Sl);
     group_grad<R>(K, G, Z, Es, S, gT, gE);
@@ -1378,10 +1479,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // holds the completion weights until the task values replace them. On positron targets
 // (swap) the component (S, l) carries the couplings of the other S, so the weights of S = I
 // and S = II trade places.
-template <typename R>
-__device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
-                                             const double* s_d, double* s_u, bool swap, R* lq, int t, double& dT,
-                                             double& dE) {
+template <typename Pr>
+__device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const Tabs<Pr>& tb, const Zone& Z, const Adj& A,
+                                             const double* s_d, double* s_u, bool swap, typename Pr::R* lq, int t,
+                                             double& dT, double& dE) {
   const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
   double* o = s_u + 4 * t;
   double v[4], vu[4], w[4], up[4];
@@ -1399,7 +1500,7 @@ __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, con
   o[1] = up[1];
   o[2] = up[2];
   o[3] = up[3];
-  const Q4 q = task_backward<R, false>(P, tab, Z, t, Q4{w[0], w[1], w[2], w[3]}, lq, dT, dE);
+  const Q4 q = task_backward<Pr, false>(P, tb, Z, t, Q4{w[0], w[1], w[2], w[3]}, lq, dT, dE);
   // completion: Phi_out(j, i) = exp(-(eps_i - eps_j)/T) q, d/dT = (eps_i - eps_j)/T^2 times it
   dT += (q.a * o[0] + q.b * o[1] + q.c * o[2] + q.d * o[3]) * (P.eps[i] - P.eps[j]) * (Z.invT * Z.invT);
   o[0] = q.a;
@@ -1410,9 +1511,10 @@ __device__ __forceinline__ void nes_task_bwd(const DevPlan& P, const R* tab, con
 
 // Pair task t (i >= j) in the backward, covering Phi_a(i, j) and Phi_a(j, i) (once on the
 // diagonal); the production factor's weights wait in the two tasks' LDS slots.
-template <typename R>
-__device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, const Zone& Z, const Adj& A,
-                                              const double* s_p, double* s_pa, R* lq, int t, double& dT, double& dE) {
+template <typename Pr>
+__device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const Tabs<Pr>& tb, const Zone& Z, const Adj& A,
+                                              const double* s_p, double* s_pa, typename Pr::R* lq, int t, double& dT,
+                                              double& dE) {
   const int ne = P.ne, ij = P.nes_ij[t], i = ij & 0xff, j = ij >> 8;
   const bool off = i != j;
   const double pf = s_p[i * ne + j];   // symmetric in (i, j)
@@ -1426,7 +1528,7 @@ __device__ __forceinline__ void pair_task_bwd(const DevPlan& P, const R* tab, co
     o2[0] = pc[2];
     o2[1] = pc[3];
   }
-  const Q4 q = task_backward<R, true>(P, tab, Z, t, Q4{w[0], w[1], off ? w[2] : 0.0, off ? w[3] : 0.0}, lq, dT, dE);
+  const Q4 q = task_backward<Pr, true>(P, tb, Z, t, Q4{w[0], w[1], off ? w[2] : 0.0, off ? w[3] : 0.0}, lq, dT, dE);
   // production factor p = exp(-(eps_i + eps_j)/T): d/dT = (eps_i + eps_j)/T^2 p
   const double pw = pf * (P.eps[i] + P.eps[j]) * (Z.invT * Z.invT);
   dT += (q.a * o1[0] + q.b * o1[1]) * pw;
@@ -1444,9 +1546,9 @@ constexpr int kMaxUnits = 32;
 
 // Backward of one zone; FUSED also contracts the recomputed task values with f into eta, chi
 // (forward and backward in one pass).
-template <typename R, bool NPS, bool FUSED>
-__device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* red, double* smem, int64_t z,
-                              int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
+template <typename Pr, bool NPS, bool FUSED>
+__device__ void zone_backward(const DevPlan& P, const Tabs<Pr>& tb, Zone* zs, double* red, double* smem, int64_t z,
+                              const double* __restrict__ Tz, const double* __restrict__ etaz,
                               const double* __restrict__ f, const double* __restrict__ g_eta,
                               const double* __restrict__ g_chi, double* __restrict__ gT_out,
                               double* __restrict__ gE_out, double* __restrict__ gf_out, double* __restrict__ eta_out,
@@ -1459,7 +1561,7 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
   // regions whatever the process mask) | detailed-balance factors [2 ne^2]
   const int off_ge = 6 * ne, off_gc = 12 * ne;
   const Lay L = layout<NPS>(P, 18 * ne);
-  stage_zone_state(P, z, selm, Tz, etaz, zs);
+  stage_zone_state(P, z, Tz, etaz, zs);
   __syncthreads();
   const Zone& Z = zs[0];
   if (!Z.valid) return;   // uniform: every lane reads the same zone state
@@ -1475,6 +1577,7 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
   const Units U = task_units(ntn, ntm, ntp);
   const int lane = threadIdx.x & 63;
   // per-lane slots after the contraction parts: 13 bulk-type values per lane, stride kBlock
+  using R = typename Pr::R;
   R* lq = reinterpret_cast<R*>(smem + L.d + 2 * n2 + 24 * ne) + threadIdx.x;
   // d/dT and d/deta_e: summed per unit in the unit's wave, then over units in unit order, so
   // the result does not depend on which wave ran which unit
@@ -1487,13 +1590,13 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
       const Zone& ZS = zs[mir ? 1 : 0];
       const int pos = ((mir ? u - U.nN : u) << 6) + lane;
       if (pos < (mir ? ntm : ntn))
-        nes_task_bwd<R>(P, tab, ZS, A, smem + L.d, smem + (mir ? L.m : L.q), mir, lq,
+        nes_task_bwd<Pr>(P, tb, ZS, A, smem + L.d, smem + (mir ? L.m : L.q), mir, lq,
                         P.task_order[ZS.k * P.ntn + pos], dT, dE);
       if (mir) dE = -dE;
     } else {
       const int pos = ((u - U.nN - U.nM) << 6) + lane;
       if (pos < ntp)
-        pair_task_bwd<R>(P, tab, Z, A, smem + L.d + n2, smem + L.p, lq, P.task_order[Z.k * P.ntn + pos], dT, dE);
+        pair_task_bwd<Pr>(P, tb, Z, A, smem + L.d + n2, smem + L.p, lq, P.task_order[Z.k * P.ntn + pos], dT, dE);
     }
     dT = wave_sum(dT);
     dE = wave_sum(dE);
@@ -1590,52 +1693,29 @@ __device__ void zone_backward(const DevPlan& P, const R* tab, Zone* zs, double* 
   }
 }
 
-// Occupancy targets: three waves per SIMD for the FP32 backward (at most 168 VGPRs), two
-// for the FP64 one.
-template <typename R, bool NPS, bool FUSED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
+// Occupancy targets (waves per SIMD): three for the Fp32 and Fd64 backward (at most 168
+// VGPRs), two for the Fp64 one.
+template <typename Pr>
+constexpr int bwd_waves() {
+  return sizeof(typename Pr::F) == 8 ? 2 : 3;
+}
+
+template <typename Pr, bool NPS, bool FUSED>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(bwd_waves<Pr>())))
 void rates_backward_kernel(
     DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
     const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
     double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out,
     double* __restrict__ eta_out, double* __restrict__ chi_out) {
-  __shared__ R tab[kTabLen];
+  __shared__ double tab[(tab_bytes<Pr>() + 7) / 8];
   __shared__ Zone zs[2];
   __shared__ double red[2 * kMaxUnits];
   extern __shared__ double smem[];
-  stage_tab<R>(P, tab);
   const int64_t z = blockIdx.x;
-  zone_backward<R, NPS, FUSED>(P, tab, zs, red, smem, z < nz ? z : -1, selm, Tz, etaz, f, g_eta, g_chi, gT_out,
-                               gE_out, gf_out, eta_out, chi_out);
-}
-
-template <bool NPS, bool FUSED>
-__global__ __launch_bounds__(kBlock) void rates_backward_sparse(
-    DevPlan P, int64_t nz, const double* __restrict__ Tz, const double* __restrict__ etaz,
-    const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
-    double* __restrict__ gT_out, double* __restrict__ gE_out, double* __restrict__ gf_out,
-    double* __restrict__ eta_out, double* __restrict__ chi_out) {
-  __shared__ double tab[kTabLen];
-  __shared__ Zone zs[2];
-  __shared__ double red[2 * kMaxUnits];
-  __shared__ int list[kBlock];
-  __shared__ int count;
-  extern __shared__ double smem[];
-  stage_tab<double>(P, tab);
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nz; base += (int64_t)gridDim.x * blockDim.x) {
-    if (threadIdx.x == 0) count = 0;
-    __syncthreads();
-    const int64_t z = base + threadIdx.x;
-    if (z < nz && fabs(etaz[z]) > P.eta_fp64) list[atomicAdd(&count, 1)] = (int)threadIdx.x;
-    __syncthreads();
-    const int n = count;
-    for (int c = 0; c < n; ++c) {
-      zone_backward<double, NPS, FUSED>(P, tab, zs, red, smem, base + list[c], kSelAll, Tz, etaz, f, g_eta, g_chi,
-                                        gT_out, gE_out, gf_out, eta_out, chi_out);
-      __syncthreads();
-    }
-    __syncthreads();   // every lane has read count before the next window resets it
-  }
+  if (z >= nz || !selected(P, selm, etaz[z])) return;   // uniform: one zone per workgroup
+  const Tabs<Pr> tb = stage_tabs<Pr>(P, tab);
+  zone_backward<Pr, NPS, FUSED>(P, tb, zs, red, smem, z, Tz, etaz, f, g_eta, g_chi, gT_out, gE_out, gf_out, eta_out,
+                                chi_out);
 }
 
 // Per-zone LDS: the layouts above plus the contraction parts (at most 4 x ne x 3 x 4 doubles
@@ -1663,45 +1743,37 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-// Workgroups of the sparse FP64 pass: enough to scan every zone in a few windows.
-unsigned sparse_grid(int64_t nz) {
-  const int64_t windows = (nz + kBlock - 1) / kBlock;
-  return (unsigned)(windows < 1024 ? windows : 1024);
-}
-
 // Zones per launch: one workgroup per zone, and a dispatch holds fewer than 2^32 work-items.
 // Larger calls are issued as consecutive slices on the same stream.
 constexpr int64_t kSliceZones = int64_t(1) << 22;
 
+template <typename Pr, bool NPS>
+hipError_t forward_pass(const DevPlan& P, int64_t nz, int selm, const double* T, const double* eta_e,
+                        const double* f, double* eta, double* chi, double* jac, int out, hipStream_t s) {
+  auto k = out == kOutJac     ? rates_forward_kernel<Pr, kOutJac, NPS>
+           : out == kOutTasks ? rates_forward_kernel<Pr, kOutTasks, NPS>
+           : out == kOutTable ? rates_forward_kernel<Pr, kOutTable, NPS>
+                              : rates_forward_kernel<Pr, kOutRates, NPS>;
+  const size_t lds = zone_lds_fwd(P);
+  hipError_t e;
+  if ((e = allow_lds(k, lds)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3((unsigned)nz), dim3(kBlock), lds, s, P, nz, selm, T, eta_e, f, eta, chi, jac);
+  return hipGetLastError();
+}
+
+// The mixed path runs three dense passes over the zones, one per class (see selected()); each
+// workgroup of a pass leaves at once when its zone belongs to another. The FP64 path is one
+// pass.
 template <bool NPS>
 hipError_t forward_slice_t(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
                            double* eta, double* chi, double* jac, int out, hipStream_t s) {
-  const size_t lds = zone_lds_fwd(P);
-  const dim3 grid((unsigned)nz), block(kBlock);
-  hipError_t e;
   if (P.precision == VTX_MIXED) {
-    auto bulk = out == kOutJac     ? rates_forward_kernel<float, kOutJac, NPS>
-                : out == kOutTasks ? rates_forward_kernel<float, kOutTasks, NPS>
-                : out == kOutTable ? rates_forward_kernel<float, kOutTable, NPS>
-                                   : rates_forward_kernel<float, kOutRates, NPS>;
-    auto sparse = out == kOutJac     ? rates_forward_sparse<kOutJac, NPS>
-                  : out == kOutTasks ? rates_forward_sparse<kOutTasks, NPS>
-                  : out == kOutTable ? rates_forward_sparse<kOutTable, NPS>
-                                     : rates_forward_sparse<kOutRates, NPS>;
-    if ((e = allow_lds(bulk, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(bulk, grid, block, lds, s, P, nz, kSelBulk, T, eta_e, f, eta, chi, jac);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = allow_lds(sparse, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(sparse, dim3(sparse_grid(nz)), block, lds, s, P, nz, T, eta_e, f, eta, chi, jac);
-  } else {
-    auto dense = out == kOutJac     ? rates_forward_kernel<double, kOutJac, NPS>
-                 : out == kOutTasks ? rates_forward_kernel<double, kOutTasks, NPS>
-                 : out == kOutTable ? rates_forward_kernel<double, kOutTable, NPS>
-                                    : rates_forward_kernel<double, kOutRates, NPS>;
-    if ((e = allow_lds(dense, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(dense, grid, block, lds, s, P, nz, kSelAll, T, eta_e, f, eta, chi, jac);
+    hipError_t e = forward_pass<Fp32, NPS>(P, nz, kSelBulk, T, eta_e, f, eta, chi, jac, out, s);
+    if (e == hipSuccess) e = forward_pass<Fd64, NPS>(P, nz, kSelFd, T, eta_e, f, eta, chi, jac, out, s);
+    if (e == hipSuccess) e = forward_pass<Fp64, NPS>(P, nz, kSelHigh, T, eta_e, f, eta, chi, jac, out, s);
+    return e;
   }
-  return hipGetLastError();
+  return forward_pass<Fp64, NPS>(P, nz, kSelAll, T, eta_e, f, eta, chi, jac, out, s);
 }
 
 hipError_t forward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
@@ -1722,30 +1794,33 @@ hipError_t interp_slice_t(const DevPlan& P, const vtx_lattice& lat, const double
   return hipGetLastError();
 }
 
+template <typename Pr, bool NPS, bool FUSED>
+hipError_t backward_pass(const DevPlan& P, int64_t nz, int selm, const double* T, const double* eta_e,
+                         const double* f, const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e,
+                         double* g_f, double* eta, double* chi, hipStream_t s) {
+  auto k = rates_backward_kernel<Pr, NPS, FUSED>;
+  const size_t lds = zone_lds_bwd(P, sizeof(typename Pr::R), FUSED);
+  hipError_t e;
+  if ((e = allow_lds(k, lds)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3((unsigned)nz), dim3(kBlock), lds, s, P, nz, selm, T, eta_e, f, g_eta, g_chi, g_T,
+                     g_eta_e, g_f, eta, chi);
+  return hipGetLastError();
+}
+
 template <bool NPS, bool FUSED>
 hipError_t backward_slice_t(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
                             const double* g_eta, const double* g_chi, double* g_T, double* g_eta_e, double* g_f,
                             double* eta, double* chi, hipStream_t s) {
-  const size_t lds32 = zone_lds_bwd(P, sizeof(float), FUSED), lds64 = zone_lds_bwd(P, sizeof(double), FUSED);
-  const dim3 grid((unsigned)nz), block(kBlock);
-  hipError_t e;
   if (P.precision == VTX_MIXED) {
-    auto bulk = rates_backward_kernel<float, NPS, FUSED>;
-    auto sparse = rates_backward_sparse<NPS, FUSED>;
-    if ((e = allow_lds(bulk, lds32)) != hipSuccess) return e;
-    hipLaunchKernelGGL(bulk, grid, block, lds32, s, P, nz, kSelBulk, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f,
-                       eta, chi);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = allow_lds(sparse, lds64)) != hipSuccess) return e;
-    hipLaunchKernelGGL(sparse, dim3(sparse_grid(nz)), block, lds64, s, P, nz, T, eta_e, f, g_eta, g_chi, g_T,
-                       g_eta_e, g_f, eta, chi);
-  } else {
-    auto dense = rates_backward_kernel<double, NPS, FUSED>;
-    if ((e = allow_lds(dense, lds64)) != hipSuccess) return e;
-    hipLaunchKernelGGL(dense, grid, block, lds64, s, P, nz, kSelAll, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f,
-                       eta, chi);
+    hipError_t e = backward_pass<Fp32, NPS, FUSED>(P, nz, kSelBulk, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f,
+                                                   eta, chi, s);
+    if (e == hipSuccess)
+      e = backward_pass<Fd64, NPS, FUSED>(P, nz, kSelFd, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s);
+    if (e == hipSuccess)
+      e = backward_pass<Fp64, NPS, FUSED>(P, nz, kSelHigh, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s);
+    return e;
   }
-  return hipGetLastError();
+  return backward_pass<Fp64, NPS, FUSED>(P, nz, kSelAll, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s);
 }
 
 hipError_t backward_slice(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,

@@ -33,8 +33,8 @@ def _fma(a, b, c):
 
 
 def exp2(x, c):
-    """The kernel's evaluation order, with exact fma."""
-    x = min(max(x, -2100.0), 2100.0)
+    """The kernel's evaluation order, with exact fma (the kernel's callers cap x at 1000)."""
+    x = max(x, -2100.0)
     n = float(round(x))   # round half to even, as rint
     t = (x - n) * LN2
     p = c[-1]

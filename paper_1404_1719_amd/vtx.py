@@ -131,7 +131,7 @@ class GridHandle:
 
 
 def make_opts(precision="fp64", nquad=48, rule="panel", processes=VTX_NES | VTX_PAIR, sin2w=0.2312,
-              eta_fp64=64.0):
+              eta_fp64=30.0):
     o = Opts()
     library().vtx_opts_default(ctypes.byref(o))
     o.precision = {"fp64": VTX_FP64, "mixed": VTX_MIXED}[precision] if isinstance(precision, str) else precision

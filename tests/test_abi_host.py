@@ -40,7 +40,7 @@ def test_default_options():
     o = vtx.Opts()
     lib.vtx_opts_default(ctypes.byref(o))
     assert (o.precision, o.nquad, o.rule, o.processes) == (0, 48, 1, 3)
-    assert o.sin2w == 0.2312 and o.eta_fp64 == 64.0
+    assert o.sin2w == 0.2312 and o.eta_fp64 == 30.0
 
 
 def _call_fwd(grid, opts, nz, ptr=1):

@@ -321,32 +321,38 @@ def test_backward_largest_grid():
     assert max(grad_err(gT, rT).max(), grad_err(gE, rE).max(), grad_err(gf, rf).max()) <= FP64_TOL
 
 
-def test_mixed_fp64_pass():
-    """Mixed precision sends zones with |eta_e| above the threshold to a second, FP64 pass:
-    those zones match the FP64 path bit for bit (forward and backward), the rest stay within
-    the mixed bars."""
-    inp = synth.make_inputs("medium", nzones=24)
-    inp.eta_e[:6] = [-30.0, -12.0, 25.0, 39.0, 16.0, -16.0]
-    thr = 15.0
-    big = np.abs(inp.eta_e) > thr
-    assert big.sum() >= 6 and (~big).sum() >= 6
-    say(f"[gpu] mixed with FP64 pass: {int(big.sum())} of {big.size} zones above |eta_e| = {thr}")
-    e64, c64 = gpu_forward(inp, "fp64", 48, "panel")
-    em, cm = gpu_forward(inp, "mixed", 48, "panel", eta_fp64=thr)
-    assert np.array_equal(em[big], e64[big]) and np.array_equal(cm[big], c64[big])
-    re, rc, ae, ac = oracle_forward(inp, 48, "panel")
-    small = ~big
-    err = max(rel_err(em[small], re[small], ae[small]).max(), rel_err(cm[small], rc[small], ac[small]).max())
-    say(f"    FP32-pass zones: max rel err {err:.2e}")
-    assert err <= MIXED_TOL
+def test_mixed_zone_classes():
+    """The mixed path splits zones by |eta_e|: FP32 throughout up to the threshold, FP64
+    Fermi-Dirac factors above it, and entirely FP64 above 64. Zones of the last class match the
+    FP64 path bit for bit (forward and backward); the other two stay within the mixed bars of
+    the oracle. A lower threshold moves zones between the first two classes only."""
+    inp = synth.make_inputs("medium", nzones=30)
+    inp.eta_e[:12] = [-70.0, -45.0, -31.0, 12.0, 25.0, 31.0, 39.0, 55.0, 63.5, 64.5, 90.0, -16.0]
+    inp.T[:12] = [0.6, 1.5, 0.8, 3.0, 0.5, 2.0, 1.0, 0.7, 5.0, 0.9, 4.0, 0.55]
     ge, gc = synth.random_gradients(inp.T.shape[0], inp.eps.shape[0], 8)
+    re, rc, ae, ac = oracle_forward(inp, 48, "panel")
+    rT, rE, rf = ograd.vjp(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, ge, gc, orates.Options(nquad=48, rule="panel"))
+    e64, c64 = gpu_forward(inp, "fp64", 48, "panel")
     g64 = gpu_backward(inp, ge, gc, "fp64", 48, "panel")
-    gm = gpu_backward(inp, ge, gc, "mixed", 48, "panel", eta_fp64=thr)
-    for a, b in zip(gm, g64):
-        assert np.array_equal(a[big], b[big])
-        gerr = grad_err(a[small], b[small]).max()
-        say(f"    FP32-pass zones, gradients against the FP64 path: {gerr:.2e}")
-        assert gerr <= MIXED_TOL
+    for thr in (30.0, 15.0):
+        a = np.abs(inp.eta_e)
+        high = a > 64.0
+        fd = (a > thr) & ~high
+        bulk = ~(a > thr)
+        assert high.sum() >= 2 and fd.sum() >= 5 and bulk.sum() >= 5
+        say(f"[gpu] mixed classes at threshold {thr}: {int(bulk.sum())} FP32, {int(fd.sum())} FP64 Fermi-Dirac, "
+            f"{int(high.sum())} FP64")
+        em, cm = gpu_forward(inp, "mixed", 48, "panel", eta_fp64=thr)
+        assert np.array_equal(em[high], e64[high]) and np.array_equal(cm[high], c64[high])
+        gm = gpu_backward(inp, ge, gc, "mixed", 48, "panel", eta_fp64=thr)
+        for got, ref in zip(gm, g64):
+            assert np.array_equal(got[high], ref[high])
+        for name, sel in (("FP32", bulk), ("FP64 Fermi-Dirac", fd)):
+            err = max(rel_err(em[sel], re[sel], ae[sel]).max(), rel_err(cm[sel], rc[sel], ac[sel]).max())
+            gerr = max(grad_err(gm[0][sel], rT[sel]).max(), grad_err(gm[1][sel], rE[sel]).max(),
+                       grad_err(gm[2][sel], rf[sel]).max())
+            say(f"    {name} zones: forward {err:.2e}, backward {gerr:.2e}")
+            assert err <= MIXED_TOL and gerr <= MIXED_TOL
 
 
 def test_backward_batch_independent():
