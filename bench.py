@@ -1,17 +1,21 @@
 """Benchmark: zone x (eps, eps') kernel evaluations per second, forward + backward.
 
 One step = forward (eta, chi) + backward (g_T, g_eta_e, g_f) over every zone of the
-workload, inputs resident in HBM, in chunks issued back to back on one compute stream.
-Default workload: 4096 rays x 600 zones, NE = 21, 64-node rule, mixed precision, 8 chunks.
-Prints ONE JSON line (rank 0). Units: zones * NE^2 per second (each unit covers 3 species,
-both processes, l = 0, 1, one forward and one backward evaluation).
+workload, inputs resident in HBM, in 8 chunks issued back to back on one compute stream.
+Default workload: 4096 rays x 600 zones, NE = 21, 64-node rule, mixed precision with FP64
+Fermi-Dirac factors for |eta_e| > 30. Prints ONE JSON line. Units: zones * NE^2 per second
+(each unit covers 3 species, both processes, l = 0, 1, one forward and one backward
+evaluation).
 
-Also reported: the same step in plain FP64 (speedup of mixed over FP64), the maximal
-relative error per output against the FP64 oracle on sampled zones, a roofline entry for
-the dominant kernel (algorithmic FLOPs per launch / measured launch time), the oracle
-timed on the host cores on a bounded sample, the same step with the workload held in
-pinned host memory and streamed through the GPU chunk by chunk (PCIe transfers included),
-and the explicit Jacobian blocks timed over one chunk.
+Also reported: the same step in plain FP64 (speedup of mixed over FP64, and its own roofline
+entry); the maximal relative error per output against stored FP64 oracle outputs
+(tests/golden/ref_<workload>.npz, written by a script that calls only the oracle) on 4,096
+stratified zones forward and 512 backward, with the stratum eta_e > 30, T < 2 MeV on its own;
+a roofline entry for the dominant launch; the oracle timed on the host cores on a bounded
+sample; the whole step end to end with the workload in pinned host memory, streamed through
+the GPU in 8 chunks (package stream.Streamer, PCIe transfers included); the mixed path with
+the FP64 Fermi-Dirac threshold at 64 instead of 30; the explicit Jacobian blocks over one
+chunk; the tabulated comparison; all three processes; the fused forward + backward call.
 """
 import argparse
 import hashlib
@@ -114,57 +118,75 @@ def _oracle_chunk(arg):
     return len(idx)
 
 
-def sampled_errors(inp, run, wl, count=6):
-    """Max relative error per output on sampled zones vs the FP64 oracle (same rule): the
-    forward's four outputs, and the backward's g_T, g_eta_e, g_f against the oracle's
-    reverse-mode products for the run's own upstream gradients (floor: 1e-3 x the mean
-    magnitude of the field, as g_f = K^T g sums terms of both signs)."""
+def load_reference(name):
+    """Stored FP64 oracle outputs of a workload's zone sample, or None (tests/golden)."""
+    path = os.path.join(ROOT, "tests", "golden", f"ref_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def stored_errors(inp, run, ref, stratum=None):
+    """Max relative error per output against the stored oracle outputs: forward on the
+    reference's zone sample, |y - y_ref| / max(|y_ref|, 1e-3 A, 1e-290) with A the sum of |terms|;
+    backward on its sub-sample for the run's pooled upstream gradients, floor 1e-3 x the mean
+    magnitude of the field (g_f = K^T g sums terms of both signs). stratum(T, eta_e) selects
+    zones reported again on their own."""
     import torch
-    from oracle import grad as ograd
-    from oracle import rates as orates
-    idx = synth.sample_zones(inp, count, seed=11)
-    it = torch.from_numpy(idx).to(run.eta.device)
+    idx, idx_b = ref["idx"], ref["idx_b"]
 
-    def pick(t):
-        return t.index_select(0, it).cpu().numpy()
+    def pick(t, ix):
+        return t.index_select(0, torch.from_numpy(ix).to(t.device)).cpu().numpy()
 
-    e, c, ge, gc = pick(run.eta), pick(run.chi), pick(run.g_eta), pick(run.g_chi)
-    gT, gE, gf = pick(run.gT), pick(run.gE), pick(run.gf)
-    sub = synth.subset(inp, idx)
-    opts = orates.Options(nquad=wl.nquad, rule=wl.rule)
-    re, rc, ae, ac = orates.forward_with_scale(sub.eps, sub.w, sub.T, sub.eta_e, sub.f, opts)
-    rT, rE, rf = ograd.vjp(sub.eps, sub.w, sub.T, sub.eta_e, sub.f, ge, gc, opts)
-
-    def err(y, r, a):
-        return float(np.max(np.abs(y - r) / np.maximum(np.maximum(np.abs(r), 1e-3 * a), 1e-290)))
+    def ferr(y, r, a):
+        return np.abs(y - r) / np.maximum(np.maximum(np.abs(r), 1e-3 * a.astype(np.float64)), 1e-290)
 
     def gerr(g, r):
-        return float(np.max(np.abs(g - r) / np.maximum(np.abs(r), 1e-3 * np.mean(np.abs(r)) + 1e-300)))
+        return np.abs(g - r) / np.maximum(np.abs(r), 1e-3 * np.mean(np.abs(r)) + 1e-300)
 
-    return {"eta0": err(e[:, :, 0], re[:, :, 0], ae[:, :, 0]), "eta1": err(e[:, :, 1], re[:, :, 1], ae[:, :, 1]),
-            "chi0": err(c[:, :, 0], rc[:, :, 0], ac[:, :, 0]), "chi1": err(c[:, :, 1], rc[:, :, 1], ac[:, :, 1]),
-            "g_T": gerr(gT, rT), "g_eta_e": gerr(gE, rE), "g_f": gerr(gf, rf), "zones": len(idx)}
+    e, c = pick(run.eta, idx), pick(run.chi, idx)
+    f = {"eta0": ferr(e[:, :, 0], ref["eta"][:, :, 0], ref["a_eta"][:, :, 0]),
+         "eta1": ferr(e[:, :, 1], ref["eta"][:, :, 1], ref["a_eta"][:, :, 1]),
+         "chi0": ferr(c[:, :, 0], ref["chi"][:, :, 0], ref["a_chi"][:, :, 0]),
+         "chi1": ferr(c[:, :, 1], ref["chi"][:, :, 1], ref["a_chi"][:, :, 1])}
+    g = {k: gerr(pick(t, idx_b), ref[k]) for k, t in (("g_T", run.gT), ("g_eta_e", run.gE), ("g_f", run.gf))}
+    out = {k: float(v.max()) for k, v in {**f, **g}.items()}
+    out["zones_forward"], out["zones_backward"] = int(idx.size), int(idx_b.size)
+    if stratum is not None:
+        sf, sb = stratum(inp.T[idx], inp.eta_e[idx]), stratum(inp.T[idx_b], inp.eta_e[idx_b])
+        out["stratum"] = {**{k: float(v[sf].max(initial=0.0)) for k, v in f.items()},
+                          **{k: float(v[sb].max(initial=0.0)) for k, v in g.items()},
+                          "zones_forward": int(sf.sum()), "zones_backward": int(sb.sum())}
+    return out
+
+
+def corner(T, eta_e):
+    """The stratum of high degeneracy at low temperature: eta_e > 30, T < 2 MeV."""
+    return (eta_e > 30.0) & (T < 2.0)
 
 
 class Runner:
     """Device-resident buffers of one workload and the chunked two-stream step."""
 
-    def __init__(self, inp, wl, precision, chunks, processes=3):
+    def __init__(self, inp, wl, precision, chunks, processes=3, eta_fp64=30.0, grad_seed=7):
         import torch
         from paper_1404_1719_amd import vtx
         self.torch, self.vtx = torch, vtx
         dev = torch.device("cuda:0")
         self.grid = vtx.GridHandle(inp.eps, inp.w)
-        self.opts = vtx.make_opts(precision, wl.nquad, wl.rule, processes)
+        self.opts = vtx.make_opts(precision, wl.nquad, wl.rule, processes, eta_fp64=eta_fp64)
         self.nz, self.ne = inp.T.shape[0], wl.ne
         self.T = torch.from_numpy(inp.T).to(dev)
         self.E = torch.from_numpy(inp.eta_e).to(dev)
         self.f = torch.from_numpy(inp.f).to(dev)
         shp = (self.nz, 3, 2, self.ne)
-        g = torch.Generator(device=dev)
-        g.manual_seed(synth.SEED_BASE + 3000)
-        self.g_eta = torch.randn(shp, dtype=torch.float64, device=dev, generator=g)
-        self.g_chi = torch.randn(shp, dtype=torch.float64, device=dev, generator=g)
+        # upstream gradients: zone z takes row z mod 4099 of a seeded pool (synth.pooled_gradients),
+        # the rows the stored oracle reference used
+        pe, pc = (torch.from_numpy(a).to(dev) for a in synth.gradient_pool(self.ne, grad_seed))
+        rows = torch.arange(self.nz, device=dev) % pe.shape[0]
+        self.g_eta, self.g_chi = pe.index_select(0, rows), pc.index_select(0, rows)
+        del pe, pc, rows
         self.eta = torch.empty(shp, dtype=torch.float64, device=dev)
         self.chi = torch.empty(shp, dtype=torch.float64, device=dev)
         self.gT = torch.empty((self.nz,), dtype=torch.float64, device=dev)
@@ -247,133 +269,33 @@ class Runner:
         return float(np.mean(fwd)), float(np.mean(bwd)), float(np.mean(zones))
 
 
-def hip_runtime():
-    """ctypes handle of the HIP runtime this process already uses (torch's), never a second copy."""
-    import ctypes
-    with open("/proc/self/maps") as fh:
-        paths = sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln and ln.split()[-1].startswith("/")})
-    if not paths:
-        raise RuntimeError("HIP runtime not loaded")
-    return ctypes.CDLL(paths[0])
-
-
-class Streamer:
-    """The workload held in pinned host memory and streamed through the GPU chunk by chunk.
-    Inputs go host-to-device on a copy stream (DMA engines) into one of two device buffer
-    sets. The forward and the backward of a chunk read the same inputs and nothing of each
-    other (the backward recomputes the kernels), so they run on two compute streams at once,
-    and both write their outputs directly into the pinned host arrays through the arrays'
-    device mapping (hipHostGetDevicePointer): no device-to-host copy kernels compete with the
-    rate kernels for compute units, and the forward's output writes spread over the whole
-    chunk. Three streams, default priority, one hardware queue each (the null stream holds
-    the fourth)."""
-
-    IN = ("T", "E", "f", "g_eta", "g_chi")
-    OUT = ("eta", "chi", "gT", "gE", "gf")
-
-    def __init__(self, run):
-        import ctypes
-        torch = run.torch
-        self.torch, self.vtx, self.run = torch, run.vtx, run
-        src = {"T": run.T, "E": run.E, "f": run.f, "g_eta": run.g_eta, "g_chi": run.g_chi,
-               "eta": run.eta, "chi": run.chi, "gT": run.gT, "gE": run.gE, "gf": run.gf}
-        total = sum(t.numel() for t in src.values())
-        self.pool = torch.empty(total, dtype=torch.float64, pin_memory=True)   # one pinned allocation
-        self.host, off = {}, 0
-        for k, t in src.items():
-            self.host[k] = self.pool[off:off + t.numel()].view(t.shape)
-            off += t.numel()
-        for k in self.IN:
-            self.host[k].copy_(src[k])
-        dptr = ctypes.c_void_p()
-        rc = hip_runtime().hipHostGetDevicePointer(ctypes.byref(dptr), ctypes.c_void_p(self.pool.data_ptr()), 0)
-        if rc != 0 or not dptr.value:
-            raise RuntimeError(f"hipHostGetDevicePointer failed ({rc})")
-        self.mapped = dptr.value
-        self.bytes_in = sum(self.host[k].numel() for k in self.IN) * 8
-        self.bytes_out = sum(self.host[k].numel() for k in self.OUT) * 8
-        n = max(b - a for a, b in run.chunks)
-        dev = run.T.device
-        self.slots = []
-        for _ in range(2):
-            d = {k: torch.empty((n,) + tuple(src[k].shape[1:]), dtype=torch.float64, device=dev) for k in self.IN}
-            d["fwd_done"] = torch.cuda.Event()
-            d["bwd_done"] = torch.cuda.Event()
-            d["used"] = False
-            self.slots.append(d)
-        self.cf = run.streams[0]
-        self.cb = torch.cuda.Stream(device=dev)
-        self.h2d = torch.cuda.Stream(device=dev)
-
-    def out_ptr(self, t):
-        """Device address of a slice of the pinned host pool."""
-        import ctypes
-        return ctypes.c_void_p(self.mapped + (t.data_ptr() - self.pool.data_ptr()))
-
-    def step(self):
-        import ctypes
-        torch, run, H = self.torch, self.run, self.host
-        lib = self.vtx.library()
-        cur = torch.cuda.current_stream()
-        for st in (self.h2d, self.cf, self.cb):
-            st.wait_stream(cur)
-        sf, sb = ctypes.c_void_p(self.cf.cuda_stream), ctypes.c_void_p(self.cb.cuda_stream)
-        g, o = ctypes.byref(run.grid.c), ctypes.byref(run.opts)
-        for c, (a, b) in enumerate(run.chunks):
-            d = self.slots[c % 2]
-            n = b - a
-            ready = torch.cuda.Event()
-            with torch.cuda.stream(self.h2d):
-                if d["used"]:
-                    self.h2d.wait_event(d["fwd_done"])
-                    self.h2d.wait_event(d["bwd_done"])
-                for k in self.IN:
-                    d[k][:n].copy_(H[k][a:b], non_blocking=True)
-                ready.record(self.h2d)
-            self.cf.wait_event(ready)
-            self.cb.wait_event(ready)
-            p = {k: ctypes.c_void_p(d[k].data_ptr()) for k in self.IN}
-            rc = lib.vtx_rates_forward(g, o, n, p["T"], p["E"], p["f"], self.out_ptr(H["eta"][a:b]),
-                                       self.out_ptr(H["chi"][a:b]), sf)
-            rc = rc or lib.vtx_rates_backward(g, o, n, p["T"], p["E"], p["f"], p["g_eta"], p["g_chi"],
-                                              self.out_ptr(H["gT"][a:b]), self.out_ptr(H["gE"][a:b]),
-                                              self.out_ptr(H["gf"][a:b]), sb)
-            if rc:
-                raise RuntimeError(f"rates call failed ({rc})")
-            d["fwd_done"].record(self.cf)
-            d["bwd_done"].record(self.cb)
-            d["used"] = True
-        cur.wait_stream(self.cf)
-        cur.wait_stream(self.cb)
-
-    def timed(self, steps, warmup):
-        torch = self.torch
-        for _ in range(warmup):
-            self.step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            self.step()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / max(steps, 1)
-
-
-def streaming_leg(run, units, steps, warmup):
-    """Whole-job rate with the workload in pinned host memory (PCIe transfers included)."""
+def streaming_leg(inp, run, units, steps, warmup):
+    """Whole step end to end with the workload in pinned host memory, streamed through the GPU
+    in the workload's chunks by the package's stream.Streamer (PCIe transfers included): its
+    outputs are compared with the resident run's, bit for bit."""
     torch = run.torch
-    st = Streamer(run)
-    t = st.timed(steps, warmup)
-    same = bool(torch.equal(st.host["gT"].to(run.gT.device), run.gT) and
-                torch.equal(st.host["gf"].to(run.gf.device), run.gf) and
-                torch.equal(st.host["eta"].to(run.eta.device), run.eta) and
-                torch.equal(st.host["chi"].to(run.chi.device), run.chi))
+    from paper_1404_1719_amd import stream
+    st = stream.Streamer(run.grid, run.opts, run.nz, chunks=len(run.chunks))
+    for k, t in (("T", run.T), ("eta_e", run.E), ("f", run.f), ("g_eta", run.g_eta), ("g_chi", run.g_chi)):
+        st.host[k].copy_(t)
+    for _ in range(warmup):
+        st.step()
+    st.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.step()
+    st.synchronize()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / max(steps, 1)
+    same = all(bool(torch.equal(st.host[k], x.cpu())) for k, x in
+               (("eta", run.eta), ("chi", run.chi), ("g_T", run.gT), ("g_eta_e", run.gE), ("g_f", run.gf)))
     out = {"value": units / t, "unit": "zone*(eps,eps')/s", "ms_per_step": t * 1e3, "steps": steps,
-           "bytes_h2d": st.bytes_in, "bytes_to_host": st.bytes_out,
-           "pcie_GBps": (st.bytes_in + st.bytes_out) / t / 1e9,
-           "outputs_equal_resident_run": same,
-           "note": "pinned host arrays; inputs by DMA copies into 2 device buffer sets; forward and "
-                   "backward of a chunk on two compute streams at once; outputs written by the kernels "
-                   "into the mapped host arrays"}
+           "chunks": len(st.chunks), "bytes_h2d": st.bytes_h2d, "bytes_to_host": st.bytes_d2h,
+           "pcie_GBps": (st.bytes_h2d + st.bytes_d2h) / t / 1e9, "outputs_equal_resident_run": same,
+           "note": "paper_1404_1719_amd.stream.Streamer: pinned host arrays; inputs by DMA copies into 2 device "
+                   "buffer sets; forward and backward of a chunk on two compute streams at once; outputs "
+                   "written by the kernels into the mapped host arrays"}
     del st
     torch.cuda.empty_cache()
     return out
@@ -413,13 +335,13 @@ def jacobian_leg(inp, wl, precision, launches):
             "hbm_frac": written / (t * 1e-3) / 8e12, "traffic": traffic_from_profiles(tag), "kernel": tag}
 
 
-def tabulated_leg(inp, wl, precision, launches, t_direct_ms):
+def tabulated_leg(inp, wl, precision, launches, t_direct_ms, ref):
     """Tabulated comparison point: task values on a (ln T, eta_e) lattice over the workload's
     range (built by the library), interpolated per zone over one chunk, against the direct
-    forward. Errors: against the FP64 oracle's direct rates on sampled zones, with the A10
-    floor of the direct path; and over every zone of the chunk for the l = 0 outputs (which do
-    not cancel), against the library's direct forward, |y_tab - y| / max(|y|, 1e-3 max over the
-    bins of the same output)."""
+    forward. Errors: against the stored FP64 oracle outputs on the reference zones inside the
+    chunk, with the floor of the direct path; and over every zone of the chunk for the l = 0
+    outputs (which do not cancel), against the library's direct forward,
+    |y_tab - y| / max(|y|, 1e-3 max over the bins of the same output)."""
     import math
     import torch
     from paper_1404_1719_amd import vtx
@@ -461,20 +383,22 @@ def tabulated_leg(inp, wl, precision, launches, t_direct_ms):
         d = (y - r).abs() / torch.maximum(r.abs(), 1e-3 * r.abs().amax(dim=-1, keepdim=True))
         return {"max": d.max().item(), "median": d.median().item()}
 
-    from oracle import rates as orates
-    sub_idx = synth.sample_zones(synth.subset(inp, np.arange(nz)), 6, seed=12)
-    it = torch.from_numpy(sub_idx).to(dev)
-    te, tc = eta.index_select(0, it).cpu().numpy(), chi.index_select(0, it).cpu().numpy()
-    sub = synth.subset(inp, sub_idx)
-    re, rc, ae, ac = orates.forward_with_scale(sub.eps, sub.w, sub.T, sub.eta_e, sub.f,
-                                               orates.Options(nquad=wl.nquad, rule=wl.rule))
+    sampled = None
+    if ref is not None:
+        keep = ref["idx"] < nz
+        sub_idx = ref["idx"][keep]
+        it = torch.from_numpy(sub_idx).to(dev)
+        te, tc = eta.index_select(0, it).cpu().numpy(), chi.index_select(0, it).cpu().numpy()
+        re, rc = ref["eta"][keep], ref["chi"][keep]
+        ae, ac = ref["a_eta"][keep].astype(np.float64), ref["a_chi"][keep].astype(np.float64)
 
-    def a10(y, r, a):
-        return float(np.max(np.abs(y - r) / np.maximum(np.maximum(np.abs(r), 1e-3 * a), 1e-290)))
+        def a10(y, r, a):
+            return float(np.max(np.abs(y - r) / np.maximum(np.maximum(np.abs(r), 1e-3 * a), 1e-290)))
 
-    sampled = {"eta0": a10(te[:, :, 0], re[:, :, 0], ae[:, :, 0]), "eta1": a10(te[:, :, 1], re[:, :, 1], ae[:, :, 1]),
-               "chi0": a10(tc[:, :, 0], rc[:, :, 0], ac[:, :, 0]), "chi1": a10(tc[:, :, 1], rc[:, :, 1], ac[:, :, 1]),
-               "zones": len(sub_idx)}
+        sampled = {"eta0": a10(te[:, :, 0], re[:, :, 0], ae[:, :, 0]),
+                   "eta1": a10(te[:, :, 1], re[:, :, 1], ae[:, :, 1]),
+                   "chi0": a10(tc[:, :, 0], rc[:, :, 0], ac[:, :, 0]),
+                   "chi1": a10(tc[:, :, 1], rc[:, :, 1], ac[:, :, 1]), "zones": int(sub_idx.size)}
 
     nv = vtx.task_values(wl.ne, 3)
     out = {"lattice": f"{nt} x {nh} nodes, d ln T = {dlnT}, d eta_e = {deta}, over the workload's range",
@@ -489,6 +413,21 @@ def tabulated_leg(inp, wl, precision, launches, t_direct_ms):
     return out
 
 
+def roofline(wl, precision, t_fwd, t_bwd, zl):
+    """Roofline entry of the dominant launch (the backward call of a chunk): algorithmic FLOPs
+    per launch / its HIP-event duration. In the mixed path that call runs three kernels, one
+    per zone class (FP32; FP64 Fermi-Dirac factors; FP64 above |eta_e| = 64), and its duration
+    is their sum."""
+    dom_ms, dom_bwd = (t_bwd, True) if t_bwd >= t_fwd else (t_fwd, False)
+    flops = algorithmic_flops_per_zone(wl.ne, wl.nquad, dom_bwd) * zl
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    tag = f"rates_{'backward' if dom_bwd else 'forward'}_{precision}_{wl.name}"
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[precision], "traffic": traffic_from_profiles(tag),
+            "kernel": tag, "launch_ms": dom_ms, "zones_per_launch": zl,
+            "valu_issue": valu_issue_from_profiles(tag), "fwd_launch_ms": t_fwd, "bwd_launch_ms": t_bwd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -497,10 +436,14 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(synth.WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["mixed", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="steps of the FP64 comparison run (0: skip)")
+    ap.add_argument("--eta-fp64", type=float, default=30.0,
+                    help="mixed path: FP64 Fermi-Dirac factors for |eta_e| above this (default 30)")
+    ap.add_argument("--threshold64-steps", type=int, default=2,
+                    help="steps of the mixed run with the FP64 Fermi-Dirac threshold at 64 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--stream-steps", type=int, default=2,
-                    help="steps of the pinned-host streaming run, PCIe included (0: skip)")
+                    help="steps of the end-to-end run from pinned host memory, PCIe included (0: skip)")
     ap.add_argument("--fused-steps", type=int, default=2,
                     help="steps with forward and backward fused in one call per chunk (0: skip)")
     ap.add_argument("--tabulated-launches", type=int, default=3,
@@ -531,17 +474,18 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written", file=sys.stderr, flush=True)
         del src, dst
-    run = Runner(inp, wl, precision, wl.chunks)
+    ref = None if args.no_errors else load_reference(wl.name)
+    run = Runner(inp, wl, precision, wl.chunks, eta_fp64=args.eta_fp64)
     print(f"[bench] {precision}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     t_step = run.timed(args.steps, args.warmup)
     units = wl.nzones * wl.ne * wl.ne
     value = units / t_step
     t_fwd, t_bwd, zl = run.launch_times()
-    errors = None if args.no_errors else sampled_errors(inp, run, wl)
+    errors = None if ref is None else stored_errors(inp, run, ref, corner)
     streaming = None
     if args.stream_steps > 0:
-        print(f"[bench] streaming from pinned host memory: {args.stream_steps} steps", file=sys.stderr, flush=True)
-        streaming = streaming_leg(run, units, args.stream_steps, 1)
+        print(f"[bench] end to end from pinned host memory: {args.stream_steps} steps", file=sys.stderr, flush=True)
+        streaming = streaming_leg(inp, run, units, args.stream_steps, 1)
     # after the streaming leg: it compares its outputs with this run's separate-call ones
     fused = None
     if args.fused_steps > 0:
@@ -553,32 +497,37 @@ def main():
     del run
     torch.cuda.empty_cache()
 
-    # roofline of the dominant kernel (backward): algorithmic FLOPs per launch / launch time
-    dom_ms, dom_bwd = (t_bwd, True) if t_bwd >= t_fwd else (t_fwd, False)
-    flops = algorithmic_flops_per_zone(wl.ne, wl.nquad, dom_bwd) * zl
-    achieved = flops / (dom_ms * 1e-3) / 1e12
-    tag = f"rates_{'backward' if dom_bwd else 'forward'}_{precision}_{wl.name}"
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS[precision], "traffic": traffic_from_profiles(tag),
-            "kernel": tag, "launch_ms": dom_ms, "zones_per_launch": zl,
-            "valu_issue": valu_issue_from_profiles(tag),
-            "fwd_launch_ms": t_fwd, "bwd_launch_ms": t_bwd}
+    roof = roofline(wl, precision, t_fwd, t_bwd, zl)
 
     fp64 = None
     if precision == "mixed" and args.fp64_steps > 0:
         print(f"[bench] fp64 comparison: {args.fp64_steps} steps", file=sys.stderr, flush=True)
         run64 = Runner(inp, wl, "fp64", wl.chunks)
         t64 = run64.timed(args.fp64_steps, 1)
-        e64 = None if args.no_errors else sampled_errors(inp, run64, wl)
+        f64, b64, z64 = run64.launch_times()
+        e64 = None if ref is None else stored_errors(inp, run64, ref, corner)
         del run64
         torch.cuda.empty_cache()
         fp64 = {"value": units / t64, "ms_per_step": t64 * 1e3, "speedup_mixed_over_fp64": t64 / t_step,
-                "rel_err": e64}
+                "rel_err": e64, "roofline": roofline(wl, "fp64", f64, b64, z64)}
+
+    thr64 = None
+    if precision == "mixed" and args.threshold64_steps > 0:
+        print(f"[bench] mixed with the FP64 Fermi-Dirac threshold at 64: {args.threshold64_steps} steps",
+              file=sys.stderr, flush=True)
+        r64 = Runner(inp, wl, "mixed", wl.chunks, eta_fp64=64.0)
+        tt = r64.timed(args.threshold64_steps, 1)
+        et = None if ref is None else stored_errors(inp, r64, ref, lambda T, e: e > 30.0)
+        del r64
+        torch.cuda.empty_cache()
+        thr64 = {"value": units / tt, "ms_per_step": tt * 1e3, "rel_err": et,
+                 "note": "FP32 Fermi-Dirac factors up to |eta_e| = 64 (not the FP64 factors above 30 of the "
+                         "headline); 'stratum' is eta_e > 30, the zones whose factors change precision"}
 
     positron = None
     if args.positron_steps > 0:
         print(f"[bench] with neutrino-positron scattering: {args.positron_steps} steps", file=sys.stderr, flush=True)
-        runp = Runner(inp, wl, precision, wl.chunks, processes=7)
+        runp = Runner(inp, wl, precision, wl.chunks, processes=7, eta_fp64=args.eta_fp64)
         tp = runp.timed(args.positron_steps, 1)
         pf, pb, _ = runp.launch_times()
         positron = {"value": units / tp, "unit": "zone*(eps,eps')/s", "ms_per_step": tp * 1e3,
@@ -590,7 +539,7 @@ def main():
     tabulated = None
     if args.tabulated_launches > 0:
         print(f"[bench] tabulated kernels: {args.tabulated_launches} launches", file=sys.stderr, flush=True)
-        tabulated = tabulated_leg(inp, wl, precision, args.tabulated_launches, t_fwd)
+        tabulated = tabulated_leg(inp, wl, precision, args.tabulated_launches, t_fwd, ref)
 
     jac = None
     if args.jacobian_launches > 0:
@@ -602,6 +551,8 @@ def main():
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(wl)
 
+    mode = (f"FP32 with FP64 Fermi-Dirac factors for |eta_e| > {args.eta_fp64:g} (FP64 throughout above 64)"
+            if precision == "mixed" else "FP64")
     line = {
         "metric": "zone*(eps,eps') kernel evals/sec fwd+bwd", "value": value, "unit": "zone*(eps,eps')/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
@@ -609,10 +560,13 @@ def main():
         "dtype": "f32+f64" if precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.rays} rays x {wl.radial} zones, NE={wl.ne}, {wl.nquad}-node "
                                f"{wl.rule} rule, {precision}, fwd+bwd, {wl.chunks} chunks, inputs resident in HBM",
-                   "zones": wl.nzones, "ne": wl.ne, "nquad": wl.nquad, "precision": precision},
+                   "zones": wl.nzones, "ne": wl.ne, "nquad": wl.nquad, "precision": precision,
+                   "eta_fp64": args.eta_fp64 if precision == "mixed" else None, "arithmetic": mode,
+                   "streaming": "value: inputs resident in HBM; end_to_end_streamed: host memory, "
+                                f"{wl.chunks} stream-overlapped chunks, PCIe included"},
         "rel_err_vs_oracle": errors, "fp64": fp64, "roofline": roof, "cpu_baseline": cpu,
-        "streaming_pcie": streaming, "jacobian": jac, "with_positron_scattering": positron,
-        "fused_forward_backward": fused, "tabulated": tabulated,
+        "end_to_end_streamed": streaming, "threshold_64": thr64, "jacobian": jac,
+        "with_positron_scattering": positron, "fused_forward_backward": fused, "tabulated": tabulated,
     }
     print(json.dumps(line), flush=True)
 

@@ -207,11 +207,50 @@ int vtx_rates_forward_interp(const vtx_grid* grid, const vtx_opts* opts, const v
                              const double* eta_e, const double* f, double* eta, double* chi,
                              void* hip_stream);
 
+/*
+ * Newton step of an implicit radial sweep along rays. The paper's radial transport sweep is
+ * implicit and ray by ray, BDF2 in time, solved by Newton-Raphson with an explicitly built
+ * Jacobian and a direct solution of the linearised system (Sect. 2.1, radial sweep). These two
+ * calls give that step for a minimal stated system that consumes the rates (the transport
+ * terms proper are outside this library). Per ray, zones r = 0 .. nzr-1 (zones laid out ray by
+ * ray, nrays * nzr in all), unknowns F_r = f[r][3][2][ne] (nb = 6 ne values, in f's layout):
+ *   G_r = (3/2 F_r - 2 F_r^n + 1/2 F_r^{n-1}) / dt + (lo_r + up_r) F_r - lo_r F_{r-1} - up_r F_{r+1} - S_r
+ * (componentwise; F_{-1} = F_nzr = 0; lo, up >= 0 a three-point radial coupling of each
+ * component, e.g. upwind advection lo = v/dr, up = 0, or diffusion lo = up = D/dr^2), with the
+ * moment sources of the rates S0 = eta0 - chi0 f0 - 3 chi1 f1, S1 = eta1 - chi1 f0 - chi0 f1
+ * (per species and bin; time in units of length). The Jacobian is block tridiagonal:
+ * D_r = dG_r/dF_r = (3/(2 dt)) I + diag(lo_r + up_r) - dS_r/dF_r, dG_r/dF_{r-1} = -diag(lo_r),
+ * dG_r/dF_{r+1} = -diag(up_r); dS/dF comes from the rates' explicit blocks (vtx_rates_jacobian).
+ *
+ * vtx_ray_system: from jac [nz][3][2][4][ne][ne] (vtx_rates_jacobian), f, f_n, f_nm1, eta, chi
+ *   (eta, chi of the rates at f; all [nz][3][2][ne]) and lo, up [nz][nb], writes the diagonal
+ *   blocks D [nz][nb][nb] (row = (species, moment, bin) of G, column = that of F) and
+ *   rhs = -G [nz][nb]. dt > 0. All device memory; D and rhs are overwritten.
+ * vtx_ray_solve: solves -diag(lo_r) x_{r-1} + D_r x_r - diag(up_r) x_{r+1} = rhs_r along each ray
+ *   (any nb x nb blocks, 1 <= nb <= vtx_ray_max_block(), 142), in place: rhs becomes x, and D
+ *   is overwritten by the inverses of the eliminated diagonal blocks; nothing else is allocated.
+ *   One ray per workgroup, Gauss-Jordan elimination with partial pivoting in FP64. A singular
+ *   block gives non-finite x on its ray. The Newton update is F += x with rhs = -G.
+ * Errors as for the rates (VTX_EINVAL for bad sizes or null pointers, checked on the host).
+ */
+int vtx_ray_system(int32_t ne, int64_t nrays, int32_t nzr, double dt, const double* jac, const double* f,
+                   const double* f_n, const double* f_nm1, const double* eta, const double* chi,
+                   const double* lo, const double* up, double* D, double* rhs, void* hip_stream);
+int vtx_ray_solve(int32_t nb, int64_t nrays, int32_t nzr, const double* lo, double* D, const double* up,
+                  double* rhs, void* hip_stream);
+int vtx_ray_max_block(void);
+
 /* Human-readable name of a status code (static storage). */
 const char* vtx_strerror(int code);
 
 /* VTX_ABI_VERSION of the built library. */
 int vtx_abi_version(void);
+
+/* Diagnostic: the rate kernels run one zone per workgroup of 4 waves (the default); waves = 8
+ * runs them with 8. The results do not depend on it, bit for bit (a zone's task units are summed
+ * in unit order whatever wave ran them); only the speed does. Returns the previous setting, or
+ * -VTX_EINVAL for waves other than 4 or 8. Process-wide; affects later calls. */
+int vtx_set_workgroup_waves(int waves);
 
 /* Free every cached table on every device (no call may be in flight). */
 void vtx_release(void);

@@ -231,6 +231,7 @@ struct Plan {
 
 std::mutex g_mu;
 std::vector<std::unique_ptr<Plan>> g_plans;
+int g_block = 256;           // threads per workgroup of the rate kernels (vtx_set_workgroup_waves)
 std::vector<int> g_dev_ok;   // per device: 0 unknown, 1 gfx950, -1 other
 
 void couplings(double s2w, double beta[3][2]) {
@@ -423,6 +424,7 @@ int get_plan(const vtx_grid* g, const vtx_opts* o, DevPlan* out) {
   out->processes = (int)o->processes;
   out->precision = o->precision;
   out->eta_fp64 = o->eta_fp64;
+  out->block = g_block;
   return VTX_OK;
 }
 
@@ -553,6 +555,44 @@ int vtx_rates_forward_interp(const vtx_grid* grid, const vtx_opts* opts, const v
   return e == hipSuccess ? VTX_OK : VTX_EHIP;
 }
 
+int vtx_ray_system(int32_t ne, int64_t nrays, int32_t nzr, double dt, const double* jac, const double* f,
+                   const double* f_n, const double* f_nm1, const double* eta, const double* chi, const double* lo,
+                   const double* up, double* D, double* rhs, void* hip_stream) {
+  if (ne < 1 || ne > vtx::kMaxNE || nrays < 0 || nzr < 1 || nzr > (1 << 22) || !(dt > 0.0) ||
+      !std::isfinite(dt))
+    return VTX_EINVAL;
+  if (nrays > 0x7fffffffLL / nzr) return VTX_EINVAL;
+  if (nrays == 0) return VTX_OK;
+  if (!jac || !f || !f_n || !f_nm1 || !eta || !chi || !lo || !up || !D || !rhs) return VTX_EINVAL;
+  {
+    std::lock_guard<std::mutex> lock(vtx::g_mu);
+    int dev = 0;
+    const int st = vtx::current_device(&dev);
+    if (st < 0) return -st;
+  }
+  const hipError_t e = vtx::launch_ray_system(ne, nrays * nzr, nzr, dt, jac, f, f_n, f_nm1, eta, chi, lo, up, D,
+                                              rhs, (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+
+int vtx_ray_solve(int32_t nb, int64_t nrays, int32_t nzr, const double* lo, double* D, const double* up,
+                  double* rhs, void* hip_stream) {
+  if (nb < 1 || nb > vtx::max_block() || nrays < 0 || nzr < 1) return VTX_EINVAL;
+  if (nrays > 0x7fffffffLL / nzr) return VTX_EINVAL;
+  if (nrays == 0) return VTX_OK;
+  if (!lo || !D || !up || !rhs) return VTX_EINVAL;
+  {
+    std::lock_guard<std::mutex> lock(vtx::g_mu);
+    int dev = 0;
+    const int st = vtx::current_device(&dev);
+    if (st < 0) return -st;
+  }
+  const hipError_t e = vtx::launch_ray_solve(nb, nrays, nzr, lo, D, up, rhs, (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+
+int vtx_ray_max_block(void) { return vtx::max_block(); }
+
 const char* vtx_strerror(int code) {
   switch (code) {
     case VTX_OK: return "ok";
@@ -565,6 +605,14 @@ const char* vtx_strerror(int code) {
 }
 
 int vtx_abi_version(void) { return VTX_ABI_VERSION; }
+
+int vtx_set_workgroup_waves(int waves) {
+  if (waves != 4 && waves != 8) return -VTX_EINVAL;
+  std::lock_guard<std::mutex> lock(vtx::g_mu);
+  const int prev = vtx::g_block / 64;
+  vtx::g_block = 64 * waves;
+  return prev;
+}
 
 void vtx_release(void) {
   std::lock_guard<std::mutex> lock(vtx::g_mu);

@@ -1,5 +1,5 @@
 // Internal declarations shared by the host layer (vtx_host.cpp) and the kernels
-// (vtx_kernels.hip). Not part of the public ABI.
+// (vtx_kernels.hip, vtx_newton.hip). Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,6 +49,7 @@ struct DevPlan {
   int processes;    // VTX_NES | VTX_PAIR
   int precision;    // VTX_FP64 / VTX_MIXED
   int nlag;         // entries of the Laguerre table (m4 for PANEL, nquad for LAGUERRE)
+  int block;        // threads per workgroup of the rate kernels: 256, or 512 (diagnostic)
   double eta_fp64;
   double beta[3][2];
   const double* eps;        // [ne]
@@ -82,5 +83,13 @@ hipError_t launch_forward_backward(const DevPlan& P, int64_t nz, const double* T
 hipError_t launch_backward(const DevPlan& P, int64_t nz, const double* T, const double* eta_e,
                            const double* f, const double* g_eta, const double* g_chi,
                            double* g_T, double* g_eta_e, double* g_f, hipStream_t s);
+
+// Newton step of the radial sweep (vtx_newton.hip).
+hipError_t launch_ray_system(int ne, int64_t nz, int nzr, double dt, const double* jac, const double* f,
+                             const double* f_n, const double* f_nm1, const double* eta, const double* chi,
+                             const double* lo, const double* up, double* D, double* rhs, hipStream_t s);
+hipError_t launch_ray_solve(int nb, int64_t nrays, int nzr, const double* lo, double* D, const double* up,
+                            double* rhs, hipStream_t s);
+int max_block();   // largest diagonal block the solve holds in LDS
 
 }  // namespace vtx

@@ -33,9 +33,11 @@ constexpr int kOffX = 0, kOffY = kM4, kOffW = 2 * kM4, kOffGX = 3 * kM4, kOffGW 
 constexpr int kOffOne = 3 * kM4 + 2 * kMaxNquad;
 constexpr int kTabLen = 3 * kM4 + 3 * kMaxNquad;
 
-// Workgroup size: four waves. The task units of a zone spread over them, and they cover the
-// per-zone contraction's 3 ne lanes up to 32 bins.
-constexpr int kBlock = 256;
+// Workgroup size: four waves (DevPlan::block, 256 lanes), or eight as a diagnostic that the
+// results do not depend on it. The task units of a zone spread over the waves, and four waves
+// cover the per-zone contraction's 3 ne lanes up to 32 bins. Kernels accept either.
+constexpr int kMaxBlock = 512;
+constexpr int kSlotStride = 256;
 
 // Lane modes of a group: every node in the low piece, every node in the high piece, or
 // decided per node (u < split).
@@ -1042,7 +1044,7 @@ constexpr int fwd_waves() {
 }
 
 template <typename Pr, int OUT, bool NPS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fwd_waves<Pr, OUT>())))
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(fwd_waves<Pr, OUT>())))
 void rates_forward_kernel(DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz,
                           const double* __restrict__ etaz, const double* __restrict__ f,
                           double* __restrict__ eta_out, double* __restrict__ chi_out, double* __restrict__ jac) {
@@ -1060,7 +1062,7 @@ void rates_forward_kernel(DevPlan P, int64_t nz, int selm, const double* __restr
 // interpolation variables), then completed and contracted with the zone's own T and f like
 // the forward. Interpolation and contraction run in FP64 whatever precision built the table.
 template <bool NPS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void rates_interp_kernel(DevPlan P, vtx_lattice lat,
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) void rates_interp_kernel(DevPlan P, vtx_lattice lat,
                                                                  const double* __restrict__ table, int64_t nz,
                                                                  const double* __restrict__ Tz,
                                                                  const double* __restrict__ etaz,
@@ -1340,14 +1342,23 @@ __device__ __forceinline__ void node_bwd(const Loop<Pr>& L, const AdjPoly<typena
   S[6] = N::fma(yu, pb, S[6]);
 }
 
+// Nodes in flight per lane: two, or four for FP64 Fermi-Dirac factors with FP32 moments, whose
+// two-wave register budget holds them (the others would spill).
 template <typename Pr, int MODE>
 __device__ __forceinline__ void nodes_bwd(const Loop<Pr>& L, const AdjPoly<typename Pr::R>& Q, int m,
                                           const Tabs<Pr>& tb, typename Pr::R M[5], typename Pr::R H[3],
                                           typename Pr::R S[7]) {
+  if constexpr (sizeof(typename Pr::R) == 4 && sizeof(typename Pr::F) == 8) {
+#pragma unroll 4
+    for (int k = 0; k < m; ++k)
+      node_bwd<Pr, MODE>(L, Q, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], tb.r[L.oa + k],
+                         tb.r[L.ob + k], M, H, S);
+  } else {
 #pragma unroll 2
-  for (int k = 0; k < m; ++k)
-    node_bwd<Pr, MODE>(L, Q, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], tb.r[L.oa + k],
-                       tb.r[L.ob + k], M, H, S);
+    for (int k = 0; k < m; ++k)
+      node_bwd<Pr, MODE>(L, Q, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], tb.r[L.oa + k],
+                         tb.r[L.ob + k], M, H, S);
+  }
 }
 
 template <typename Pr>
@@ -1405,11 +1416,12 @@ __device__ __forceinline__ void group_grad(const Task& K, const GroupDesc& G, co
 // Recompute one task with derivatives. adj: upstream weights of the task components
 // (scattering: the four (S, l); pair: l = 0, 1 of both orientations). Returns the task
 // values q and adds d/dT, d/deta_e to gT, gE. lq: the lane's LDS slot (13 values, stride
-// kBlock) that holds a pair task's adjoint-weighted piece coefficients A[5] | B[3] | C[5].
+// kSlotStride) that holds a pair task's adjoint-weighted piece coefficients A[5] | B[3] | C[5].
 template <typename Pr, bool PAIR>
 __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const Tabs<Pr>& tb, const Zone& Z, int t, const Q4& adj,
                                             typename Pr::R* lq, double& gT, double& gE) {
   using R = typename Pr::R;
+  constexpr int bs = kSlotStride;
   const Task K = make_task<PAIR>(P, t);
   const Brk Bk = task_breakpoints<PAIR>(K, Z);
   Slots<R> Sl = {};
@@ -1430,12 +1442,12 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const Tabs<Pr>& tb
     const PairCoef& D = *opaque(P.pair_coef + K.j * P.ne + K.i);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      lq[k * kBlock] = R(adj.a * C.A[0][k] + adj.b * C.A[1][k] + adj.c * D.A[0][k] + adj.d * D.A[1][k]);
-      lq[(8 + k) * kBlock] = R(adj.a * C.C[0][k] + adj.b * C.C[1][k] + adj.c * D.C[0][k] + adj.d * D.C[1][k]);
+      lq[k * bs] = R(adj.a * C.A[0][k] + adj.b * C.A[1][k] + adj.c * D.A[0][k] + adj.d * D.A[1][k]);
+      lq[(8 + k) * bs] = R(adj.a * C.C[0][k] + adj.b * C.C[1][k] + adj.c * D.C[0][k] + adj.d * D.C[1][k]);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      lq[(5 + k) * kBlock] = R(adj.a * C.B[0][k] + adj.b * C.B[1][k] + adj.c * D.B[0][k] + adj.d * D.B[1][k]);
+      lq[(5 + k) * bs] = R(adj.a * C.B[0][k] + adj.b * C.B[1][k] + adj.c * D.B[0][k] + adj.d * D.B[1][k]);
   }
   // kept rolled: unrolled, the four groups' live state exceeds the register budget; the lower
   // end of a group is the upper end of the one before
@@ -1450,12 +1462,12 @@ __device__ __forceinline__ Q4 task_backward(const DevPlan& P, const Tabs<Pr>& tb
     const double Es = make_loop<Pr>(K, G, Z, L);
     if (PAIR) {
       // the group's piece: A (slots 0-4), B (5-7) or C (8-12); the other part stays zero
-      const R* pl = lq + (G.piece == 2 ? 8 : 0) * kBlock;
+      const R* pl = lq + (G.piece == 2 ? 8 : 0) * bs;
       R lo[5], hi[3];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) lo[k] = G.piece == 1 ? R(0) : pl[k * kBlock];
+      for (int k = 0; k < 5; ++k) lo[k] = G.piece == 1 ? R(0) : pl[k * bs];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) hi[k] = G.piece == 1 ? lq[(5 + k) * kBlock] : R(0);
+      for (int k = 0; k < 3; ++k) hi[k] = G.piece == 1 ? lq[(5 + k) * bs] : R(0);
       make_adj_poly_r<R>(lo, hi, Q);
     }
     R M[5] = {0, 0, 0, 0, 0}, H[3] = {0, 0, 0}, S[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -1576,9 +1588,11 @@ __device__ void zone_backward(const DevPlan& P, const Tabs<Pr>& tb, Zone* zs, do
   const Adj A{smem, smem + off_ge, smem + off_gc, ne};
   const Units U = task_units(ntn, ntm, ntp);
   const int lane = threadIdx.x & 63;
-  // per-lane slots after the contraction parts: 13 bulk-type values per lane, stride kBlock
+  // per-lane slots after the contraction parts: 13 bulk-type values per lane, stride
+  // kSlotStride, in banks of kSlotStride lanes (a constant stride folds into the LDS offsets)
   using R = typename Pr::R;
-  R* lq = reinterpret_cast<R*>(smem + L.d + 2 * n2 + 24 * ne) + threadIdx.x;
+  R* lq = reinterpret_cast<R*>(smem + L.d + 2 * n2 + 24 * ne) + (threadIdx.x % kSlotStride) +
+          (threadIdx.x / kSlotStride) * (13 * kSlotStride);
   // d/dT and d/deta_e: summed per unit in the unit's wave, then over units in unit order, so
   // the result does not depend on which wave ran which unit
   for (int u = U.first; u < U.nU; u += U.step) {
@@ -1701,7 +1715,7 @@ constexpr int bwd_waves() {
 }
 
 template <typename Pr, bool NPS, bool FUSED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(bwd_waves<Pr>())))
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(bwd_waves<Pr>())))
 void rates_backward_kernel(
     DevPlan P, int64_t nz, int selm, const double* __restrict__ Tz, const double* __restrict__ etaz,
     const double* __restrict__ f, const double* __restrict__ g_eta, const double* __restrict__ g_chi,
@@ -1730,7 +1744,7 @@ size_t zone_lds_fwd(const DevPlan& P) {
 // fused forward + backward reuses them for the forward's contraction parts (48 ne doubles).
 size_t zone_lds_bwd(const DevPlan& P, size_t elem, bool fused) {
   const size_t head = sizeof(double) * (18 * P.ne + task_values(P) + 2 * P.ne * P.ne);
-  const size_t bwd = head + sizeof(double) * 24 * P.ne + 13 * kBlock * elem;
+  const size_t bwd = head + sizeof(double) * 24 * P.ne + 13 * (size_t)P.block * elem;
   const size_t fwd = head + sizeof(double) * 48 * P.ne;
   return fused && fwd > bwd ? fwd : bwd;
 }
@@ -1757,7 +1771,7 @@ hipError_t forward_pass(const DevPlan& P, int64_t nz, int selm, const double* T,
   const size_t lds = zone_lds_fwd(P);
   hipError_t e;
   if ((e = allow_lds(k, lds)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3((unsigned)nz), dim3(kBlock), lds, s, P, nz, selm, T, eta_e, f, eta, chi, jac);
+  hipLaunchKernelGGL(k, dim3((unsigned)nz), dim3(P.block), lds, s, P, nz, selm, T, eta_e, f, eta, chi, jac);
   return hipGetLastError();
 }
 
@@ -1789,7 +1803,7 @@ hipError_t interp_slice_t(const DevPlan& P, const vtx_lattice& lat, const double
   const size_t lds = zone_lds_fwd(P);
   hipError_t e;
   if ((e = allow_lds(rates_interp_kernel<NPS>, lds)) != hipSuccess) return e;
-  hipLaunchKernelGGL(rates_interp_kernel<NPS>, dim3((unsigned)nz), dim3(kBlock), lds, s, P, lat, table, nz, T,
+  hipLaunchKernelGGL(rates_interp_kernel<NPS>, dim3((unsigned)nz), dim3(P.block), lds, s, P, lat, table, nz, T,
                      eta_e, f, eta, chi);
   return hipGetLastError();
 }
@@ -1802,7 +1816,7 @@ hipError_t backward_pass(const DevPlan& P, int64_t nz, int selm, const double* T
   const size_t lds = zone_lds_bwd(P, sizeof(typename Pr::R), FUSED);
   hipError_t e;
   if ((e = allow_lds(k, lds)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3((unsigned)nz), dim3(kBlock), lds, s, P, nz, selm, T, eta_e, f, g_eta, g_chi, g_T,
+  hipLaunchKernelGGL(k, dim3((unsigned)nz), dim3(P.block), lds, s, P, nz, selm, T, eta_e, f, g_eta, g_chi, g_T,
                      g_eta_e, g_f, eta, chi);
   return hipGetLastError();
 }

@@ -143,3 +143,72 @@ def random_gradients(nzones: int, ne: int, seed: int):
     g_eta = rng.standard_normal((nzones, NSPECIES, 2, ne))
     g_chi = rng.standard_normal((nzones, NSPECIES, 2, ne))
     return g_eta, g_chi
+
+
+def sample_zones_stratified(inp: ZoneInputs, count: int, seed: int = 0, corner_share: float = 0.125,
+                            cells: int = 8):
+    """Indices of a seeded zone sample stratified over (T, eta_e).
+
+    Always holds the min-T, max-T, min-eta_e and max-eta_e zones; then about ``corner_share``
+    of the sample from the corner of high degeneracy at low temperature (eta_e > 30 and T < 2
+    MeV, where the Fermi-Dirac factors are most extreme); the rest spread evenly over a
+    ``cells`` x ``cells`` grid of T (geometric bins) and eta_e (uniform bins) over the zones'
+    range, drawn at random inside each cell. Sorted, without repeats."""
+    nz = inp.T.shape[0]
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 1500 + seed))
+    chosen = []
+    seen = set()
+
+    def take(cands, k):
+        cands = np.asarray(cands)
+        if cands.size == 0 or k <= 0:
+            return
+        picks = rng.permutation(cands)
+        n = 0
+        for c in picks:
+            c = int(c)
+            if c not in seen:
+                seen.add(c)
+                chosen.append(c)
+                n += 1
+                if n >= k:
+                    break
+
+    for c in (np.argmin(inp.T), np.argmax(inp.T), np.argmin(inp.eta_e), np.argmax(inp.eta_e)):
+        take([int(c)], 1)
+    corner = np.nonzero((inp.eta_e > 30.0) & (inp.T < 2.0))[0]
+    take(corner, int(round(corner_share * count)))
+    lt = np.log(inp.T)
+    tb = np.minimum(((lt - lt.min()) / max(lt.max() - lt.min(), 1e-300) * cells).astype(np.int64), cells - 1)
+    eb = np.minimum(((inp.eta_e - inp.eta_e.min()) / max(inp.eta_e.max() - inp.eta_e.min(), 1e-300) * cells)
+                    .astype(np.int64), cells - 1)
+    cell = tb * cells + eb
+    order = np.argsort(cell, kind="stable")
+    bounds = np.searchsorted(cell[order], np.arange(cells * cells + 1))
+    left = count - len(chosen)
+    for c in range(cells * cells):
+        share = left // (cells * cells - c)
+        before = len(chosen)
+        take(order[bounds[c]:bounds[c + 1]], share)
+        left -= len(chosen) - before
+    if left > 0:
+        take(np.arange(nz), left)
+    return np.array(sorted(chosen[:count]), dtype=np.int64)
+
+
+GRAD_PERIOD = 4099
+
+
+def gradient_pool(ne: int, seed: int, period: int = GRAD_PERIOD):
+    """Seeded upstream-gradient rows g_eta, g_chi [period, 3, 2, NE] (unit normals). Zone z of a
+    workload takes row z mod period, so a full-size workload's gradients are a gather on any
+    device and the rows of sampled zones are known without drawing the rest."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 2500 + seed))
+    return (rng.standard_normal((period, NSPECIES, 2, ne)), rng.standard_normal((period, NSPECIES, 2, ne)))
+
+
+def pooled_gradients(idx, ne: int, seed: int, period: int = GRAD_PERIOD):
+    """The pool rows of the zones idx (see gradient_pool)."""
+    ge, gc = gradient_pool(ne, seed, period)
+    r = np.asarray(idx) % period
+    return np.ascontiguousarray(ge[r]), np.ascontiguousarray(gc[r])

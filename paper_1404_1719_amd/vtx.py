@@ -77,10 +77,18 @@ def library():
     lib.vtx_rates_forward_interp.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), ctypes.POINTER(Lattice),
                                              vp, i64, i64, vp, vp, vp, vp, vp, vp]
     lib.vtx_rates_forward_interp.restype = ctypes.c_int
+    lib.vtx_ray_system.argtypes = [ctypes.c_int32, i64, ctypes.c_int32, ctypes.c_double] + [vp] * 11
+    lib.vtx_ray_system.restype = ctypes.c_int
+    lib.vtx_ray_solve.argtypes = [ctypes.c_int32, i64, ctypes.c_int32, vp, vp, vp, vp, vp]
+    lib.vtx_ray_solve.restype = ctypes.c_int
+    lib.vtx_ray_max_block.argtypes = []
+    lib.vtx_ray_max_block.restype = ctypes.c_int
     lib.vtx_strerror.argtypes = [ctypes.c_int]
     lib.vtx_strerror.restype = ctypes.c_char_p
     lib.vtx_abi_version.argtypes = []
     lib.vtx_abi_version.restype = ctypes.c_int
+    lib.vtx_set_workgroup_waves.argtypes = [ctypes.c_int]
+    lib.vtx_set_workgroup_waves.restype = ctypes.c_int
     lib.vtx_release.argtypes = []
     lib.vtx_release.restype = None
     lib.vtx_gauss_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
@@ -297,6 +305,55 @@ def forward_interp(grid: GridHandle, opts: Opts, lat: Lattice, table, T, eta_e, 
     return eta, chi
 
 
+def ray_system(ne, nrays, nzr, dt, jac, f, f_n, f_nm1, eta, chi, lo, up, D=None, rhs=None, stream=None):
+    """Diagonal blocks D [nrays*nzr, 6ne, 6ne] and rhs = -G [nrays*nzr, 6ne] of the Newton step
+    of the radial sweep (vtx_ray_system; zones laid out ray by ray)."""
+    import torch
+    nz, nb = nrays * nzr, 6 * ne
+    fs = (nz, 3, 2, ne)
+    if D is None:
+        D = torch.empty((nz, nb, nb), dtype=torch.float64, device=f.device)
+    if rhs is None:
+        rhs = torch.empty((nz, nb), dtype=torch.float64, device=f.device)
+    rc = library().vtx_ray_system(ne, nrays, nzr, float(dt), _dev_ptr(jac, "jac", (nz, 3, 2, 4, ne, ne)),
+                                  _dev_ptr(f, "f", fs), _dev_ptr(f_n, "f_n", fs), _dev_ptr(f_nm1, "f_nm1", fs),
+                                  _dev_ptr(eta, "eta", fs), _dev_ptr(chi, "chi", fs), _dev_ptr(lo, "lo", (nz, nb)),
+                                  _dev_ptr(up, "up", (nz, nb)), _dev_ptr(D, "D", (nz, nb, nb)),
+                                  _dev_ptr(rhs, "rhs", (nz, nb)), _stream_handle(stream))
+    _check(rc, "vtx_ray_system")
+    return D, rhs
+
+
+def ray_solve(nrays, nzr, lo, D, up, rhs, stream=None):
+    """Block-tridiagonal solve along rays, in place (vtx_ray_solve): rhs becomes x, D is
+    overwritten. lo, up, rhs [nrays*nzr, nb]; D [nrays*nzr, nb, nb]."""
+    nz = nrays * nzr
+    nb = rhs.shape[-1]
+    rc = library().vtx_ray_solve(nb, nrays, nzr, _dev_ptr(lo, "lo", (nz, nb)), _dev_ptr(D, "D", (nz, nb, nb)),
+                                 _dev_ptr(up, "up", (nz, nb)), _dev_ptr(rhs, "rhs", (nz, nb)), _stream_handle(stream))
+    _check(rc, "vtx_ray_solve")
+    return rhs
+
+
+def newton_increment(grid: GridHandle, opts: Opts, nrays, nzr, T, eta_e, f, f_n, f_nm1, lo, up, dt, stream=None):
+    """Newton increment dF [nrays*nzr, 3, 2, ne] of the radial-sweep system at f: the rates and
+    their explicit blocks (one vtx_rates_jacobian call), the system (vtx_ray_system), the solve
+    (vtx_ray_solve). Allocates D: 8 (6 ne)^2 bytes per zone."""
+    jac, eta, chi = jacobian(grid, opts, T, eta_e, stream=stream, f=f)
+    D, rhs = ray_system(grid.ne, nrays, nzr, dt, jac, f, f_n, f_nm1, eta, chi, lo, up, stream=stream)
+    del jac
+    ray_solve(nrays, nzr, lo, D, up, rhs, stream=stream)
+    return rhs.view(f.shape)
+
+
+def set_workgroup_waves(waves: int) -> int:
+    """Diagnostic: run the rate kernels with 4 (default) or 8 waves per zone; returns the previous."""
+    prev = library().vtx_set_workgroup_waves(waves)
+    if prev < 0:
+        raise ValueError("waves must be 4 or 8")
+    return prev
+
+
 def gauss_rule(kind: int, n: int):
     """Host-side Gauss rule of the library: kind 0 Legendre on [0, 1], 1 Laguerre (w e^x)."""
     x = np.zeros(n)
@@ -332,9 +389,13 @@ def _make_function():
 
         @staticmethod
         def forward(ctx, T, eta_e, f, grid, opts):
-            ctx.grid, ctx.opts = grid, opts
-            ctx.save_for_backward(T, eta_e, f)
-            return forward(grid, opts, T.contiguous(), eta_e.contiguous(), f.contiguous())
+            # the contiguous operands the forward used, and a copy of the options, so that the
+            # backward sees exactly the forward's inputs whatever the caller changes later
+            Tc, Ec, fc = T.contiguous(), eta_e.contiguous(), f.contiguous()
+            ctx.grid = grid
+            ctx.opts = Opts.from_buffer_copy(opts)
+            ctx.save_for_backward(Tc, Ec, fc)
+            return forward(grid, ctx.opts, Tc, Ec, fc)
 
         @staticmethod
         def backward(ctx, g_eta, g_chi):

@@ -1,0 +1,116 @@
+"""Write the stored oracle references of the full-size parity tests and the benchmark's
+error report: tests/golden/ref_<workload>.npz.
+
+For each workload below, the FP64 oracle (oracle/, same rule as the library) is run on a
+seeded sample of zones stratified over (T, eta_e) (paper_1404_1719_amd.synth.
+sample_zones_stratified: the extreme zones, a share from the corner eta_e > 30, T < 2 MeV, the
+rest spread over an 8 x 8 grid), forward on the whole sample and backward on a stratified
+sub-sample, with the upstream gradients of synth.pooled_gradients (zone z takes pool row
+z mod 4099, so a full-size run draws them by a gather on the device).
+
+Stored: idx, the zones' T and eta_e, eta, chi (float64) and the absolute scales A_eta, A_chi
+of the relative-error floor (float32); idx_b, g_T, g_eta_e, g_f (float64); and a hash of the
+oracle's and the sampler's sources, which the CPU tests compare with the current files.
+
+Calls only oracle/ and the seeded input generators. Usage (about ten minutes on 8 cores):
+    python tests/golden/make_reference.py [--workers 8] [--only large]
+"""
+import argparse
+import hashlib
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from paper_1404_1719_amd import synth  # noqa: E402
+
+# workload -> (forward sample, backward sub-sample)
+PLAN = {"large": (4096, 512), "medium": (1024, 128)}
+GRAD_SEED = 7
+SAMPLE_SEED = 0
+
+
+def source_hash():
+    """sha256 over the oracle's sources and the input generator (sampling, gradients)."""
+    h = hashlib.sha256()
+    files = sorted(os.path.join(ROOT, "oracle", f) for f in os.listdir(os.path.join(ROOT, "oracle"))
+                   if f.endswith(".py"))
+    files.append(os.path.join(ROOT, "paper_1404_1719_amd", "synth.py"))
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def path(name):
+    return os.path.join(HERE, f"ref_{name}.npz")
+
+
+def samples(inp, nf, nb):
+    idx = synth.sample_zones_stratified(inp, nf, SAMPLE_SEED)
+    sub = synth.sample_zones_stratified(synth.subset(inp, idx), nb, SAMPLE_SEED + 1)
+    return idx, idx[sub]
+
+
+def _fwd(args):
+    from oracle import rates as orates
+    eps, w, T, E, f, nquad, rule = args
+    return orates.forward_with_scale(eps, w, T, E, f, orates.Options(nquad=nquad, rule=rule))
+
+
+def _bwd(args):
+    from oracle import grad as ograd
+    from oracle import rates as orates
+    eps, w, T, E, f, ge, gc, nquad, rule = args
+    return ograd.vjp(eps, w, T, E, f, ge, gc, orates.Options(nquad=nquad, rule=rule))
+
+
+def make(name, workers):
+    wl = synth.WORKLOADS[name]
+    nf, nb = PLAN[name]
+    t0 = time.time()
+    inp = synth.make_inputs(name)
+    idx, idx_b = samples(inp, nf, nb)
+    print(f"[ref] {name}: {len(idx)} forward zones, {len(idx_b)} backward zones (draw {time.time() - t0:.0f} s)",
+          flush=True)
+    sub, sub_b = synth.subset(inp, idx), synth.subset(inp, idx_b)
+    del inp
+    ge, gc = synth.pooled_gradients(idx_b, wl.ne, GRAD_SEED)
+    pieces = np.array_split(np.arange(len(idx)), 8 * workers)
+    pieces_b = np.array_split(np.arange(len(idx_b)), 4 * workers)
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        fw = ex.map(_fwd, [(sub.eps, sub.w, sub.T[p], sub.eta_e[p], sub.f[p], wl.nquad, wl.rule) for p in pieces])
+        bw = ex.map(_bwd, [(sub_b.eps, sub_b.w, sub_b.T[p], sub_b.eta_e[p], sub_b.f[p], ge[p], gc[p], wl.nquad,
+                            wl.rule) for p in pieces_b])
+        fw, bw = list(fw), list(bw)
+    eta, chi, ae, ac = (np.concatenate([r[k] for r in fw]) for k in range(4))
+    gT, gE, gf = (np.concatenate([r[k] for r in bw]) for k in range(3))
+    np.savez_compressed(path(name), workload=name, source_hash=source_hash(), grad_seed=GRAD_SEED,
+                        idx=idx, T=sub.T, eta_e=sub.eta_e, eta=eta, chi=chi, a_eta=ae.astype(np.float32),
+                        a_chi=ac.astype(np.float32),
+                        idx_b=idx_b, g_T=gT, g_eta_e=gE, g_f=gf)
+    print(f"[ref] {name}: written {path(name)} ({os.path.getsize(path(name)) / 1e6:.1f} MB, "
+          f"{time.time() - t0:.0f} s)", flush=True)
+
+
+def load(name):
+    """The stored reference of a workload as a dict of arrays (no pickle)."""
+    with np.load(path(name), allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workers", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--only", default=None, choices=sorted(PLAN))
+    a = ap.parse_args()
+    for n in PLAN:
+        if a.only in (None, n):
+            make(n, a.workers)

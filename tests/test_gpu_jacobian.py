@@ -60,12 +60,18 @@ def check(inp, precision, nquad, rule, tol, processes=3, label=""):
     absj = orates.jacobian(inp.eps, inp.w, inp.T, inp.eta_e, opts, absolute=True)
     assert np.all(np.isfinite(J))
     err = jac_err(J, ref, absj)
+    err3 = np.abs(J - ref) / np.maximum(np.maximum(np.abs(ref), 1e-3 * absj), 1e-290)
     plain = np.abs(J - ref) / np.maximum(np.abs(ref), 1e-290)
     big = np.abs(ref) >= 1e-3 * np.sum(absj, axis=-1, keepdims=True)
-    say(f"    max rel err {err.max():.2e}; over entries >= 1e-3 of their row, plain relative error by "
-        f"(process, output): " + " ".join(f"{p}{o}:{plain[:, :, p, o][big[:, :, p, o]].max(initial=0):.1e}"
-                                          for p in range(2) for o in range(4)))
+    say(f"    max rel err {err.max():.2e} (floor A), {err3.max():.2e} (floor 1e-3 A; l = 0 "
+        f"{err3[:, :, :, :2].max():.2e}, l = 1 {err3[:, :, :, 2:].max():.2e}); over entries >= 1e-3 of their "
+        f"row, plain relative error by (process, output): " +
+        " ".join(f"{p}{o}:{plain[:, :, p, o][big[:, :, p, o]].max(initial=0):.1e}" for p in range(2) for o in range(4)))
     assert err.max() <= tol
+    # l = 0 entries (no sign change in the angular weight) are held to the forward's floor
+    assert err3[:, :, :, :2].max() <= tol
+    if tol <= 1e-6:
+        assert err3.max() <= tol
     return J
 
 

@@ -1,0 +1,164 @@
+"""GPU parity of the Newton step of the radial sweep (vtx_ray_system, vtx_ray_solve) against the
+oracle (oracle.newton): the assembled diagonal blocks and right-hand side, the block-tridiagonal
+solve, and the whole increment. At the size of a workload chunk, the solve's residual is
+checked on sampled rays against their saved blocks.
+
+Bars: FP64 relative 1e-9 on blocks (against the largest entry of each block) and on the solve;
+the increment from mixed-precision rates within 1e-4 of the FP64 oracle's.
+"""
+import numpy as np
+import pytest
+
+from oracle import newton as onewton
+from oracle import rates as orates
+from paper_1404_1719_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1404_1719_amd import vtx  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def problem(nrays, nzr, ne=21, seed=1):
+    """Zone states of the medium workload's ranges; the time step and the radial coupling on the
+    scale of the rates (the median opacity kappa: dt = 1/kappa, lo, up ~ kappa U(0, 1/2)), so the
+    rates' Jacobian weighs as much as the other terms."""
+    eps, w = synth.energy_grid(ne, 2.0, 380.0)
+    T, eta_e, f = synth.draw_zones(nrays * nzr, ne, eps, (1.0, 40.0), (0.0, 40.0), (-2.0, 15.0), 0.05, 4400 + seed)
+    rng = np.random.default_rng(seed)
+    f_n = np.clip(f * (1 + 0.01 * rng.standard_normal(f.shape)), 0, 1)
+    f_nm1 = np.clip(f * (1 + 0.01 * rng.standard_normal(f.shape)), 0, 1)
+    nb = 6 * ne
+    _, chi = orates.forward(eps, w, T, eta_e, f, orates.Options(nquad=16))
+    kappa = float(np.median(chi[:, :, 0]))
+    lo = kappa * rng.uniform(0.0, 0.5, (nrays * nzr, nb))
+    up = kappa * rng.uniform(0.0, 0.5, (nrays * nzr, nb))
+    return eps, w, T, eta_e, f, f_n, f_nm1, lo, up, 1.0 / kappa
+
+
+def oracle_system(eps, w, T, E, f, f_n, f_nm1, lo, up, dt, nrays, nzr, nquad=48):
+    opts = orates.Options(nquad=nquad)
+    eta, chi = orates.forward(eps, w, T, E, f, opts)
+    jac = orates.jacobian(eps, w, T, E, opts)
+    sh = (nrays, nzr) + f.shape[1:]
+    nb = f[0].size
+    D, rhs = onewton.system(jac.reshape((nrays, nzr) + jac.shape[1:]), f.reshape(sh), f_n.reshape(sh),
+                            f_nm1.reshape(sh), eta.reshape(sh), chi.reshape(sh), lo.reshape(nrays, nzr, nb),
+                            up.reshape(nrays, nzr, nb), dt)
+    return D, rhs
+
+
+def test_system_and_solve_against_oracle():
+    nrays, nzr = 2, 4
+    eps, w, T, E, f, fn, fm, lo, up, dt = problem(nrays, nzr)
+    ne, nb = eps.shape[0], f[0].size
+    Dref, rref = oracle_system(eps, w, T, E, f, fn, fm, lo, up, dt, nrays, nzr)
+    grid = vtx.GridHandle(eps, w)
+    opts = vtx.make_opts("fp64", 48, "panel")
+    jac, eta, chi = vtx.jacobian(grid, opts, dev(T), dev(E), f=dev(f))
+    D, rhs = vtx.ray_system(ne, nrays, nzr, dt, jac, dev(f), dev(fn), dev(fm), eta, chi, dev(lo), dev(up))
+    torch.cuda.synchronize()
+    Dg = D.cpu().numpy().reshape(Dref.shape)
+    rg = rhs.cpu().numpy().reshape(rref.shape)
+    blk = np.abs(Dref).max(axis=(-1, -2), keepdims=True)
+    eD = (np.abs(Dg - Dref) / blk).max()
+    er = (np.abs(rg - rref) / np.abs(rref).max(axis=-1, keepdims=True)).max()
+    print(f"[gpu] ray system NE={ne}: blocks {eD:.2e}, right-hand side {er:.2e}", flush=True)
+    assert eD <= 1e-9 and er <= 1e-9
+    # the solve of the oracle's system against the oracle's dense solve
+    xref = onewton.solve(lo.reshape(nrays, nzr, nb), Dref, up.reshape(nrays, nzr, nb), rref)
+    Dd, bd = dev(Dref.reshape(-1, nb, nb)), dev(rref.reshape(-1, nb))
+    vtx.ray_solve(nrays, nzr, dev(lo), Dd, dev(up), bd)
+    torch.cuda.synchronize()
+    x = bd.cpu().numpy().reshape(xref.shape)
+    ex = np.abs(x - xref).max() / np.abs(xref).max()
+    print(f"    solve: max |x - x_ref| / max |x_ref| = {ex:.2e}", flush=True)
+    assert ex <= 1e-9
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-4)])
+def test_newton_increment(precision, tol):
+    nrays, nzr = 2, 3
+    eps, w, T, E, f, fn, fm, lo, up, dt = problem(nrays, nzr, seed=2)
+    nb = f[0].size
+    Dref, rref = oracle_system(eps, w, T, E, f, fn, fm, lo, up, dt, nrays, nzr)
+    xref = onewton.solve(lo.reshape(nrays, nzr, nb), Dref, up.reshape(nrays, nzr, nb), rref).reshape(f.shape)
+    grid = vtx.GridHandle(eps, w)
+    opts = vtx.make_opts(precision, 48, "panel")
+    dF = vtx.newton_increment(grid, opts, nrays, nzr, dev(T), dev(E), dev(f), dev(fn), dev(fm), dev(lo), dev(up), dt)
+    torch.cuda.synchronize()
+    x = dF.cpu().numpy()
+    err = np.abs(x - xref).max() / np.abs(xref).max()
+    print(f"[gpu] Newton increment {precision}: {err:.2e}", flush=True)
+    assert err <= tol
+
+
+def test_pivoting_edge_cases():
+    """A zero leading entry (the solve must pivot), blocks of one value, a ray of one zone."""
+    rng = np.random.default_rng(9)
+    for nrays, nzr, nb in ((3, 5, 9), (2, 4, 1), (4, 1, 17), (1, 7, 142)):
+        D = rng.standard_normal((nrays, nzr, nb, nb)) + 0.5 * nb ** 0.5 * np.eye(nb)
+        D[:, :, 0, 0] = 0.0
+        if nb > 1:
+            D[:, :, 0, 1] += 3.0
+        lo, up = rng.uniform(0, 1, (nrays, nzr, nb)), rng.uniform(0, 1, (nrays, nzr, nb))
+        b = rng.standard_normal((nrays, nzr, nb))
+        xref = onewton.solve(lo, D, up, b)
+        bd = dev(b.reshape(-1, nb))
+        vtx.ray_solve(nrays, nzr, dev(lo.reshape(-1, nb)), dev(D.reshape(-1, nb, nb)), dev(up.reshape(-1, nb)), bd)
+        torch.cuda.synchronize()
+        x = bd.cpu().numpy().reshape(xref.shape)
+        err = np.abs(x - xref).max() / np.abs(xref).max()
+        assert err <= 1e-9, (nrays, nzr, nb, err)
+    with pytest.raises(RuntimeError):
+        z = torch.zeros((1, 143), dtype=torch.float64, device=DEV)
+        vtx.ray_solve(1, 1, z, torch.zeros((1, 143, 143), dtype=torch.float64, device=DEV), z, z.clone())
+
+
+def test_solve_at_chunk_scale_residual():
+    """64 rays x 600 zones at NE = 21 (blocks of 126), the system of the medium workload's zone
+    states: on sampled rays, the saved blocks times the solution reproduce the right-hand side."""
+    nrays, nzr, ne = 64, 600, 21
+    wl = synth.WORKLOADS["medium"]
+    inp = synth.make_inputs("medium", nzones=nrays * nzr)
+    nb = 6 * ne
+    rng = np.random.default_rng(11)
+    f = inp.f
+    fn = np.clip(f * (1 + 0.01 * rng.standard_normal(f.shape)), 0, 1)
+    lo = rng.uniform(0.0, 0.5, (nrays * nzr, nb))
+    up = rng.uniform(0.0, 0.5, (nrays * nzr, nb))
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts("mixed", wl.nquad, wl.rule)
+    Tt, Et, ft, fnt, lot, upt = dev(inp.T), dev(inp.eta_e), dev(f), dev(fn), dev(lo), dev(up)
+    jac, eta, chi = vtx.jacobian(grid, opts, Tt, Et, f=ft)
+    print(f"[gpu] ray solve at scale: {nrays} rays x {nzr} zones, blocks {nb}", flush=True)
+    kappa = float(torch.median(chi[:, :, 0]).item())
+    lot, upt = lot * kappa, upt * kappa
+    D, rhs = vtx.ray_system(ne, nrays, nzr, 1.0 / kappa, jac, ft, fnt, fnt, eta, chi, lot, upt)
+    del jac
+    keep = [0, 37, 63]
+    Dk = {a: D[a * nzr:(a + 1) * nzr].cpu().numpy() for a in keep}
+    bk = {a: rhs[a * nzr:(a + 1) * nzr].cpu().numpy() for a in keep}
+    vtx.ray_solve(nrays, nzr, lot, D, upt, rhs)
+    torch.cuda.synchronize()
+    x = rhs.cpu().numpy().reshape(nrays, nzr, nb)
+    assert np.all(np.isfinite(x))
+    lo_s, up_s = lot.cpu().numpy(), upt.cpu().numpy()
+    for a in keep:
+        la, ua = lo_s.reshape(nrays, nzr, nb)[a], up_s.reshape(nrays, nzr, nb)[a]
+        y = np.einsum("rij,rj->ri", Dk[a], x[a])
+        y[1:] -= la[1:] * x[a, :-1]
+        y[:-1] -= ua[:-1] * x[a, 1:]
+        scale = np.abs(Dk[a]).max() * np.abs(x[a]).max()
+        res = np.abs(y - bk[a]).max() / scale
+        print(f"    ray {a}: residual {res:.2e} of |D| |x|", flush=True)
+        assert res <= 1e-12

@@ -10,7 +10,6 @@ Full-size workloads run in one launch over every zone, exactly as the benchmark 
 them, and sampled zones (always including the min-T, max-T and max-eta_e zones) are
 compared with the oracle zone by zone.
 """
-import functools
 import sys
 
 import numpy as np
@@ -93,102 +92,6 @@ def test_single_process(processes):
     inp = synth.make_inputs("medium", nzones=8)
     check_forward(inp, "fp64", 48, "panel", FP64_TOL, processes, label="medium-8")
     check_forward(inp, "mixed", 48, "panel", MIXED_TOL, processes, label="medium-8")
-
-
-@functools.lru_cache(maxsize=1)
-def _full_inputs(name):
-    say(f"[gpu] full-size {name}: drawing {synth.WORKLOADS[name].nzones} zones")
-    return synth.make_inputs(name)
-
-
-def _full_then_sample(name, count, precision):
-    wl = synth.WORKLOADS[name]
-    inp = _full_inputs(name)
-    grid = vtx.GridHandle(inp.eps, inp.w)
-    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
-    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
-    say(f"[gpu] full-size {name} {precision}: one launch over {wl.nzones} zones")
-    eta, chi = vtx.forward(grid, opts, T, E, f)
-    torch.cuda.synchronize()
-    idx = synth.sample_zones(inp, count)
-    it = torch.from_numpy(idx).to(DEV)
-    e = eta.index_select(0, it).cpu().numpy()
-    c = chi.index_select(0, it).cpu().numpy()
-    del eta, chi, T, E, f
-    torch.cuda.empty_cache()
-    sub = synth.subset(inp, idx)
-    re, rc, ae, ac = oracle_forward(sub, wl.nquad, wl.rule)
-    err = max(rel_err(e, re, ae).max(), rel_err(c, rc, ac).max())
-    say(f"    {name} {precision}: sampled {len(idx)} zones, max rel err {err:.2e}")
-    assert np.all(np.isfinite(e)) and np.all(np.isfinite(c))
-    return err
-
-
-@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
-def test_medium_full_size_sampled(precision, tol):
-    assert _full_then_sample("medium", 40, precision) <= tol
-
-
-@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
-def test_large_full_size_sampled(precision, tol):
-    assert _full_then_sample("large", 24, precision) <= tol
-
-
-@functools.lru_cache(maxsize=1)
-def _large_backward_reference(count):
-    """Sampled zones of the large workload, their upstream gradients (drawn on the device for
-    every zone, seeded) and the oracle's reverse-mode products for them."""
-    wl = synth.WORKLOADS["large"]
-    inp = _full_inputs("large")
-    gen = torch.Generator(device=DEV)
-    gen.manual_seed(synth.SEED_BASE + 4000)
-    shp = tuple(inp.f.shape)
-    ge = torch.randn(shp, dtype=torch.float64, device=DEV, generator=gen)
-    gc = torch.randn(shp, dtype=torch.float64, device=DEV, generator=gen)
-    idx = synth.sample_zones(inp, count)
-    it = torch.from_numpy(idx).to(DEV)
-    g_eta, g_chi = (x.index_select(0, it).cpu().numpy() for x in (ge, gc))
-    del ge, gc
-    torch.cuda.empty_cache()
-    sub = synth.subset(inp, idx)
-    say(f"[gpu] large backward: oracle for {len(idx)} sampled zones")
-    ref = ograd.vjp(sub.eps, sub.w, sub.T, sub.eta_e, sub.f, g_eta, g_chi,
-                    orates.Options(nquad=wl.nquad, rule=wl.rule))
-    return idx, ref
-
-
-@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
-def test_backward_large_full_size_sampled(precision, tol):
-    """The backward over the whole large workload in the launches the benchmark times (8 chunks
-    of 307,200 zones), upstream gradients drawn on the device; sampled zones (the min-T, max-T
-    and max-eta_e zones among them) against the oracle's reverse-mode products."""
-    wl = synth.WORKLOADS["large"]
-    idx, (rT, rE, rf) = _large_backward_reference(12)
-    inp = _full_inputs("large")
-    grid = vtx.GridHandle(inp.eps, inp.w)
-    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
-    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
-    gen = torch.Generator(device=DEV)
-    gen.manual_seed(synth.SEED_BASE + 4000)
-    ge = torch.randn(tuple(f.shape), dtype=torch.float64, device=DEV, generator=gen)
-    gc = torch.randn(tuple(f.shape), dtype=torch.float64, device=DEV, generator=gen)
-    gT = torch.empty(T.shape, dtype=torch.float64, device=DEV)
-    gE = torch.empty_like(gT)
-    gf = torch.empty_like(f)
-    bounds = np.linspace(0, T.shape[0], 9).astype(np.int64)
-    say(f"[gpu] large backward {precision}: 8 launches of {bounds[1]} zones")
-    for a, b in zip(bounds[:-1], bounds[1:]):
-        vtx.backward(grid, opts, T[a:b], E[a:b], f[a:b], ge[a:b], gc[a:b], gT[a:b], gE[a:b], gf[a:b])
-    torch.cuda.synchronize()
-    it = torch.from_numpy(idx).to(DEV)
-    got = [x.index_select(0, it).cpu().numpy() for x in (gT, gE, gf)]
-    del T, E, f, ge, gc, gT, gE, gf
-    torch.cuda.empty_cache()
-    for g in got:
-        assert np.all(np.isfinite(g))
-    eT, eE, ef = grad_err(got[0], rT).max(), grad_err(got[1], rE).max(), grad_err(got[2], rf).max()
-    say(f"    rel err g_T {eT:.2e} g_eta_e {eE:.2e} g_f {ef:.2e}")
-    assert max(eT, eE, ef) <= tol
 
 
 def test_edge_cases():
@@ -307,6 +210,83 @@ def test_autograd_function():
     assert np.array_equal(T.grad.cpu().numpy(), gT)
     assert np.array_equal(E.grad.cpu().numpy(), gE)
     assert np.array_equal(f.grad.cpu().numpy(), gf)
+
+
+def test_autograd_strided_inputs_and_options_copy():
+    """Strided (non-contiguous) T, eta_e, f pass forward and backward; changing the options
+    object between forward and backward does not change the gradient."""
+    inp = synth.make_inputs("small", nzones=4)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts("fp64", 32, "laguerre")
+    big_T = to_dev(np.stack([inp.T, inp.T + 1.0], axis=1))
+    big_E = to_dev(np.stack([inp.eta_e, inp.eta_e - 1.0], axis=1))
+    big_f = to_dev(np.concatenate([inp.f, inp.f], axis=3))
+    Ts, Es, fs = big_T[:, 0], big_E[:, 0], big_f[..., :inp.eps.shape[0]]
+    assert not Ts.is_contiguous() and not Es.is_contiguous() and not fs.is_contiguous()
+    Ts, Es, fs = (x.detach().requires_grad_(True) for x in (Ts, Es, fs))
+    ge, gc = synth.random_gradients(4, inp.eps.shape[0], 5)
+    eta, chi = vtx.rates(Ts, Es, fs, grid, opts)
+    opts.nquad = 8   # must not reach the backward
+    (eta * to_dev(ge) + chi * to_dev(gc)).sum().backward()
+    gT, gE, gf = gpu_backward(inp, ge, gc, "fp64", 32, "laguerre")
+    assert np.array_equal(Ts.grad.cpu().numpy(), gT)
+    assert np.array_equal(Es.grad.cpu().numpy(), gE)
+    assert np.array_equal(fs.grad.cpu().numpy(), gf)
+
+
+def test_nonfinite_input_stays_in_its_zone():
+    """NaN or Inf in one zone's T, eta_e or f leaves every other zone's outputs and gradients
+    bit for bit as they were (each workgroup reads only its own zone)."""
+    inp = synth.make_inputs("medium", nzones=12)
+    ge, gc = synth.random_gradients(12, inp.eps.shape[0], 21)
+    for prec in ("fp64", "mixed"):
+        e0, c0 = gpu_forward(inp, prec, 48, "panel")
+        g0 = gpu_backward(inp, ge, gc, prec, 48, "panel")
+        for field, z, val in (("T", 3, np.nan), ("eta_e", 5, np.inf), ("eta_e", 7, np.nan), ("f", 9, np.inf),
+                              ("T", 11, -np.inf)):
+            bad = synth.subset(inp, np.arange(12))
+            if field == "f":
+                bad.f[z, 1, 0, 4] = val
+            else:
+                getattr(bad, field)[z] = val
+            e, c = gpu_forward(bad, prec, 48, "panel")
+            g = gpu_backward(bad, ge, gc, prec, 48, "panel")
+            keep = np.arange(12) != z
+            assert np.array_equal(e[keep], e0[keep]) and np.array_equal(c[keep], c0[keep]), (prec, field)
+            for a, b in zip(g, g0):
+                assert np.array_equal(a[keep], b[keep]), (prec, field)
+        say(f"[gpu] non-finite inputs ({prec}): other zones unchanged")
+
+
+def test_workgroup_size_independence():
+    """The rate kernels with 8 waves per zone instead of 4 give the same outputs, gradients,
+    fused results and Jacobian blocks, bit for bit, in both precisions and every zone class."""
+    inp = synth.make_inputs("medium", nzones=10)
+    inp.eta_e[:4] = [45.0, -70.0, 12.0, 33.0]
+    ge, gc = synth.random_gradients(10, inp.eps.shape[0], 23)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    T, E, f, dge, dgc = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f), to_dev(ge), to_dev(gc)
+
+    def run(precision, processes):
+        opts = vtx.make_opts(precision, 48, "panel", processes)
+        out = list(vtx.forward(grid, opts, T, E, f)) + list(vtx.backward(grid, opts, T, E, f, dge, dgc))
+        out += list(vtx.forward_backward(grid, opts, T, E, f, dge, dgc))
+        out += list(vtx.jacobian(grid, opts, T, E, f=f))
+        torch.cuda.synchronize()
+        return [x.cpu().numpy() for x in out]
+
+    try:
+        for precision in ("fp64", "mixed"):
+            for processes in (3, 7):
+                assert vtx.set_workgroup_waves(4) in (4, 8)
+                a = run(precision, processes)
+                assert vtx.set_workgroup_waves(8) == 4
+                b = run(precision, processes)
+                for x, y in zip(a, b):
+                    assert np.array_equal(x, y), (precision, processes)
+        say("[gpu] 4 and 8 waves per zone: identical results")
+    finally:
+        vtx.set_workgroup_waves(4)
 
 
 def test_backward_largest_grid():

@@ -1,0 +1,130 @@
+"""GPU parity at the workloads' full size, against stored oracle references (needs a gfx950 GPU).
+
+The whole workload runs in the launches the benchmark times (the large one in 8 chunks of
+307,200 zones), then the stored FP64 oracle outputs (tests/golden/ref_<workload>.npz, written
+by tests/golden/make_reference.py, which calls only oracle/) are compared on their zone
+sample: 4,096 zones forward and 512 backward on the large workload, 1,024 and 128 on the
+medium one, stratified over (T, eta_e) with the corner eta_e > 30, T < 2 MeV and the extreme
+zones always included. Upstream gradients: synth.pooled_gradients (zone z takes row
+z mod 4099), gathered on the device.
+
+Errors: forward |y - y_ref| / max(|y_ref|, 1e-3 A, 1e-290) with A the sum of |terms| of y;
+backward |g - g_ref| / max(|g_ref|, 1e-3 mean |g_ref| of the field). Bars: FP64 1e-6, mixed
+1e-4, asserted over all sampled zones; the corner stratum is printed on its own.
+"""
+import functools
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1404_1719_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1404_1719_amd import vtx  # noqa: E402
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_reference  # noqa: E402
+
+DEV = "cuda:0"
+TOL = {"fp64": 1e-6, "mixed": 1e-4}
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@functools.lru_cache(maxsize=1)
+def _inputs(name):
+    say(f"[gpu] drawing the full {name} workload ({synth.WORKLOADS[name].nzones} zones)")
+    return synth.make_inputs(name)
+
+
+@functools.lru_cache(maxsize=2)
+def _ref(name):
+    return make_reference.load(name)
+
+
+def _chunks(nz, n):
+    b = np.linspace(0, nz, n + 1).astype(np.int64)
+    return [(int(x), int(y)) for x, y in zip(b[:-1], b[1:]) if y > x]
+
+
+def fwd_err(y, r, a):
+    return np.abs(y - r) / np.maximum(np.maximum(np.abs(r), 1e-3 * a.astype(np.float64)), 1e-290)
+
+
+def grad_err(g, r):
+    return np.abs(g - r) / np.maximum(np.abs(r), 1e-3 * np.mean(np.abs(r)) + 1e-300)
+
+
+def corner(inp, idx):
+    return (inp.eta_e[idx] > 30.0) & (inp.T[idx] < 2.0)
+
+
+@pytest.mark.parametrize("name", ["large", "medium"])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_forward_full_size_stored_reference(name, precision):
+    wl = synth.WORKLOADS[name]
+    inp, ref = _inputs(name), _ref(name)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+    T, E, f = (torch.from_numpy(a).to(DEV) for a in (inp.T, inp.eta_e, inp.f))
+    eta, chi = torch.empty_like(f), torch.empty_like(f)
+    chunks = _chunks(T.shape[0], wl.chunks)
+    say(f"[gpu] {name} {precision} forward: {len(chunks)} launches over {T.shape[0]} zones; "
+        f"{ref['idx'].size} stored zones")
+    for a, b in chunks:
+        vtx.forward(grid, opts, T[a:b], E[a:b], f[a:b], eta[a:b], chi[a:b])
+    torch.cuda.synchronize()
+    it = torch.from_numpy(ref["idx"]).to(DEV)
+    e, c = eta.index_select(0, it).cpu().numpy(), chi.index_select(0, it).cpu().numpy()
+    del T, E, f, eta, chi
+    torch.cuda.empty_cache()
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(c))
+    errs = {"eta0": fwd_err(e[:, :, 0], ref["eta"][:, :, 0], ref["a_eta"][:, :, 0]),
+            "eta1": fwd_err(e[:, :, 1], ref["eta"][:, :, 1], ref["a_eta"][:, :, 1]),
+            "chi0": fwd_err(c[:, :, 0], ref["chi"][:, :, 0], ref["a_chi"][:, :, 0]),
+            "chi1": fwd_err(c[:, :, 1], ref["chi"][:, :, 1], ref["a_chi"][:, :, 1])}
+    cz = corner(inp, ref["idx"])
+    say("    max rel err " + " ".join(f"{k} {v.max():.2e}" for k, v in errs.items()) +
+        f"; corner ({int(cz.sum())} zones) " + " ".join(f"{k} {v[cz].max(initial=0):.2e}" for k, v in errs.items()))
+    assert max(v.max() for v in errs.values()) <= TOL[precision]
+
+
+@pytest.mark.parametrize("name", ["large", "medium"])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_backward_full_size_stored_reference(name, precision):
+    wl = synth.WORKLOADS[name]
+    inp, ref = _inputs(name), _ref(name)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+    nz = inp.T.shape[0]
+    T, E, f = (torch.from_numpy(a).to(DEV) for a in (inp.T, inp.eta_e, inp.f))
+    pe, pc = (torch.from_numpy(a).to(DEV) for a in synth.gradient_pool(wl.ne, int(ref["grad_seed"])))
+    rows = torch.arange(nz, device=DEV) % pe.shape[0]
+    ge, gc = pe.index_select(0, rows), pc.index_select(0, rows)
+    del rows
+    gT, gE, gf = torch.empty_like(T), torch.empty_like(T), torch.empty_like(f)
+    chunks = _chunks(nz, wl.chunks)
+    say(f"[gpu] {name} {precision} backward: {len(chunks)} launches; {ref['idx_b'].size} stored zones")
+    for a, b in chunks:
+        vtx.backward(grid, opts, T[a:b], E[a:b], f[a:b], ge[a:b], gc[a:b], gT[a:b], gE[a:b], gf[a:b])
+    torch.cuda.synchronize()
+    it = torch.from_numpy(ref["idx_b"]).to(DEV)
+    got = [x.index_select(0, it).cpu().numpy() for x in (gT, gE, gf)]
+    del T, E, f, ge, gc, gT, gE, gf, pe, pc
+    torch.cuda.empty_cache()
+    errs = {k: grad_err(g, ref[k]) for k, g in zip(("g_T", "g_eta_e", "g_f"), got)}
+    for g in got:
+        assert np.all(np.isfinite(g))
+    cz = corner(inp, ref["idx_b"])
+    say("    max rel err " + " ".join(f"{k} {v.max():.2e}" for k, v in errs.items()) +
+        f"; corner ({int(cz.sum())} zones) " + " ".join(f"{k} {v[cz].max(initial=0):.2e}" for k, v in errs.items()))
+    assert max(v.max() for v in errs.values()) <= TOL[precision]

@@ -205,3 +205,28 @@ def test_short_interval_route_slips(monkeypatch):
     monkeypatch.setattr(ang, "_nes_direct", bad)
     e, ep, E = pins_ang.CASES_NES_SHORT[0]
     assert _brute_fails(1, 1, e, ep, E, ang.h_nes, pins_ang.brute_nes_avg, 1.0)
+
+
+def test_newton_source_jacobian_slips(monkeypatch):
+    """The source's derivative without the factor 3 of the f1 coupling, or with the blocks of the
+    pair's partner species taken from the species itself, must fail the finite-difference pin."""
+    import oracle.newton as onewton
+    import test_oracle_newton as pins_newton
+    orig = onewton.source_jacobian
+
+    def no_three(jac, f, eta, chi):
+        dS = orig(jac, f, eta, chi)
+        nz, B = dS.shape[0], dS.shape[1]
+        ne = B // 6
+        d = dS.reshape(nz, 3, 2, ne, 3, 2, ne)
+        for s in range(3):
+            for i in range(ne):
+                d[:, s, 0, i, s, 1, i] += 2.0 / 3.0 * 3.0 * chi[:, s, 1, i]   # -3 chi1 -> -chi1
+        return d.reshape(nz, B, B)
+    monkeypatch.setattr(onewton, "source_jacobian", no_three)
+    with pytest.raises(AssertionError):
+        pins_newton.test_diagonal_blocks_are_the_residual_derivative()
+    monkeypatch.setattr(onewton, "SOURCE", ((0, 1, 2), (0, 1, 2)))
+    monkeypatch.setattr(onewton, "source_jacobian", orig)
+    with pytest.raises(AssertionError):
+        pins_newton.test_source_jacobian_from_the_rates_blocks()
