@@ -146,12 +146,24 @@ def stored_errors(inp, run, ref, stratum=None):
         return np.abs(g - r) / np.maximum(np.abs(r), 1e-3 * np.mean(np.abs(r)) + 1e-300)
 
     e, c = pick(run.eta, idx), pick(run.chi, idx)
-    f = {"eta0": ferr(e[:, :, 0], ref["eta"][:, :, 0], ref["a_eta"][:, :, 0]),
-         "eta1": ferr(e[:, :, 1], ref["eta"][:, :, 1], ref["a_eta"][:, :, 1]),
-         "chi0": ferr(c[:, :, 0], ref["chi"][:, :, 0], ref["a_chi"][:, :, 0]),
-         "chi1": ferr(c[:, :, 1], ref["chi"][:, :, 1], ref["a_chi"][:, :, 1])}
+
+    def forward_errors(scale):
+        return {"eta0": ferr(e[:, :, 0], ref["eta"][:, :, 0], ref[scale + "_eta"][:, :, 0]),
+                "eta1": ferr(e[:, :, 1], ref["eta"][:, :, 1], ref[scale + "_eta"][:, :, 1]),
+                "chi0": ferr(c[:, :, 0], ref["chi"][:, :, 0], ref[scale + "_chi"][:, :, 0]),
+                "chi1": ferr(c[:, :, 1], ref["chi"][:, :, 1], ref[scale + "_chi"][:, :, 1])}
+
+    # the mixed path's bar uses the quadrature-level scale Aq, the FP64 path's the output level A
+    f = forward_errors("aq" if run.precision == "mixed" else "a")
+    fa = forward_errors("a")
     g = {k: gerr(pick(t, idx_b), ref[k]) for k, t in (("g_T", run.gT), ("g_eta_e", run.gE), ("g_f", run.gf))}
     out = {k: float(v.max()) for k, v in {**f, **g}.items()}
+    out["floor"] = "1e-3 Aq (sum of |terms| with |H| kernels)" if run.precision == "mixed" else "1e-3 A"
+    if run.precision == "mixed":
+        n_all = sum(v.size for v in fa.values())
+        out["output_level_floor"] = {**{k: float(v.max()) for k, v in fa.items()},
+                                     "entries_above_1e-4": sum(int((v > 1e-4).sum()) for v in fa.values()),
+                                     "entries": n_all}
     out["zones_forward"], out["zones_backward"] = int(idx.size), int(idx_b.size)
     if stratum is not None:
         sf, sb = stratum(inp.T[idx], inp.eta_e[idx]), stratum(inp.T[idx_b], inp.eta_e[idx_b])
@@ -175,6 +187,7 @@ class Runner:
         self.torch, self.vtx = torch, vtx
         dev = torch.device("cuda:0")
         self.grid = vtx.GridHandle(inp.eps, inp.w)
+        self.precision = precision
         self.opts = vtx.make_opts(precision, wl.nquad, wl.rule, processes, eta_fp64=eta_fp64)
         self.nz, self.ne = inp.T.shape[0], wl.ne
         self.T = torch.from_numpy(inp.T).to(dev)
@@ -335,6 +348,62 @@ def jacobian_leg(inp, wl, precision, launches):
             "hbm_frac": written / (t * 1e-3) / 8e12, "traffic": traffic_from_profiles(tag), "kernel": tag}
 
 
+def newton_leg(inp, wl, precision, nrays):
+    """Newton step of the radial sweep over nrays rays x the workload's radial zones (one chunk's
+    worth of the first zones): the rates and their explicit blocks (vtx_rates_jacobian), the
+    system (vtx_ray_system) and the block-tridiagonal solve (vtx_ray_solve), each timed with HIP
+    events on its stream. Time step and radial coupling on the rates' scale (dt = 1/kappa,
+    lo, up ~ kappa U(0, 1/2), kappa the median opacity). Algorithmic work of the solve: per zone
+    one Gauss-Jordan inversion of a 6 NE block (2 nb^3 flop) and three block-vector products
+    (6 nb^2); the system writes nb^2 + nb doubles per zone and reads the 24 NE^2 of the blocks."""
+    import torch
+    from paper_1404_1719_amd import vtx
+    nzr = wl.radial
+    nz = nrays * nzr
+    ne, nb = wl.ne, 6 * wl.ne
+    dev = torch.device("cuda:0")
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts(precision, wl.nquad, wl.rule)
+    T = torch.from_numpy(inp.T[:nz]).to(dev)
+    E = torch.from_numpy(inp.eta_e[:nz]).to(dev)
+    f = torch.from_numpy(inp.f[:nz]).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(synth.SEED_BASE + 6000)
+    f_n = (f * (1 + 0.01 * torch.randn(f.shape, dtype=torch.float64, device=dev, generator=g))).clamp(0, 1)
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    with torch.cuda.stream(s):
+        ev[0].record(s)
+        jac, eta, chi = vtx.jacobian(grid, opts, T, E, stream=s, f=f)
+        ev[1].record(s)
+        kappa = torch.median(chi[:, :, 0])
+        lo = kappa * 0.5 * torch.rand((nz, nb), dtype=torch.float64, device=dev, generator=g)
+        up = kappa * 0.5 * torch.rand((nz, nb), dtype=torch.float64, device=dev, generator=g)
+        dt = 1.0 / float(kappa.item())
+        D, rhs = vtx.ray_system(ne, nrays, nzr, dt, jac, f, f_n, f_n, eta, chi, lo, up, stream=s)
+        ev[2].record(s)
+        vtx.ray_solve(nrays, nzr, lo, D, up, rhs, stream=s)
+        ev[3].record(s)
+    s.synchronize()
+    finite = bool(torch.isfinite(rhs).all().item())
+    t_rates, t_sys, t_solve = (ev[k].elapsed_time(ev[k + 1]) for k in range(3))
+    flops = nz * (2.0 * nb ** 3 + 6.0 * nb ** 2)
+    sys_bytes = nz * 8.0 * (nb * nb + nb + 24 * ne * ne + 10 * nb)
+    solve_bytes = nz * 8.0 * (3 * nb * nb + 6 * nb)
+    out = {"rays": nrays, "zones_per_ray": nzr, "block": nb, "rates_and_blocks_ms": t_rates,
+           "system_ms": t_sys, "system_GBps": sys_bytes / (t_sys * 1e-3) / 1e9,
+           "solve_ms": t_solve, "solve_TFLOPs": flops / (t_solve * 1e-3) / 1e12,
+           "solve_frac_fp64_peak": flops / (t_solve * 1e-3) / 78.6e12,
+           "solve_GBps": solve_bytes / (t_solve * 1e-3) / 1e9, "solution_finite": finite,
+           "note": "one Newton update of the BDF2 radial system along each ray; solve = block "
+                   "elimination with Gauss-Jordan inversion of each diagonal block in LDS, one ray per "
+                   "workgroup"}
+    del jac, eta, chi, D, rhs, lo, up, T, E, f, f_n
+    torch.cuda.empty_cache()
+    return out
+
+
 def tabulated_leg(inp, wl, precision, launches, t_direct_ms, ref):
     """Tabulated comparison point: task values on a (ln T, eta_e) lattice over the workload's
     range (built by the library), interpolated per zone over one chunk, against the direct
@@ -450,6 +519,8 @@ def main():
                     help="timed launches of the tabulated comparison over one chunk (0: skip)")
     ap.add_argument("--positron-steps", type=int, default=2,
                     help="steps of the run with neutrino-positron scattering added (0: skip)")
+    ap.add_argument("--newton-rays", type=int, default=256,
+                    help="rays of the Newton-step leg (radial zones of the workload each; 0: skip)")
     ap.add_argument("--jacobian-launches", type=int, default=3,
                     help="timed launches of the explicit Jacobian over one chunk (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -546,6 +617,11 @@ def main():
         print(f"[bench] explicit Jacobian: {args.jacobian_launches} launches", file=sys.stderr, flush=True)
         jac = jacobian_leg(inp, wl, precision, args.jacobian_launches)
 
+    newton = None
+    if args.newton_rays > 0:
+        print(f"[bench] Newton step of the radial sweep: {args.newton_rays} rays", file=sys.stderr, flush=True)
+        newton = newton_leg(inp, wl, precision, args.newton_rays)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -565,7 +641,7 @@ def main():
                    "streaming": "value: inputs resident in HBM; end_to_end_streamed: host memory, "
                                 f"{wl.chunks} stream-overlapped chunks, PCIe included"},
         "rel_err_vs_oracle": errors, "fp64": fp64, "roofline": roof, "cpu_baseline": cpu,
-        "end_to_end_streamed": streaming, "threshold_64": thr64, "jacobian": jac,
+        "end_to_end_streamed": streaming, "threshold_64": thr64, "jacobian": jac, "newton_step": newton,
         "with_positron_scattering": positron, "fused_forward_backward": fused, "tabulated": tabulated,
     }
     print(json.dumps(line), flush=True)

@@ -71,11 +71,10 @@ enum vtx_precision {
   VTX_MIXED = 1   /* FP32 quadrature bulk (node coordinates, Fermi-Dirac factors, angular-weight
                      moments and their accumulation); FP64 angular-weight contraction,
                      detailed-balance factors and the per-zone contraction. Zones with
-                     |eta_e| > eta_fp64 take their Fermi-Dirac factors in FP64 (FP32 moments).
-                     Zones with |eta_e| > 64 run entirely in FP64, whatever eta_fp64: a task's
-                     whole integrand can then sit near exp(-|eta_e|), and FP32 ends near
-                     exp(-87). The zones of each class are computed by their own pass over the
-                     call's zones */
+                     |eta_e| > eta_fp64 run entirely in FP64, their Fermi-Dirac factors among
+                     the rest; the threshold is capped at 64, where a task's whole integrand can
+                     sit near exp(-|eta_e|) and FP32 ends near exp(-87). Each class of zones is
+                     computed by its own pass over the call's zones */
 };
 
 enum vtx_rule { VTX_RULE_LAGUERRE = 0, VTX_RULE_PANEL = 1 };
@@ -99,8 +98,8 @@ typedef struct {
   int32_t rule;        /* vtx_rule */
   uint32_t processes;  /* bitmask of vtx_process, nonzero (default VTX_NES | VTX_PAIR) */
   double sin2w;        /* weak mixing angle sin^2(theta_W), default 0.2312 */
-  double eta_fp64;     /* mixed precision: zones with |eta_e| > eta_fp64 take FP64 Fermi-Dirac
-                          factors (default 30) */
+  double eta_fp64;     /* mixed precision: zones with |eta_e| > min(eta_fp64, 64) run in FP64,
+                          Fermi-Dirac factors included (default 30) */
 } vtx_opts;
 
 /* Fill *opts with the defaults: FP64, 48 nodes, PANEL, both processes, 0.2312, 30. */
@@ -227,7 +226,7 @@ int vtx_rates_forward_interp(const vtx_grid* grid, const vtx_opts* opts, const v
  *   blocks D [nz][nb][nb] (row = (species, moment, bin) of G, column = that of F) and
  *   rhs = -G [nz][nb]. dt > 0. All device memory; D and rhs are overwritten.
  * vtx_ray_solve: solves -diag(lo_r) x_{r-1} + D_r x_r - diag(up_r) x_{r+1} = rhs_r along each ray
- *   (any nb x nb blocks, 1 <= nb <= vtx_ray_max_block(), 142), in place: rhs becomes x, and D
+ *   (any nb x nb blocks, 1 <= nb <= vtx_ray_max_block(), 140), in place: rhs becomes x, and D
  *   is overwritten by the inverses of the eliminated diagonal blocks; nothing else is allocated.
  *   One ray per workgroup, Gauss-Jordan elimination with partial pivoting in FP64. A singular
  *   block gives non-finite x on its ray. The Newton update is F += x with rhs = -G.

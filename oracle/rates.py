@@ -342,14 +342,21 @@ def forward(eps, w, T, eta_e, f, opts=Options(), chunk=32):
     return np.concatenate(outs_e), np.concatenate(outs_c)
 
 
-def forward_with_scale(eps, w, T, eta_e, f, opts=Options(), chunk=32):
-    """(eta, chi, A_eta, A_chi): outputs plus their sums of absolute terms."""
-    res = [[], [], [], []]
+def forward_with_scale(eps, w, T, eta_e, f, opts=Options(), chunk=32, quadrature=False):
+    """(eta, chi, A_eta, A_chi): outputs plus their sums of absolute terms. With ``quadrature``
+    also (Aq_eta, Aq_chi): the same sums with every kernel replaced by its absolute quadrature
+    (|H| in the integrand), the scale of the rounding of a quadrature whose angular weight
+    changes sign (l = 1); for l = 0 (H >= 0) it equals A."""
+    res = [[], [], [], [], [], []]
     for z0 in range(0, len(T), chunk):
         sl = slice(z0, z0 + chunk)
         k = zone_kernels(eps, np.asarray(T)[sl], np.asarray(eta_e)[sl], opts)
         e, c = contract(k, w, f[sl], opts)
         ae, ac = contract_abs(k, w, f[sl], opts)
-        for lst, v in zip(res, (e, c, ae, ac)):
+        vals = [e, c, ae, ac]
+        if quadrature:
+            kq = zone_kernels(eps, np.asarray(T)[sl], np.asarray(eta_e)[sl], opts, absolute=True)
+            vals += list(contract_abs(kq, w, f[sl], opts))
+        for lst, v in zip(res, vals):
             lst.append(v)
-    return tuple(np.concatenate(r) for r in res)
+    return tuple(np.concatenate(r) for r in res if r)

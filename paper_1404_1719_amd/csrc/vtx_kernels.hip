@@ -15,8 +15,8 @@
 //
 // Mixed precision runs the bulk in FP32 (node coordinates, Fermi-Dirac factors, angular-weight
 // moments and their accumulation) with FP64 contractions and detailed-balance factors; zones
-// with |eta_e| above a threshold take their Fermi-Dirac factors in FP64 (a second pass over
-// the zones with the same node loops, the blocking factor from one FP64 exponential).
+// with |eta_e| above a threshold run in FP64 (a second pass over the zones with the FP64 node
+// loops, whose blocking factor takes one FP64 exponential).
 #include <hip/hip_runtime.h>
 
 #include "../../include/vtx_rates.h"
@@ -86,15 +86,11 @@ __device__ __forceinline__ double recip_pos(double x) {
 
 // Precision of a kernel: R, the bulk type (piece variable, node weights, angular-weight moments
 // and their accumulation), and F, the type of the Fermi-Dirac arguments and blocking factors.
-// The mixed path runs Fp32 on zones of moderate degeneracy and Fd64 (Fermi-Dirac factors in
-// FP64, the rest as Fp32) on zones with |eta_e| above its threshold; the FP64 path runs Fp64.
+// The mixed path runs Fp32 on zones of moderate degeneracy and Fp64 on zones with |eta_e| above
+// its threshold; the FP64 path runs Fp64 throughout.
 struct Fp32 {
   using R = float;
-  using F = float;
-};
-struct Fd64 {
-  using R = float;
-  using F = double;
+  using F = float;   // the policies keep the two types apart; both use one type throughout
 };
 struct Fp64 {
   using R = double;
@@ -177,9 +173,8 @@ struct Zone {
   int k;       // #{eps_j < mu_e}: selects the task order
 };
 
-// Node tables of a kernel in LDS: the bulk type's (piece variable, weights) and, where the
-// Fermi-Dirac type differs, a second one in that type for the Fermi-Dirac arguments. Both
-// have the same layout, so a map's offset serves either.
+// Node table of a kernel in LDS, in the kernel's type (piece variable, weights, Fermi-Dirac
+// arguments).
 __device__ __forceinline__ void fill_tab(const DevPlan& P, double* tab) {
   for (int k = threadIdx.x; k < P.m4; k += blockDim.x) {
     const double4 n = P.leg64[k];
@@ -209,32 +204,24 @@ __device__ __forceinline__ void fill_tab(const DevPlan& P, float* tab) {
   }
 }
 
+// The node table as read by the piece variable and weights (r) and by the Fermi-Dirac
+// arguments (f): one table in LDS, in the kernel's type.
 template <typename Pr>
 struct Tabs {
-  const typename Pr::R* r;   // piece variable, weights, end weights
-  const typename Pr::F* f;   // Fermi-Dirac arguments
+  const typename Pr::R* r;
+  const typename Pr::F* f;
 };
 
-// LDS bytes of a kernel's node tables.
 template <typename Pr>
 constexpr int tab_bytes() {
-  return kTabLen * (int)(sizeof(typename Pr::R) +
-                         (sizeof(typename Pr::R) == sizeof(typename Pr::F) ? 0 : sizeof(typename Pr::F)));
+  return kTabLen * (int)sizeof(typename Pr::R);
 }
 
 template <typename Pr>
 __device__ __forceinline__ Tabs<Pr> stage_tabs(const DevPlan& P, double* raw) {
-  using R = typename Pr::R;
-  using F = typename Pr::F;
-  R* tr = reinterpret_cast<R*>(raw);
-  fill_tab(P, tr);
-  if constexpr (sizeof(R) == sizeof(F)) {
-    return {tr, reinterpret_cast<const F*>(tr)};
-  } else {
-    F* tf = reinterpret_cast<F*>(raw + (kTabLen * sizeof(R) + 7) / 8);
-    fill_tab(P, tf);
-    return {tr, tf};
-  }
+  typename Pr::R* t = reinterpret_cast<typename Pr::R*>(raw);
+  fill_tab(P, t);
+  return {t, t};
 }
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
@@ -657,21 +644,16 @@ __device__ __forceinline__ Q4 task_forward(const DevPlan& P, const Tabs<Pr>& tb,
 // [12 ne] after f.
 
 // Zone selection of a pass. The FP64 path takes every zone. The mixed path splits them into
-// three classes by |eta_e|: up to its threshold (and values that do not compare) FP32
-// throughout; above it FP64 Fermi-Dirac factors with FP32 moments; above kFp32Range entirely
-// FP64. The last guards range, not accuracy: a task's whole integrand can sit near e^-|eta_e|
-// (pair annihilation with mu_e above eps_i + eps_j), and FP32 moments end near e^-87.
-constexpr int kSelAll = 0, kSelBulk = 1, kSelFd = 2, kSelHigh = 3;
+// two classes by |eta_e|: up to its threshold (and values that do not compare) FP32, above it
+// FP64. The threshold is capped at kFp32Range, which guards range, not accuracy: a task's whole
+// integrand can sit near e^-|eta_e| (pair annihilation with mu_e above eps_i + eps_j), and FP32
+// ends near e^-87.
+constexpr int kSelAll = 0, kSelBulk = 1, kSelHigh = 2;
 constexpr double kFp32Range = 64.0;
 
 __device__ __forceinline__ bool selected(const DevPlan& P, int selm, double eta) {
-  const double a = fabs(eta), lo = fmin(P.eta_fp64, kFp32Range);
-  switch (selm) {
-    case kSelBulk: return !(a > lo);
-    case kSelFd: return a > lo && a <= kFp32Range;
-    case kSelHigh: return a > kFp32Range;
-    default: return true;
-  }
+  const bool high = fabs(eta) > fmin(P.eta_fp64, kFp32Range);
+  return selm == kSelBulk ? !high : (selm == kSelHigh ? high : true);
 }
 
 __device__ void stage_zone_state(const DevPlan& P, int64_t z, const double* Tz, const double* etaz,
@@ -1035,12 +1017,11 @@ __device__ void zone_forward(const DevPlan& P, const Tabs<Pr>& tb, Zone* zs, dou
 
 // Workgroup b takes zone b, if the pass selects it. Occupancy targets (waves per SIMD): Fp32
 // five (at most 102 VGPRs; five one-zone workgroups of 31 KB fill the 160 KB of LDS at 21
-// bins), Fd64 and Fp64 three (four would spill); the FP64 export of task values for tables
+// bins), Fp64 three (four would spill); the FP64 export of task values for tables
 // (built once per lattice) two, where three would spill.
 template <typename Pr, int OUT>
 constexpr int fwd_waves() {
-  return sizeof(typename Pr::R) == 8 ? ((OUT == kOutTasks || OUT == kOutTable) ? 2 : 3)
-                                     : (sizeof(typename Pr::F) == 8 ? 3 : 5);
+  return sizeof(typename Pr::R) == 8 ? ((OUT == kOutTasks || OUT == kOutTable) ? 2 : 3) : 5;
 }
 
 template <typename Pr, int OUT, bool NPS>
@@ -1342,23 +1323,14 @@ __device__ __forceinline__ void node_bwd(const Loop<Pr>& L, const AdjPoly<typena
   S[6] = N::fma(yu, pb, S[6]);
 }
 
-// Nodes in flight per lane: two, or four for FP64 Fermi-Dirac factors with FP32 moments, whose
-// two-wave register budget holds them (the others would spill).
 template <typename Pr, int MODE>
 __device__ __forceinline__ void nodes_bwd(const Loop<Pr>& L, const AdjPoly<typename Pr::R>& Q, int m,
                                           const Tabs<Pr>& tb, typename Pr::R M[5], typename Pr::R H[3],
                                           typename Pr::R S[7]) {
-  if constexpr (sizeof(typename Pr::R) == 4 && sizeof(typename Pr::F) == 8) {
-#pragma unroll 4
-    for (int k = 0; k < m; ++k)
-      node_bwd<Pr, MODE>(L, Q, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], tb.r[L.oa + k],
-                         tb.r[L.ob + k], M, H, S);
-  } else {
 #pragma unroll 2
-    for (int k = 0; k < m; ++k)
-      node_bwd<Pr, MODE>(L, Q, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], tb.r[L.oa + k],
-                         tb.r[L.ob + k], M, H, S);
-  }
+  for (int k = 0; k < m; ++k)
+    node_bwd<Pr, MODE>(L, Q, tb.r[L.ou + k], tb.f[L.o1 + k], tb.f[L.o2 + k], tb.r[L.ow + k], tb.r[L.oa + k],
+                       tb.r[L.ob + k], M, H, S);
 }
 
 template <typename Pr>
@@ -1707,11 +1679,11 @@ __device__ void zone_backward(const DevPlan& P, const Tabs<Pr>& tb, Zone* zs, do
   }
 }
 
-// Occupancy targets (waves per SIMD): three for the Fp32 and Fd64 backward (at most 168
+// Occupancy targets (waves per SIMD): three for the Fp32 backward (at most 168
 // VGPRs), two for the Fp64 one.
 template <typename Pr>
 constexpr int bwd_waves() {
-  return sizeof(typename Pr::F) == 8 ? 2 : 3;
+  return sizeof(typename Pr::R) == 8 ? 2 : 3;
 }
 
 template <typename Pr, bool NPS, bool FUSED>
@@ -1775,15 +1747,14 @@ hipError_t forward_pass(const DevPlan& P, int64_t nz, int selm, const double* T,
   return hipGetLastError();
 }
 
-// The mixed path runs three dense passes over the zones, one per class (see selected()); each
-// workgroup of a pass leaves at once when its zone belongs to another. The FP64 path is one
+// The mixed path runs two dense passes over the zones, one per class (see selected()); each
+// workgroup of a pass leaves at once when its zone belongs to the other. The FP64 path is one
 // pass.
 template <bool NPS>
 hipError_t forward_slice_t(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
                            double* eta, double* chi, double* jac, int out, hipStream_t s) {
   if (P.precision == VTX_MIXED) {
     hipError_t e = forward_pass<Fp32, NPS>(P, nz, kSelBulk, T, eta_e, f, eta, chi, jac, out, s);
-    if (e == hipSuccess) e = forward_pass<Fd64, NPS>(P, nz, kSelFd, T, eta_e, f, eta, chi, jac, out, s);
     if (e == hipSuccess) e = forward_pass<Fp64, NPS>(P, nz, kSelHigh, T, eta_e, f, eta, chi, jac, out, s);
     return e;
   }
@@ -1828,8 +1799,6 @@ hipError_t backward_slice_t(const DevPlan& P, int64_t nz, const double* T, const
   if (P.precision == VTX_MIXED) {
     hipError_t e = backward_pass<Fp32, NPS, FUSED>(P, nz, kSelBulk, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f,
                                                    eta, chi, s);
-    if (e == hipSuccess)
-      e = backward_pass<Fd64, NPS, FUSED>(P, nz, kSelFd, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s);
     if (e == hipSuccess)
       e = backward_pass<Fp64, NPS, FUSED>(P, nz, kSelHigh, T, eta_e, f, g_eta, g_chi, g_T, g_eta_e, g_f, eta, chi, s);
     return e;

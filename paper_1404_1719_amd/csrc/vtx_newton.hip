@@ -178,7 +178,7 @@ __device__ __forceinline__ void matvec(const double* A, const double* w, const d
   }
 }
 
-constexpr int kMaxNb = 142;   // nb^2 + 4 nb doubles of LDS within 160 KB
+constexpr int kMaxNb = 140;   // nb^2 + 4 nb doubles and the pivot rows within the 160 KiB of LDS
 
 __global__ __launch_bounds__(kNBlock) void ray_solve_kernel(int nb, int64_t nrays, int nzr,
                                                             const double* __restrict__ lo, double* __restrict__ D,

@@ -8,9 +8,11 @@ rest spread over an 8 x 8 grid), forward on the whole sample and backward on a s
 sub-sample, with the upstream gradients of synth.pooled_gradients (zone z takes pool row
 z mod 4099, so a full-size run draws them by a gather on the device).
 
-Stored: idx, the zones' T and eta_e, eta, chi (float64) and the absolute scales A_eta, A_chi
-of the relative-error floor (float32); idx_b, g_T, g_eta_e, g_f (float64); and a hash of the
-oracle's and the sampler's sources, which the CPU tests compare with the current files.
+Stored: idx, the zones' T and eta_e, eta, chi (float64) and the absolute scales of the
+relative-error floor (float32): A_eta, A_chi, the sums of the absolute values of each output's
+terms, and Aq_eta, Aq_chi, the same with every kernel taken as its absolute quadrature (|H|);
+idx_b, g_T, g_eta_e, g_f (float64); and a hash of the oracle's and the sampler's sources, which
+the CPU tests compare with the current files.
 
 Calls only oracle/ and the seeded input generators. Usage (about ten minutes on 8 cores):
     python tests/golden/make_reference.py [--workers 8] [--only large]
@@ -36,12 +38,15 @@ GRAD_SEED = 7
 SAMPLE_SEED = 0
 
 
+# the oracle modules the stored values come from, and the input generator
+SOURCES = ("oracle/angular.py", "oracle/grad.py", "oracle/physics.py", "oracle/rates.py", "oracle/rule.py",
+           "paper_1404_1719_amd/synth.py")
+
+
 def source_hash():
-    """sha256 over the oracle's sources and the input generator (sampling, gradients)."""
+    """sha256 over the sources the stored values depend on (oracle modules, input generator)."""
     h = hashlib.sha256()
-    files = sorted(os.path.join(ROOT, "oracle", f) for f in os.listdir(os.path.join(ROOT, "oracle"))
-                   if f.endswith(".py"))
-    files.append(os.path.join(ROOT, "paper_1404_1719_amd", "synth.py"))
+    files = [os.path.join(ROOT, f) for f in SOURCES]
     for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
@@ -62,7 +67,7 @@ def samples(inp, nf, nb):
 def _fwd(args):
     from oracle import rates as orates
     eps, w, T, E, f, nquad, rule = args
-    return orates.forward_with_scale(eps, w, T, E, f, orates.Options(nquad=nquad, rule=rule))
+    return orates.forward_with_scale(eps, w, T, E, f, orates.Options(nquad=nquad, rule=rule), quadrature=True)
 
 
 def _bwd(args):
@@ -90,11 +95,11 @@ def make(name, workers):
         bw = ex.map(_bwd, [(sub_b.eps, sub_b.w, sub_b.T[p], sub_b.eta_e[p], sub_b.f[p], ge[p], gc[p], wl.nquad,
                             wl.rule) for p in pieces_b])
         fw, bw = list(fw), list(bw)
-    eta, chi, ae, ac = (np.concatenate([r[k] for r in fw]) for k in range(4))
+    eta, chi, ae, ac, qe, qc = (np.concatenate([r[k] for r in fw]) for k in range(6))
     gT, gE, gf = (np.concatenate([r[k] for r in bw]) for k in range(3))
     np.savez_compressed(path(name), workload=name, source_hash=source_hash(), grad_seed=GRAD_SEED,
                         idx=idx, T=sub.T, eta_e=sub.eta_e, eta=eta, chi=chi, a_eta=ae.astype(np.float32),
-                        a_chi=ac.astype(np.float32),
+                        a_chi=ac.astype(np.float32), aq_eta=qe.astype(np.float32), aq_chi=qc.astype(np.float32),
                         idx_b=idx_b, g_T=gT, g_eta_e=gE, g_f=gf)
     print(f"[ref] {name}: written {path(name)} ({os.path.getsize(path(name)) / 1e6:.1f} MB, "
           f"{time.time() - t0:.0f} s)", flush=True)

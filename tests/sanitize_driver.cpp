@@ -44,7 +44,7 @@ hipError_t launch_ray_system(int, int64_t, int, double, const double*, const dou
 hipError_t launch_ray_solve(int, int64_t, int, const double*, double*, const double*, double*, hipStream_t) {
   unreachable("ray_solve");
 }
-int max_block() { return 142; }
+int max_block() { return 140; }
 }  // namespace vtx
 
 static int failures = 0;
@@ -136,10 +136,10 @@ int main() {
   EXPECT(vtx_ray_system(4, 1, 1, -1.0, d, d, d, d, d, d, d, d, d, d, nullptr) == VTX_EINVAL);
   EXPECT(vtx_ray_system(4, 0, 1, 1.0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                         nullptr, nullptr, nullptr) == VTX_OK);
-  EXPECT(vtx_ray_solve(143, 1, 1, d, d, d, d, nullptr) == VTX_EINVAL);
+  EXPECT(vtx_ray_solve(141, 1, 1, d, d, d, d, nullptr) == VTX_EINVAL);
   EXPECT(vtx_ray_solve(4, 1, 0, d, d, d, d, nullptr) == VTX_EINVAL);
   EXPECT(vtx_ray_solve(4, 1, 1, nullptr, d, d, d, nullptr) == VTX_EINVAL);
-  EXPECT(vtx_ray_max_block() == 142);
+  EXPECT(vtx_ray_max_block() == 140);
   for (int code = -1; code < 6; ++code) EXPECT(vtx_strerror(code) != nullptr);
   EXPECT(vtx_abi_version() == VTX_ABI_VERSION);
   vtx_release();

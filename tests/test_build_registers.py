@@ -8,10 +8,8 @@ device code with the library's own flags and reads the code-object metadata:
 
 * no kernel uses scratch (private segment) or spills VGPRs;
 * the FP32 forward and interpolation kernels fit five waves per SIMD (at most 96 VGPRs);
-* the FP32 backward, the forward with FP64 Fermi-Dirac factors and the FP64 forward fit three
-  (at most 168);
-* the backward with FP64 Fermi-Dirac factors, the FP64 backward and the FP64 export of task
-  values for tables fit two (at most 256).
+* the FP32 backward and the FP64 forward fit three (at most 168);
+* the FP64 backward and the FP64 export of task values for tables fit two (at most 256).
 """
 import os
 import re
@@ -29,10 +27,8 @@ BUDGET = [
     (r"rates_forward_kernelINS0_4Fp32", 96),
     (r"rates_interp_kernel", 96),
     (r"rates_backward_kernelINS0_4Fp32", 168),
-    (r"rates_forward_kernelINS0_4Fd64", 168),
     (r"rates_forward_kernelINS0_4Fp64ELi[01]E", 168),
     (r"rates_forward_kernelINS0_4Fp64ELi[23]E", 256),
-    (r"rates_backward_kernelINS0_4Fd64", 256),
     (r"rates_backward_kernelINS0_4Fp64", 256),
 ]
 

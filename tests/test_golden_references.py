@@ -30,8 +30,13 @@ def test_reference_is_current_and_whole(name):
     assert idx.shape == (nf,) and idx_b.shape == (nb,)
     assert np.all(np.diff(idx) > 0) and np.all(np.isin(idx_b, idx))
     assert ref["eta"].shape == (nf, 3, 2, ne) and ref["g_f"].shape == (nb, 3, 2, ne)
-    for k in ("eta", "chi", "a_eta", "a_chi", "g_T", "g_eta_e", "g_f"):
+    for k in ("eta", "chi", "a_eta", "a_chi", "aq_eta", "aq_chi", "g_T", "g_eta_e", "g_f"):
         assert np.all(np.isfinite(ref[k])), k
+    # |integral of H B| <= integral of |H| B: the quadrature-level scale bounds the output level
+    for o in ("eta", "chi"):
+        a, aq = ref["a_" + o].astype(np.float64), ref["aq_" + o].astype(np.float64)
+        assert np.all(aq >= a * (1 - 1e-6)), o
+        assert np.allclose(aq[:, :, 0], a[:, :, 0], rtol=1e-6, atol=0), o   # l = 0: H >= 0
     if "T" in ref:
         T, E = ref["T"], ref["eta_e"]
         assert np.sum((E > 30) & (T < 2)) >= (nf // 10 if name == "large" else 1)

@@ -39,7 +39,7 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-def gpu_jacobian(inp, precision, nquad, rule, processes=3, eta_fp64=64.0):
+def gpu_jacobian(inp, precision, nquad, rule, processes=3, eta_fp64=30.0):
     grid = vtx.GridHandle(inp.eps, inp.w)
     opts = vtx.make_opts(precision, nquad, rule, processes, eta_fp64=eta_fp64)
     jac = vtx.jacobian(grid, opts, to_dev(inp.T), to_dev(inp.eta_e))

@@ -41,7 +41,7 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-def gpu_forward(inp, precision, nquad, rule, processes=3, eta_fp64=64.0):
+def gpu_forward(inp, precision, nquad, rule, processes=3, eta_fp64=30.0):
     grid = vtx.GridHandle(inp.eps, inp.w)
     opts = vtx.make_opts(precision, nquad, rule, processes, eta_fp64=eta_fp64)
     T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
@@ -142,7 +142,7 @@ def test_deterministic_and_batch_independent():
 
 # ---------------------------------------------------------------------------- backward
 
-def gpu_backward(inp, ge, gc, precision, nquad, rule, eta_fp64=64.0, processes=3):
+def gpu_backward(inp, ge, gc, precision, nquad, rule, eta_fp64=30.0, processes=3):
     grid = vtx.GridHandle(inp.eps, inp.w)
     opts = vtx.make_opts(precision, nquad, rule, processes, eta_fp64=eta_fp64)
     out = vtx.backward(grid, opts, to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f), to_dev(ge), to_dev(gc))
@@ -302,10 +302,10 @@ def test_backward_largest_grid():
 
 
 def test_mixed_zone_classes():
-    """The mixed path splits zones by |eta_e|: FP32 throughout up to the threshold, FP64
-    Fermi-Dirac factors above it, and entirely FP64 above 64. Zones of the last class match the
-    FP64 path bit for bit (forward and backward); the other two stay within the mixed bars of
-    the oracle. A lower threshold moves zones between the first two classes only."""
+    """The mixed path splits zones by |eta_e|: FP32 up to the threshold, FP64 above it (the
+    threshold capped at 64). Zones above it match the FP64 path bit for bit (forward and
+    backward); the others stay within the mixed bars of the oracle. A lower threshold moves
+    zones from the first class to the second."""
     inp = synth.make_inputs("medium", nzones=30)
     inp.eta_e[:12] = [-70.0, -45.0, -31.0, 12.0, 25.0, 31.0, 39.0, 55.0, 63.5, 64.5, 90.0, -16.0]
     inp.T[:12] = [0.6, 1.5, 0.8, 3.0, 0.5, 2.0, 1.0, 0.7, 5.0, 0.9, 4.0, 0.55]
@@ -314,25 +314,21 @@ def test_mixed_zone_classes():
     rT, rE, rf = ograd.vjp(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, ge, gc, orates.Options(nquad=48, rule="panel"))
     e64, c64 = gpu_forward(inp, "fp64", 48, "panel")
     g64 = gpu_backward(inp, ge, gc, "fp64", 48, "panel")
-    for thr in (30.0, 15.0):
-        a = np.abs(inp.eta_e)
-        high = a > 64.0
-        fd = (a > thr) & ~high
-        bulk = ~(a > thr)
-        assert high.sum() >= 2 and fd.sum() >= 5 and bulk.sum() >= 5
-        say(f"[gpu] mixed classes at threshold {thr}: {int(bulk.sum())} FP32, {int(fd.sum())} FP64 Fermi-Dirac, "
-            f"{int(high.sum())} FP64")
+    for thr in (30.0, 15.0, 100.0):
+        high = np.abs(inp.eta_e) > min(thr, 64.0)
+        bulk = ~high
+        assert high.sum() >= 3 and bulk.sum() >= 5
+        say(f"[gpu] mixed classes at threshold {thr}: {int(bulk.sum())} FP32, {int(high.sum())} FP64")
         em, cm = gpu_forward(inp, "mixed", 48, "panel", eta_fp64=thr)
         assert np.array_equal(em[high], e64[high]) and np.array_equal(cm[high], c64[high])
         gm = gpu_backward(inp, ge, gc, "mixed", 48, "panel", eta_fp64=thr)
         for got, ref in zip(gm, g64):
             assert np.array_equal(got[high], ref[high])
-        for name, sel in (("FP32", bulk), ("FP64 Fermi-Dirac", fd)):
-            err = max(rel_err(em[sel], re[sel], ae[sel]).max(), rel_err(cm[sel], rc[sel], ac[sel]).max())
-            gerr = max(grad_err(gm[0][sel], rT[sel]).max(), grad_err(gm[1][sel], rE[sel]).max(),
-                       grad_err(gm[2][sel], rf[sel]).max())
-            say(f"    {name} zones: forward {err:.2e}, backward {gerr:.2e}")
-            assert err <= MIXED_TOL and gerr <= MIXED_TOL
+        err = max(rel_err(em[bulk], re[bulk], ae[bulk]).max(), rel_err(cm[bulk], rc[bulk], ac[bulk]).max())
+        gerr = max(grad_err(gm[0][bulk], rT[bulk]).max(), grad_err(gm[1][bulk], rE[bulk]).max(),
+                   grad_err(gm[2][bulk], rf[bulk]).max())
+        say(f"    FP32 zones: forward {err:.2e}, backward {gerr:.2e}")
+        assert err <= MIXED_TOL and gerr <= MIXED_TOL
 
 
 def test_backward_batch_independent():
