@@ -9,7 +9,8 @@ component). Readings used here:
 * nu_x stands for nu_mu, anti-nu_mu, nu_tau, anti-nu_tau: C_V = -1/2 + 2 s_W, C_A = -1/2,
   averaged over particle/antiparticle so beta_I = beta_II = ((C_V+C_A)^2 + (C_V-C_A)^2)/2;
   its pair partner is nu_x itself.
-The overall scale beyond G_F (electron-mass terms, s_W) is a convention: parity unpinned.
+The overall scale beyond G_F (s_W) is a convention: parity unpinned. With the electron mass
+(oracle.massive) the matrix element gains m^2 (q.q') beta_III, beta_III = C_V^2 - C_A^2.
 """
 import math
 
@@ -21,10 +22,16 @@ NU_E, NU_EBAR, NU_X = 0, 1, 2
 PARTNER = (NU_EBAR, NU_E, NU_X)
 
 
-def couplings(sin2w: float = SIN2W):
-    """beta[s] = (beta_I, beta_II) for species s in (nu_e, anti-nu_e, nu_x)."""
+def couplings(sin2w: float = SIN2W, electron_mass: bool = False):
+    """beta[s] = (beta_I, beta_II) for species s in (nu_e, anti-nu_e, nu_x); with the electron
+    mass a third entry beta_III = C_V^2 - C_A^2, the same for a species and its antiparticle
+    (C_A -> -C_A), so nu_x's average over both is that of nu_mu."""
     cv_e = 0.5 + 2.0 * sin2w
     b_e = ((cv_e + 0.5) ** 2, (cv_e - 0.5) ** 2)
     cv_x = -0.5 + 2.0 * sin2w
     avg = 0.5 * ((cv_x - 0.5) ** 2 + (cv_x + 0.5) ** 2)
-    return ((b_e[0], b_e[1]), (b_e[1], b_e[0]), (avg, avg))
+    out = ((b_e[0], b_e[1]), (b_e[1], b_e[0]), (avg, avg))
+    if electron_mass:
+        m_e, m_x = cv_e * cv_e - 0.25, cv_x * cv_x - 0.25
+        out = (out[0] + (m_e,), out[1] + (m_e,), out[2] + (m_x,))
+    return out

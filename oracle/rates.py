@@ -61,6 +61,7 @@ class Options:
     rule: str = RULE_PANEL
     processes: int = PROC_NES | PROC_PAIR
     sin2w: float = physics.SIN2W
+    electron_mass: bool = False     # weights, rule and couplings with m_e (oracle.massive)
 
 
 def _sigma(z):
@@ -138,6 +139,9 @@ def pair_quadrature(eps, T, mu, opts, absolute=False):
 def task_quadratures(eps, T, eta_e, opts, absolute=False):
     """Steps 1 and 3 only: the quadratures before completion, dict with "nes" / "nps"
     q[z, t, S, l] (tasks t = (i >= j)) and "pair" A[z, i, j, l]."""
+    if opts.electron_mass:
+        from . import massive
+        return massive.task_quadratures(eps, T, eta_e, opts, absolute)
     eps = np.asarray(eps, dtype=float)
     T = np.asarray(T)
     mu = np.asarray(eta_e) * T
@@ -162,7 +166,7 @@ def complete(eps, T, quad):
             q = quad[name]
             nz = q.shape[0]
             ii, jj = nes_tasks(ne)
-            full = np.zeros((nz, ne, ne, 2, 2), dtype=q.dtype)
+            full = np.zeros((nz, ne, ne) + q.shape[-2:], dtype=q.dtype)
             full[:, ii, jj] = q
             # up-scatter j > i from the down-scatter task (j, i): exp(-(eps_j - eps_i)/T); the
             # factor is formed for j > i only (elsewhere it would overflow at small T, unused)
@@ -175,7 +179,8 @@ def complete(eps, T, quad):
             out[name + "_in"] = np.swapaxes(phi_out, 1, 2)
     if "pair" in quad:
         A = quad["pair"]
-        phi_a = np.stack([A, np.swapaxes(A, 1, 2)], axis=-2)  # [z, i, j, S, l]
+        # [z, i, j, S, l]; with the electron mass the symmetric third structure follows
+        phi_a = np.stack([A, np.swapaxes(A, 1, 2)] + ([quad["pair3"]] if "pair3" in quad else []), axis=-2)
         prod = np.exp(-(eps[None, :, None] + eps[None, None, :]) / T[:, None, None])
         out["pair_a"] = phi_a
         out["pair_p"] = prod[..., None, None] * phi_a
@@ -188,19 +193,26 @@ def zone_kernels(eps, T, eta_e, opts, absolute=False):
 
 
 def _species(kern, beta):
-    return beta[0] * kern[..., 0, :] + beta[1] * kern[..., 1, :]   # [z, i, j, l]
+    """sum_S beta_S kern[..., S, :] over the kernel's structures: (I, II), or (I, II, III)
+    with the electron mass."""
+    out = beta[0] * kern[..., 0, :]
+    for S in range(1, kern.shape[-2]):
+        out = out + beta[S] * kern[..., S, :]
+    return out   # [z, i, j, l]
 
 
 def scattering_kernels(kernels, b):
-    """(Phi_in, Phi_out) [z, i, j, l] of one species with couplings b = (beta_I, beta_II),
-    summed over the scattering targets present: electrons with b, positrons with b swapped."""
+    """(Phi_in, Phi_out) [z, i, j, l] of one species with couplings b = (beta_I, beta_II[,
+    beta_III]), summed over the scattering targets present: electrons with b, positrons with
+    beta_I and beta_II swapped (C_A -> -C_A leaves beta_III = C_V^2 - C_A^2 alone)."""
     pin = pout = 0.0
+    bp = (b[1], b[0]) + tuple(b[2:])
     if "nes_out" in kernels:
         pin = pin + _species(kernels["nes_in"], b)
         pout = pout + _species(kernels["nes_out"], b)
     if "nps_out" in kernels:
-        pin = pin + _species(kernels["nps_in"], (b[1], b[0]))
-        pout = pout + _species(kernels["nps_out"], (b[1], b[0]))
+        pin = pin + _species(kernels["nps_in"], bp)
+        pout = pout + _species(kernels["nps_out"], bp)
     return pin, pout
 
 
@@ -216,7 +228,7 @@ def contract(kernels, w, f, opts):
     dtype = np.result_type(f, *[k for k in kernels.values()])
     eta = np.zeros((nz, 3, 2, ne), dtype=dtype)
     chi = np.zeros((nz, 3, 2, ne), dtype=dtype)
-    betas = physics.couplings(opts.sin2w)
+    betas = physics.couplings(opts.sin2w, opts.electron_mass)
     for s in range(3):
         b = betas[s]
         if has_scattering(kernels):
@@ -250,9 +262,9 @@ def contract_abs(kernels, w, f, opts):
     nz, _, _, ne = f.shape
     aeta = np.zeros((nz, 3, 2, ne))
     achi = np.zeros((nz, 3, 2, ne))
-    betas = physics.couplings(opts.sin2w)
+    betas = physics.couplings(opts.sin2w, opts.electron_mass)
     for s in range(3):
-        b = betas[s]
+        b = tuple(abs(x) for x in betas[s])   # beta_III can be negative
         if has_scattering(ak):
             pin, pout = scattering_kernels(ak, b)
             f0 = f[:, s, 0, None, :] * cw
@@ -294,9 +306,9 @@ def jacobian_blocks(kernels, w, opts, absolute=False):
     dtype = np.result_type(*[v for v in k.values()])
     jac = np.zeros((nz, 3, 2, 4, ne, ne), dtype=dtype)
     sgn = 1.0 if absolute else -1.0
-    betas = physics.couplings(opts.sin2w)
+    betas = physics.couplings(opts.sin2w, opts.electron_mass)
     for s in range(3):
-        b = betas[s]
+        b = tuple(abs(x) for x in betas[s]) if absolute else betas[s]
         if has_scattering(k):
             pin, pout = scattering_kernels(k, b)
             pin = pin * cw[:, None]     # [z, i, j, l]

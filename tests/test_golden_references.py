@@ -6,7 +6,8 @@ report (tests/golden/ref_<workload>.npz, written by tests/golden/make_reference.
   eta_e > 30, T < 2 MeV, a backward sub-sample inside it, finite values.
 * For the medium workload (cheap to draw) the sample is the sampler's, the stored zone states
   are the workload's, and the oracle recomputed on a few stored zones gives the stored values
-  bit for bit.
+  bit for bit (the float32 gradient scale to its rounding).
+* The gradient scale aq_g_f bounds |g_f| (it sums the absolute values of g_f's terms).
 """
 import os
 import sys
@@ -30,8 +31,11 @@ def test_reference_is_current_and_whole(name):
     assert idx.shape == (nf,) and idx_b.shape == (nb,)
     assert np.all(np.diff(idx) > 0) and np.all(np.isin(idx_b, idx))
     assert ref["eta"].shape == (nf, 3, 2, ne) and ref["g_f"].shape == (nb, 3, 2, ne)
-    for k in ("eta", "chi", "a_eta", "a_chi", "aq_eta", "aq_chi", "g_T", "g_eta_e", "g_f"):
+    for k in ("eta", "chi", "a_eta", "a_chi", "aq_eta", "aq_chi", "g_T", "g_eta_e", "g_f", "aq_g_f"):
         assert np.all(np.isfinite(ref[k])), k
+    # the gradient's absolute scale bounds it: |J^T g| <= |J|_abs^T |g|
+    assert ref["aq_g_f"].shape == ref["g_f"].shape
+    assert np.all(ref["aq_g_f"].astype(np.float64) >= np.abs(ref["g_f"]) * (1 - 1e-6))
     # |integral of H B| <= integral of |H| B: the quadrature-level scale bounds the output level
     for o in ("eta", "chi"):
         a, aq = ref["a_" + o].astype(np.float64), ref["aq_" + o].astype(np.float64)
@@ -62,3 +66,5 @@ def test_medium_reference_reproduces():
     gT, gE, gf = ograd.vjp(sb.eps, sb.w, sb.T, sb.eta_e, sb.f, ge, gc, opts)
     assert np.allclose(gT, ref["g_T"][zb], rtol=1e-13, atol=0) and np.allclose(gf, ref["g_f"][zb], rtol=1e-12,
                                                                                   atol=1e-300)
+    J = orates.jacobian(sb.eps, sb.w, sb.T, sb.eta_e, opts, absolute=True)
+    assert np.allclose(make_reference.grad_f_scale(J, ge, gc), ref["aq_g_f"][zb], rtol=1e-6, atol=0)

@@ -142,7 +142,7 @@ def test_interpolation_with_swapped_fractions(monkeypatch):
         pins_tab.test_exact_on_bilinear_data()
 
 
-def _cv_flipped_couplings(sin2w=phys.SIN2W):
+def _cv_flipped_couplings(sin2w=phys.SIN2W, electron_mass=False):
     """nu_e with the nu_mu vector coupling C_V = -1/2 + 2 s_W (a dropped charged-current term)."""
     cv = -0.5 + 2.0 * sin2w
     b_e = ((cv + 0.5) ** 2, (cv - 0.5) ** 2)
@@ -153,7 +153,7 @@ def _cv_flipped_couplings(sin2w=phys.SIN2W):
 _GOOD_COUPLINGS = phys.couplings
 
 
-def _unaveraged_nux(sin2w=phys.SIN2W):
+def _unaveraged_nux(sin2w=phys.SIN2W, electron_mass=False):
     """nu_x as nu_mu alone (no average over particle and antiparticle)."""
     good = _GOOD_COUPLINGS(sin2w)
     cv = -0.5 + 2.0 * sin2w
@@ -230,3 +230,39 @@ def test_newton_source_jacobian_slips(monkeypatch):
     monkeypatch.setattr(onewton, "source_jacobian", orig)
     with pytest.raises(AssertionError):
         pins_newton.test_source_jacobian_from_the_rates_blocks()
+
+
+def test_massive_weight_slips(monkeypatch):
+    """Electron-mass weights: massless kinematics in the azimuthal angle (P -> E), the positron's
+    momentum taken equal to the electron's, and a doubled mass structure must each trip the
+    four-vector brute force or the vacuum pair cross-section."""
+    import oracle.massive as mas
+    import test_oracle_massive as pins_mas
+
+    def fails_nes(l, S, e, ep, E):
+        ref = pins_mas.brute_h(pins_mas.brute_nes_avg, l, S, e, ep, E, 1.0)
+        return abs(float(mas.h_nes(l, S, e, ep, E)) - ref) > 5e-8 * abs(float(mas.h_nes(0, 1, e, ep, E)))
+
+    def fails_pair(l, S, e, ep, E):
+        ref = pins_mas.brute_h(pins_mas.brute_pair_avg, l, S, e, ep, E, -1.0)
+        return abs(float(mas.h_pair(l, S, e, ep, E)) - ref) > 5e-8 * abs(float(mas.h_pair(0, 1, e, ep, E)))
+
+    nes, pair = mas._nes_integrand, mas._pair_integrand
+    with monkeypatch.context() as mp:
+        mp.setattr(mas, "_nes_integrand", lambda l, S, e, ep, E, P, m, k: nes(l, S, e, ep, E, E, m, k))
+        assert fails_nes(0, 1, 2.0, 1.0, 0.8)
+    with monkeypatch.context() as mp:
+        mp.setattr(mas, "_pair_integrand", lambda l, S, e, ep, E, P, Pb, m, k: pair(l, S, e, ep, E, P, P, m, k))
+        assert fails_pair(1, 2, 2.0, 1.0, 0.8)
+    with monkeypatch.context() as mp:
+        mp.setattr(mas, "_pair_integrand",
+                   lambda l, S, e, ep, E, P, Pb, m, k: pair(l, S, e, ep, E, P, Pb, m, k) * (2.0 if S == 3 else 1.0))
+        f = lambda E: float(mas.h_pair(0, 3, 1.0, 0.3, E))
+        got = si_quad(f, mas.ME, 1.3 - mas.ME)
+        assert abs(got - pins_mas._vacuum_closed(1.0, 0.3, 3, 0)) > 1e-6 * abs(got)
+
+
+def si_quad(f, a, b):
+    import scipy.integrate as si
+    pts = np.linspace(a, b, 9)
+    return sum(si.quad(f, x, y, epsabs=0, epsrel=1e-12, limit=400)[0] for x, y in zip(pts[:-1], pts[1:]))
