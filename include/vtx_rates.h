@@ -114,6 +114,29 @@ int vtx_rates_forward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones
                       double* eta, double* chi, void* hip_stream);
 
 /*
+ * Forward with the electron mass m = 0.51099895 MeV: the accuracy variant for low T and eps,
+ * where m is not small against the electron energies (the rates of Sect. 2.1's list of model
+ * components with massive e+-). Same arguments, layouts, outputs and error behaviour as
+ * vtx_rates_forward; opts->precision must be VTX_FP64 and opts->rule VTX_RULE_PANEL (else
+ * VTX_EINVAL). What changes:
+ *   - electrons and positrons have total energy E >= m and momentum P = sqrt(E^2 - m^2); the
+ *     chemical potential mu_e = eta_e T includes the rest mass (positrons at -mu_e);
+ *   - the spin-summed matrix element gains m^2 (q.q') beta_III, beta_III = C_V^2 - C_A^2
+ *     (the same for a species and its antiparticle), with a minus sign for scattering and a
+ *     plus sign for the pair; H^{N,P}_{l,III} = 1/(eps eps') Int dk P_l(x) m^2 (q.q');
+ *   - the rule: scattering panels between sorted {m, max(m, mu-Delta), max(m, mu),
+ *     min(E_k, max(m, mu) + 10 T)} in s with E = m + (b_3 - m) s^2, then the Gauss-Laguerre
+ *     tail; E_k = (sqrt(Delta^2 + 4 eps_i eps_j + (eps_i+eps_j)^2 m^2/(eps_i eps_j)) - Delta)/2
+ *     is the kink of H. Pair panels between sorted {m, E_lo, E_hi, clip(mu, m, w-m), w-m} in
+ *     theta with E = m + (w - 2m) sin^2(pi theta/2), E_lo,hi = (w -+ |eps_i - eps_j|
+ *     sqrt(1 - m^2/(eps_i eps_j)))/2; the pair kernel vanishes unless eps_i eps_j > m^2.
+ * Only the forward exists in this form (no backward, Jacobian or mixed precision).
+ */
+int vtx_rates_forward_mass(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
+                           const double* T, const double* eta_e, const double* f,
+                           double* eta, double* chi, void* hip_stream);
+
+/*
  * Backward (vector-Jacobian product): given upstream gradients g_eta, g_chi of a scalar L,
  * writes g_T = dL/dT (at fixed eta_e), g_eta_e = dL/deta_e (at fixed T) and g_f = dL/df.
  * These are the exact derivatives of the discrete rule above, including the motion of the
@@ -261,9 +284,15 @@ void vtx_release(void);
  * vtx_eval_hpoly: evaluates the angular weight H from the library's coefficient tables:
  *   process VTX_NES (requires e >= ep) or VTX_PAIR, comp = 2*(S-1) + l (S = 1, 2 for I, II),
  *   at n energies E[] (host), into out[] (host).
+ * vtx_eval_hmass: the angular weight with the electron mass from the library's Laurent
+ *   coefficient tables, on the exact route of long momentum-transfer intervals (the kernels
+ *   switch to Gauss points on the integrand where the interval is short against its distance
+ *   from k = 0; this hook does not); comp = 2*(S-1) + l for S = I, II and 4 + l for the
+ *   third structure m^2 (q.q'). Same arguments otherwise; 0 outside the kinematic range.
  */
 int vtx_gauss_rule(int kind, int n, double* x, double* w);
 int vtx_eval_hpoly(int process, int comp, double e, double ep, int n, const double* E, double* out);
+int vtx_eval_hmass(int process, int comp, double e, double ep, int n, const double* E, double* out);
 
 /*
  * Host-side copy of one task's coefficient table, prefactor G_F^2/(pi e ep) included:

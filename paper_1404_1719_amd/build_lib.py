@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "lib", "libvtxrates.so")
 SOURCES = [os.path.join(CSRC, "vtx_kernels.hip"), os.path.join(CSRC, "vtx_newton.hip"),
+           os.path.join(CSRC, "vtx_massive.hip"),
            os.path.join(CSRC, "vtx_host.cpp")]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/vtx_rates.h"
+#include "hmass_gen.h"
 #include "hpoly_gen.h"
 #include "vtx_internal.h"
 
@@ -217,6 +218,36 @@ double bernstein_low(const double* g5, double u) {
   return s;
 }
 
+// Electron-mass weights of scattering task (e >= ep) and pair {e, ep}: the generator's Laurent
+// coefficients times the prefactor, the third structure with its sign in the rates (minus for
+// scattering, plus for the pair), and the rule's breakpoints that depend on the task only.
+//   scattering kink E_k: root of P + P' = e + ep, (sqrt(om^2 + 4 e ep + w^2 m^2/(e ep)) - om)/2;
+//   pair: E = (w -+ y)/2 with y = |e - ep| sqrt(1 - m^2/(e ep)), open when e ep > m^2.
+void mass_coefficients(double e, double ep, bool pair, MassCoef& C) {
+  std::memset(&C, 0, sizeof(C));
+  const double m = kMe, w = e + ep, om = e - ep;
+  if (pair)
+    vtx_hmass_pair(e, ep, m, C.c, C.c3);
+  else
+    vtx_hmass_nes(e, ep, m, C.c, C.c3);
+  const double pref = kGF * kGF / (M_PI * e * ep);
+  for (int c = 0; c < 4; ++c)
+    for (int k = 0; k < 16; ++k) C.c[c][k] *= pref;
+  const double s3 = pair ? pref : -pref;
+  for (int l = 0; l < 2; ++l)
+    for (int k = 0; k < 3; ++k) C.c3[l][k] *= s3;
+  if (!pair) {
+    const double ek = 0.5 * (std::sqrt(om * om + 4.0 * e * ep + w * w * m * m / (e * ep)) - om);
+    C.k0 = std::fmax(ek, m);
+  } else {
+    const bool open = e * ep > m * m && w > 2.0 * m;
+    const double y = open ? std::fabs(om) * std::sqrt(1.0 - m * m / (e * ep)) : 0.0;
+    C.k0 = 0.5 * (w - y);
+    C.k1 = 0.5 * (w + y);
+    C.support = open ? 1.0 : 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Table cache
 
@@ -234,7 +265,7 @@ std::vector<std::unique_ptr<Plan>> g_plans;
 int g_block = 256;           // threads per workgroup of the rate kernels (vtx_set_workgroup_waves)
 std::vector<int> g_dev_ok;   // per device: 0 unknown, 1 gfx950, -1 other
 
-void couplings(double s2w, double beta[3][2]) {
+void couplings(double s2w, double beta[3][2], double beta3[3]) {
   const double cve = 0.5 + 2.0 * s2w;
   beta[0][0] = (cve + 0.5) * (cve + 0.5);
   beta[0][1] = (cve - 0.5) * (cve - 0.5);
@@ -243,6 +274,9 @@ void couplings(double s2w, double beta[3][2]) {
   const double cvx = -0.5 + 2.0 * s2w;
   const double avg = 0.5 * ((cvx - 0.5) * (cvx - 0.5) + (cvx + 0.5) * (cvx + 0.5));
   beta[2][0] = beta[2][1] = avg;
+  // beta_III = C_V^2 - C_A^2: unchanged by C_A -> -C_A, so shared by particle and antiparticle
+  beta3[0] = beta3[1] = (cve - 0.5) * (cve + 0.5);
+  beta3[2] = (cvx - 0.5) * (cvx + 0.5);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -299,6 +333,18 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   for (int i = 0; i < ne; ++i)
     for (int j = 0; j < ne; ++j) ok = pair_coefficients(g->eps[i], g->eps[j], pcoef[i * ne + j]) && ok;
   if (!ok) return VTX_EINVAL;
+  std::vector<MassCoef> mnes(ntn), mpair(ntn);
+  for (int i = 0, t = 0; i < ne; ++i)
+    for (int j = 0; j <= i; ++j, ++t) {
+      mass_coefficients(g->eps[i], g->eps[j], false, mnes[t]);
+      mass_coefficients(g->eps[i], g->eps[j], true, mpair[t]);
+    }
+  std::vector<double2> mgauss(kMassGauss);
+  {
+    double gx[kMassGauss], gw[kMassGauss];
+    if (!gauss_rule(0, kMassGauss, gx, gw)) return VTX_EINVAL;
+    for (int k = 0; k < kMassGauss; ++k) mgauss[k] = make_double2(gx[k], gw[k]);
+  }
   std::vector<double> tx(m4), tw(m4), lx(nlag), lw(nlag);
   if (!gauss_rule(0, m4, tx.data(), tw.data()) || !gauss_rule(1, nlag, lx.data(), lw.data())) return VTX_EINVAL;
   std::vector<double4> leg64(m4), lag64(nlag);
@@ -322,6 +368,8 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   const size_t o_ie = place(sizeof(double) * ne);
   const size_t o_ij = place(sizeof(int) * ntn), o_nc = place(sizeof(NesCoef) * ntn);
   const size_t o_pc = place(sizeof(PairCoef) * ntp);
+  const size_t o_mn = place(sizeof(MassCoef) * ntn), o_mp = place(sizeof(MassCoef) * ntn);
+  const size_t o_mg = place(sizeof(double2) * kMassGauss);
   const size_t o_l64 = place(sizeof(double4) * m4), o_g64 = place(sizeof(double4) * nlag);
   const size_t o_l32 = place(sizeof(float4) * m4), o_g32 = place(sizeof(float4) * nlag);
   std::vector<uint16_t> order;
@@ -335,6 +383,9 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   put(o_ij, nes_ij.data(), sizeof(int) * ntn);
   put(o_nc, ncoef.data(), sizeof(NesCoef) * ntn);
   put(o_pc, pcoef.data(), sizeof(PairCoef) * ntp);
+  put(o_mn, mnes.data(), sizeof(MassCoef) * ntn);
+  put(o_mp, mpair.data(), sizeof(MassCoef) * ntn);
+  put(o_mg, mgauss.data(), sizeof(double2) * kMassGauss);
   put(o_l64, leg64.data(), sizeof(double4) * m4);
   put(o_g64, lag64.data(), sizeof(double4) * nlag);
   put(o_l32, leg32.data(), sizeof(float4) * m4);
@@ -353,13 +404,16 @@ int build_plan(int device, const vtx_grid* g, const vtx_opts* o, Plan** out) {
   d.m4 = m4;
   d.rule = o->rule;
   d.nlag = nlag;
-  couplings(o->sin2w, d.beta);
+  couplings(o->sin2w, d.beta, d.beta3);
   d.eps = (const double*)(b + o_eps);
   d.c0w = (const double*)(b + o_c0w);
   d.inv_eps = (const double*)(b + o_ie);
   d.nes_ij = (const int*)(b + o_ij);
   d.nes_coef = (const NesCoef*)(b + o_nc);
   d.pair_coef = (const PairCoef*)(b + o_pc);
+  d.mass_nes = (const MassCoef*)(b + o_mn);
+  d.mass_pair = (const MassCoef*)(b + o_mp);
+  d.mass_gauss = (const double2*)(b + o_mg);
   d.leg64 = (const double4*)(b + o_l64);
   d.lag64 = (const double4*)(b + o_g64);
   d.leg32 = (const float4*)(b + o_l32);
@@ -453,6 +507,20 @@ int vtx_rates_forward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones
   rc = vtx::get_plan(grid, opts, &P);
   if (rc != VTX_OK) return rc;
   const hipError_t e = vtx::launch_forward(P, nzones, T, eta_e, f, eta, chi, (hipStream_t)hip_stream);
+  return e == hipSuccess ? VTX_OK : VTX_EHIP;
+}
+
+int vtx_rates_forward_mass(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones, const double* T,
+                           const double* eta_e, const double* f, double* eta, double* chi, void* hip_stream) {
+  int rc = vtx::check_args(grid, opts, nzones);
+  if (rc != VTX_OK) return rc;
+  if (opts->precision != VTX_FP64 || opts->rule != VTX_RULE_PANEL) return VTX_EINVAL;
+  if (nzones == 0) return VTX_OK;
+  if (!T || !eta_e || !f || !eta || !chi) return VTX_EINVAL;
+  vtx::DevPlan P;
+  rc = vtx::get_plan(grid, opts, &P);
+  if (rc != VTX_OK) return rc;
+  const hipError_t e = vtx::launch_forward_mass(P, nzones, T, eta_e, f, eta, chi, (hipStream_t)hip_stream);
   return e == hipSuccess ? VTX_OK : VTX_EHIP;
 }
 
@@ -619,6 +687,59 @@ void vtx_release(void) {
   for (auto& p : vtx::g_plans)
     if (p->dbuf) (void)hipFree(p->dbuf);
   vtx::g_plans.clear();
+}
+
+int vtx_eval_hmass(int process, int comp, double e, double ep, int n, const double* E, double* out) {
+  if ((process != VTX_NES && process != VTX_PAIR) || comp < 0 || comp > 5 || n < 0 || (n > 0 && (!E || !out)))
+    return VTX_EINVAL;
+  if (!(e > 0.0) || !(ep > 0.0) || (process == VTX_NES && e < ep)) return VTX_EINVAL;
+  const bool pair = process == VTX_PAIR;
+  vtx::MassCoef C;
+  vtx::mass_coefficients(e, ep, pair, C);
+  const double m = vtx::kMe, w = e + ep, om = e - ep;
+  // undo the prefactor and the third structure's sign: H itself
+  const double pref = vtx::kGF * vtx::kGF / (M_PI * e * ep), s3 = pair ? pref : -pref;
+  for (int q = 0; q < n; ++q) {
+    const double x = E[q];
+    double k0 = 0.0, k1 = 0.0;
+    if (!pair) {
+      const double xp = x + om;
+      if (x > m && xp > m) {
+        const double P = std::sqrt((x - m) * (x + m)), Pp = std::sqrt((xp - m) * (xp + m));
+        k0 = (2.0 * x + om) * om / (P + Pp);
+        k1 = std::fmin(w, P + Pp);
+      }
+    } else {
+      const double xb = w - x;
+      if (x > m && xb > m) {
+        const double P = std::sqrt((x - m) * (x + m)), Pb = std::sqrt((xb - m) * (xb + m));
+        k0 = std::fmax(std::fabs(om), std::fabs((2.0 * x - w) * w) / (P + Pb));
+        k1 = P + Pb;
+      }
+    }
+    const double L = k1 - k0;
+    if (!(L > 0.0)) {
+      out[q] = 0.0;
+      continue;
+    }
+    // h_n = (k1^{n+1} - k0^{n+1}) / ((n + 1) L), n = -4, -2, 0, 2, 4, 6
+    double sn[7] = {1.0, 0, 0, 0, 0, 0, 0};
+    for (int a = 1; a <= 6; ++a) sn[a] = k1 * sn[a - 1] + std::pow(k0, a);
+    const double ixy = k0 > 0.0 ? 1.0 / (k0 * k1) : 0.0;
+    const double h[6] = {sn[2] * ixy * ixy * ixy / 3.0, ixy, 1.0, sn[2] / 3.0, sn[4] / 5.0, sn[6] / 7.0};
+    double acc = 0.0;
+    if (comp < 4) {
+      for (int r = 0; r < 5; ++r)
+        for (int a = 0; a < 3; ++a) acc += C.c[comp][3 * r + a] * std::pow(x, a) * h[r];
+      acc += C.c[comp][15] * h[5];
+      out[q] = L * acc / pref;
+    } else {
+      const int l = comp - 4;
+      acc = C.c3[l][0] * h[2] + C.c3[l][1] * h[3] + C.c3[l][2] * h[4];
+      out[q] = L * acc / s3;
+    }
+  }
+  return VTX_OK;
 }
 
 int vtx_gauss_rule(int kind, int n, double* x, double* w) {

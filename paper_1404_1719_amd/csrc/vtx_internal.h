@@ -15,6 +15,8 @@ constexpr int kMaxNquad = 64;
 constexpr double kKappa = 10.0;
 constexpr double kGF = 1.1663787e-11;        // MeV^-2
 constexpr double kHbarC = 1.973269804e-11;   // MeV cm
+constexpr double kMe = 0.51099895;           // electron mass, MeV
+constexpr int kMassGauss = 6;                // points of the short momentum-transfer route
 
 // Angular-weight coefficients of one scattering task (eps_i >= eps_j), comps
 // (S, l) = (I,0), (I,1), (II,0), (II,1); variable u = E / eps_j.
@@ -37,6 +39,19 @@ struct PairCoef {
   double A[2][5];
   double B[2][3];
   double C[2][5];
+};
+
+// Electron-mass weights of one task (i >= j; for the pair, the unordered pair {i, j}):
+// c[comp][slot], comps (S, l) = (I,0), (I,1), (II,0), (II,1), are the Laurent coefficients of
+// the azimuth-averaged integrand in E^a k^n (slot 3 (n + 4)/2 + a for n = -4..4, slot 15 for
+// (6, 0)) and c3[l][n/2] the third structure's (n = 0, 2, 4), with the prefactor
+// G_F^2/(pi e_i e_j) folded in and the third structure's sign in the rates (minus for
+// scattering, plus for the pair). k0: scattering E_k, the kink of H (>= m); pair E_lo;
+// k1: pair E_hi; support: pair, 1 when the pair is open (e_i e_j > m^2, e_i + e_j > 2m).
+struct MassCoef {
+  double c[4][16];
+  double c3[2][3];
+  double k0, k1, support, pad;
 };
 
 // Everything a kernel needs about the zone-independent tables; passed by value.
@@ -62,6 +77,10 @@ struct DevPlan {
   // whose groups take the same node-loop variants are contiguous (see task_order in
   // vtx_host.cpp). Scattering tasks and pair tasks (one per unordered pair) share it.
   const uint16_t* task_order; // [ne + 1][ntn]
+  const MassCoef* mass_nes;   // [ntn] electron-mass weights, scattering task t
+  const MassCoef* mass_pair;  // [ntn] electron-mass weights, pair {i, j} of task t
+  const double2* mass_gauss;  // [kMassGauss] {t, w} on [0, 1]
+  double beta3[3];            // beta_III = C_V^2 - C_A^2 per species
   const double4* leg64;     // [m4]   {t, 1 - t, w, 0} on [0, 1]
   const double4* lag64;     // [nlag] {x, x, w exp(x), 0}
   const float4* leg32;
@@ -91,5 +110,10 @@ hipError_t launch_ray_system(int ne, int64_t nz, int nzr, double dt, const doubl
 hipError_t launch_ray_solve(int nb, int64_t nrays, int nzr, const double* lo, double* D, const double* up,
                             double* rhs, hipStream_t s);
 int max_block();   // largest diagonal block the solve holds in LDS
+
+// Forward with the electron mass (vtx_massive.hip), FP64, PANEL rule.
+hipError_t launch_forward_mass(const DevPlan& P, int64_t nz, const double* T, const double* eta_e, const double* f,
+                               double* eta, double* chi, hipStream_t s);
+size_t mass_lds_bytes(int ne);
 
 }  // namespace vtx

@@ -11,6 +11,10 @@ Workloads (named by shape; all draw order fixed as T, eta_e, a_s, noise, h):
                 a_s ~ U(-2, 15), 5 % multiplicative log-normal noise on f0, 48 nodes, panel rule.
 * ``large``   : 4096 rays x 600 zones, NE = 21, T ~ U(0.5, 60), eta_e ~ U(0, 60), a_s ~ U(-2, 15),
                 5 % noise, 64 nodes, panel rule (one GPU's share of a 3-D model).
+* ``lowt``    : 256 rays x 400 zones, NE = 21 log bins 0.5-300 MeV, T ~ U(0.2, 8), eta_e ~ U(-2, 30),
+                a_s ~ U(-2, 10), 5 % noise, 48 nodes, panel rule: the cool, outer zones where the
+                electron mass (0.511 MeV) is not small against T and the lowest bins, the regime
+                of the rates with the electron mass.
 
 Energy grid: NE + 1 geometric bin edges e_0..e_NE, centres eps_i = sqrt(e_i e_{i+1}) and
 bin volumes w_i = (e_{i+1}^3 - e_i^3)/3 [MeV^3], the measure of the eps'^2 d eps' phase-space
@@ -65,6 +69,8 @@ WORKLOADS = {
                             (-2.0, 15.0), 0.05, 48, "panel", "fp64"),
     "large": Workload("large", 5, 4096, 600, 21, 2.0, 380.0, (0.5, 60.0), (0.0, 60.0), (-2.0, 15.0),
                       0.05, 64, "panel", "mixed", chunks=8),
+    "lowt": Workload("lowt", 6, 256, 400, 21, 0.5, 300.0, (0.2, 8.0), (-2.0, 30.0), (-2.0, 10.0),
+                     0.05, 48, "panel", "fp64"),
 }
 
 

@@ -61,6 +61,8 @@ def library():
     lib.vtx_opts_default.restype = None
     lib.vtx_rates_forward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp, vp, vp]
     lib.vtx_rates_forward.restype = ctypes.c_int
+    lib.vtx_rates_forward_mass.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64, vp, vp, vp, vp, vp, vp]
+    lib.vtx_rates_forward_mass.restype = ctypes.c_int
     lib.vtx_rates_backward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), i64,
                                        vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.vtx_rates_backward.restype = ctypes.c_int
@@ -95,6 +97,8 @@ def library():
     lib.vtx_gauss_rule.restype = ctypes.c_int
     lib.vtx_eval_hpoly.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
     lib.vtx_eval_hpoly.restype = ctypes.c_int
+    lib.vtx_eval_hmass.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+    lib.vtx_eval_hmass.restype = ctypes.c_int
     lib.vtx_task_coefficients.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
     lib.vtx_task_coefficients.restype = ctypes.c_int
     _lib = lib
@@ -181,6 +185,23 @@ def forward(grid: GridHandle, opts: Opts, T, eta_e, f, eta=None, chi=None, strea
                                      _dev_ptr(eta_e, "eta_e", (nz,)), _dev_ptr(f, "f", shp),
                                      _dev_ptr(eta, "eta", shp), _dev_ptr(chi, "chi", shp), _stream_handle(stream))
     _check(rc, "vtx_rates_forward")
+    return eta, chi
+
+
+def forward_mass(grid: GridHandle, opts: Opts, T, eta_e, f, eta=None, chi=None, stream=None):
+    """eta, chi with the electron mass (vtx_rates_forward_mass; FP64 opts, PANEL rule)."""
+    import torch
+    nz = T.shape[0]
+    shp = (nz, 3, 2, grid.ne)
+    if eta is None:
+        eta = torch.empty(shp, dtype=torch.float64, device=T.device)
+    if chi is None:
+        chi = torch.empty(shp, dtype=torch.float64, device=T.device)
+    rc = library().vtx_rates_forward_mass(ctypes.byref(grid.c), ctypes.byref(opts), nz, _dev_ptr(T, "T", (nz,)),
+                                          _dev_ptr(eta_e, "eta_e", (nz,)), _dev_ptr(f, "f", shp),
+                                          _dev_ptr(eta, "eta", shp), _dev_ptr(chi, "chi", shp),
+                                          _stream_handle(stream))
+    _check(rc, "vtx_rates_forward_mass")
     return eta, chi
 
 
@@ -372,6 +393,16 @@ def eval_hpoly(process: int, comp: int, e: float, ep: float, E):
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "vtx_eval_hpoly")
     return out
 
+
+
+def eval_hmass(process: int, comp: int, e: float, ep: float, E):
+    """Host-side angular weight with the electron mass (exact route) from the library's tables."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    out = np.zeros_like(E)
+    _check(library().vtx_eval_hmass(process, comp, e, ep, E.size,
+                                    E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "vtx_eval_hmass")
+    return out
 
 def task_coefficients(process: int, e: float, ep: float):
     """Host copy of one task's coefficient table (32 / 26 doubles, layout in include/vtx_rates.h)."""

@@ -45,6 +45,9 @@ hipError_t launch_ray_solve(int, int64_t, int, const double*, double*, const dou
   unreachable("ray_solve");
 }
 int max_block() { return 140; }
+hipError_t launch_forward_mass(const DevPlan&, int64_t, const double*, const double*, const double*, double*, double*,
+                               hipStream_t) { unreachable("forward_mass"); }
+size_t mass_lds_bytes(int) { unreachable("mass_lds_bytes"); }
 }  // namespace vtx
 
 static int failures = 0;
@@ -90,6 +93,17 @@ int main() {
   EXPECT(vtx_eval_hpoly(VTX_NES, 4, 3.0, 2.0, 1, E.data(), out.data()) == VTX_EINVAL);
   EXPECT(vtx_eval_hpoly(VTX_NES, 0, 2.0, 3.0, 1, E.data(), out.data()) == VTX_EINVAL);
   EXPECT(vtx_task_coefficients(VTX_NPS, 3.0, 2.0, coef.data()) == VTX_EINVAL);
+  // electron-mass weights: thresholds, the diagonal and energies far outside the range
+  const double esm[] = {0.3, 0.6, 2.0, 20.0, 380.0};
+  for (double e : esm)
+    for (double ep : esm)
+      for (int comp = 0; comp < 6; ++comp) {
+        if (e >= ep) EXPECT(vtx_eval_hmass(VTX_NES, comp, e, ep, 97, E.data(), out.data()) == VTX_OK);
+        EXPECT(vtx_eval_hmass(VTX_PAIR, comp, e, ep, 97, E.data(), out.data()) == VTX_OK);
+        for (double v : out) EXPECT(std::isfinite(v));
+      }
+  EXPECT(vtx_eval_hmass(VTX_NES, 6, 3.0, 2.0, 1, E.data(), out.data()) == VTX_EINVAL);
+  EXPECT(vtx_eval_hmass(VTX_NES, 0, 2.0, 3.0, 1, E.data(), out.data()) == VTX_EINVAL);
   EXPECT(vtx_task_coefficients(VTX_PAIR, -1.0, 2.0, coef.data()) == VTX_EINVAL);
   // options and argument checks of every entry point
   vtx_opts o;
@@ -125,6 +139,14 @@ int main() {
   vtx_grid gb{ne, eps_bad.data(), wv.data()};
   const int rc_unsorted = vtx_rates_forward(&gb, &o, 1, d, d, d, d, d, nullptr);
   EXPECT(rc_unsorted == VTX_EINVAL || rc_unsorted == VTX_EDEVICE);
+  EXPECT(vtx_rates_forward_mass(&g, &o, -1, d, d, d, d, d, nullptr) == VTX_EINVAL);
+  EXPECT(vtx_rates_forward_mass(&g, &o, 1, d, nullptr, d, d, d, nullptr) == VTX_EINVAL);
+  bad = o;
+  bad.precision = VTX_MIXED;
+  EXPECT(vtx_rates_forward_mass(&g, &bad, 1, d, d, d, d, d, nullptr) == VTX_EINVAL);
+  bad = o;
+  bad.rule = VTX_RULE_LAGUERRE;
+  EXPECT(vtx_rates_forward_mass(&g, &bad, 1, d, d, d, d, d, nullptr) == VTX_EINVAL);
   // valid arguments stop at the device check (no GPU here)
   const int rc = vtx_rates_forward(&g, &o, 1, d, d, d, d, d, nullptr);
   EXPECT(rc == VTX_EDEVICE || rc == VTX_EHIP);

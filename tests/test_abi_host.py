@@ -211,3 +211,48 @@ def test_one_hip_runtime_whatever_the_import_order():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def _mass_interval(proc, a, b, E, m):
+    """(k0, k1) of the momentum-transfer interval with the electron mass (0, 0 if closed)."""
+    with np.errstate(invalid="ignore", divide="ignore"):
+        if proc == vtx.VTX_NES:
+            Ep = E + a - b
+            P, Pp = np.sqrt(np.maximum(E * E - m * m, 0)), np.sqrt(np.maximum(Ep * Ep - m * m, 0))
+            return (Pp - P), np.minimum(a + b, P + Pp)
+        Eb = a + b - E
+        P, Pb = np.sqrt(np.maximum(E * E - m * m, 0)), np.sqrt(np.maximum(Eb * Eb - m * m, 0))
+        return np.maximum(abs(a - b), np.abs(P - Pb)), P + Pb
+
+
+def test_hmass_tables_match_oracle():
+    """The generated Laurent coefficients of the electron-mass weights (exact route) against the
+    oracle's weights, where the kernels take that route: intervals longer than a quarter of
+    their distance from k = 0."""
+    from oracle import massive
+    rng = np.random.default_rng(6)
+    eps, _ = synth.energy_grid(21, 2.0, 380.0)
+    eps = np.concatenate([[0.3, 0.6, 1.1], eps])
+    m = massive.ME
+    n_checked = 0
+    for _ in range(80):
+        i, j = sorted(rng.integers(0, eps.size, 2))[::-1]
+        e, ep = eps[i], eps[j]
+        E = m + np.concatenate([rng.uniform(0.0, 2 * ep, 30), rng.uniform(0, 4 * e + 50, 30)])
+        for proc, fn in ((vtx.VTX_NES, massive.h_nes), (vtx.VTX_PAIR, massive.h_pair)):
+            for a, b in ((e, ep), (ep, e)):
+                if proc == vtx.VTX_NES and a < b:
+                    continue
+                Ev = E if proc == vtx.VTX_NES else np.clip(E, m, a + b - m)
+                k0, k1 = _mass_interval(proc, a, b, Ev, m)
+                Ev = Ev[(k1 - k0) > 0.25 * k0]
+                if Ev.size == 0:
+                    continue
+                n_checked += Ev.size
+                scale = sum(np.abs(fn(0, S, a, b, Ev)) for S in (1, 2, 3)) + 1e-300
+                for comp in range(6):
+                    S, l = (1 + comp // 2, comp % 2) if comp < 4 else (3, comp - 4)
+                    got = vtx.eval_hmass(proc, comp, a, b, Ev)
+                    ref = fn(l, S, a, b, Ev)
+                    assert np.all(np.abs(got - ref) <= 1e-10 * scale), (proc, a, b, comp)
+    assert n_checked > 2000

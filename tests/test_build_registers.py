@@ -9,7 +9,8 @@ device code with the library's own flags and reads the code-object metadata:
 * no kernel uses scratch (private segment) or spills VGPRs;
 * the FP32 forward and interpolation kernels fit five waves per SIMD (at most 96 VGPRs);
 * the FP32 backward and the FP64 forward fit three (at most 168);
-* the FP64 backward and the FP64 export of task values for tables fit two (at most 256).
+* the FP64 backward and the FP64 export of task values for tables fit two (at most 256);
+* the forward with the electron mass (FP64, one 256-lane workgroup per zone) fits two.
 """
 import os
 import re
@@ -30,6 +31,7 @@ BUDGET = [
     (r"rates_forward_kernelINS0_4Fp64ELi[01]E", 168),
     (r"rates_forward_kernelINS0_4Fp64ELi[23]E", 256),
     (r"rates_backward_kernelINS0_4Fp64", 256),
+    (r"rates_mass_kernel", 256),
 ]
 
 
@@ -37,12 +39,14 @@ BUDGET = [
 def kernels(tmp_path_factory):
     if not (os.path.exists(HIPCC) or shutil.which("hipcc")):
         pytest.skip("hipcc not available")
-    out = tmp_path_factory.mktemp("isa") / "vtx_kernels.s"
     flags = [f for f in build_lib.FLAGS if f not in ("-shared", "-fPIC")]
-    src = os.path.join(build_lib.CSRC, "vtx_kernels.hip")
-    subprocess.run([HIPCC] + flags + ["--cuda-device-only", "-S", "-o", str(out), src], check=True,
-                   capture_output=True)
-    text = out.read_text()
+    text = ""
+    for name in ("vtx_kernels", "vtx_massive"):
+        out = tmp_path_factory.mktemp("isa") / (name + ".s")
+        src = os.path.join(build_lib.CSRC, name + ".hip")
+        subprocess.run([HIPCC] + flags + ["--cuda-device-only", "-S", "-o", str(out), src], check=True,
+                       capture_output=True)
+        text += out.read_text()
     meta = {}
     for blk in text.split("  - .agpr_count")[1:]:
         name = re.search(r"\.name:\s+(\S+)", blk).group(1)

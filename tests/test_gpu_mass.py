@@ -1,0 +1,89 @@
+"""GPU parity of the forward with the electron mass (vtx_rates_forward_mass) against the FP64
+CPU oracle with the mass (oracle.massive through oracle.rates), needs a gfx950 GPU.
+
+Error as for the massless forward: |y - y_ref| / max(|y_ref|, 1e-3 A, 1e-290), A the sum of |terms|
+of y; bar 1e-6 (FP64). Cases: the cool-zone workload (bins from 0.5 MeV, T from 0.2 MeV, so
+pair thresholds, electron thresholds and mu_e below the rest mass all occur), the process
+masks, one bin, 32 bins at 64 nodes, extreme T and eta_e, and the options it refuses.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rates as orates
+from paper_1404_1719_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1404_1719_amd import vtx  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def check(inp, nquad, processes, label):
+    say(f"[gpu] forward with the electron mass {label}: nz={inp.T.shape[0]} ne={inp.eps.shape[0]} "
+        f"nquad={nquad} processes={processes}")
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts("fp64", nquad, "panel", processes)
+    eta, chi = vtx.forward_mass(grid, opts, to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f))
+    torch.cuda.synchronize()
+    e, c = eta.cpu().numpy(), chi.cpu().numpy()
+    oo = orates.Options(nquad=nquad, processes=processes, electron_mass=True)
+    re, rc, ae, ac = orates.forward_with_scale(inp.eps, inp.w, inp.T, inp.eta_e, inp.f, oo)
+    err_e = np.abs(e - re) / np.maximum(np.maximum(np.abs(re), 1e-3 * ae), 1e-290)
+    err_c = np.abs(c - rc) / np.maximum(np.maximum(np.abs(rc), 1e-3 * ac), 1e-290)
+    say(f"    max rel err eta0 {err_e[:, :, 0].max():.2e} eta1 {err_e[:, :, 1].max():.2e} "
+        f"chi0 {err_c[:, :, 0].max():.2e} chi1 {err_c[:, :, 1].max():.2e}")
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(c))
+    assert max(err_e.max(), err_c.max()) <= TOL
+    return e, c
+
+
+def test_cool_zones_all_processes():
+    check(synth.make_inputs("lowt", nzones=12), 48, 7, "lowt")
+
+
+@pytest.mark.parametrize("processes", [1, 2, 4])
+def test_process_masks(processes):
+    check(synth.subset(synth.make_inputs("lowt", nzones=12), np.arange(4)), 48, processes, "lowt-4")
+
+
+def test_edge_grids_and_states():
+    # one bin above the pair threshold and one below it
+    for e1 in (3.0, 0.4):
+        eps, w = np.array([e1]), np.array([1.5 * e1 ** 3])
+        T = np.array([0.1, 1.0, 5.0])
+        eta = np.array([-3.0, 4.0, 1.0])
+        f = np.full((3, 3, 2, 1), 0.3)
+        f[:, :, 1] = 0.05
+        check(synth.ZoneInputs(eps, w, T, eta, f), 16, 7, f"ne=1 eps={e1}")
+    # 32 bins from below the electron mass, 64 nodes; extreme temperatures and degeneracies
+    eps, w = synth.energy_grid(32, 0.2, 200.0)
+    T = np.array([0.05, 0.2, 1.0, 30.0, 80.0])
+    eta = np.array([-20.0, 45.0, 0.0, 3.0, 70.0])
+    _, _, f = synth.draw_zones(5, 32, eps, (1.0, 2.0), (0.0, 1.0), (-2.0, 10.0), 0.05, 99)
+    check(synth.ZoneInputs(eps, w, T, eta, f), 64, 7, "ne=32/n64 extremes")
+
+
+def test_refused_options():
+    inp = synth.make_inputs("lowt", nzones=2)
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
+    for opts in (vtx.make_opts("mixed", 48, "panel"), vtx.make_opts("fp64", 32, "laguerre")):
+        with pytest.raises(RuntimeError):
+            vtx.forward_mass(grid, opts, T, E, f)
