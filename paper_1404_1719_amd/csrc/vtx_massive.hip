@@ -14,12 +14,12 @@
 // sum c_{n,a} E^a k^n with n even in -4..6 (Laurent coefficients per task, host tables), and
 // H = Integral_{k0}^{k1} f dk. Two routes, by the length L = k1 - k0 of the momentum-transfer
 // interval against its distance k0 from k = 0 (the only singular point):
-//   long  (L > k0/4): exact, H = L sum c_{n,a} E^a h_n with h_n = (k1^{n+1} - k0^{n+1})/((n+1) L)
+//   long  (L > k0/16): exact, H = L sum c_{n,a} E^a h_n with h_n = (k1^{n+1} - k0^{n+1})/((n+1) L)
 //         formed from positive terms only; the node accumulates W B L E^a h_n into 16 moments
 //         and the task contracts them with its coefficients once, at the end;
-//   short (L <= k0/4): the Laurent terms cancel there, so f is evaluated directly from the
-//         cosines of the kinematics at 6 Gauss-Legendre points on [k0, k1] (the singular point
-//         lies at least 4 L away, Bernstein-ellipse radius >= 9 + 4 sqrt 5, error ~1e-12).
+//   short (L <= k0/16): the Laurent terms cancel there, so f is evaluated directly from the
+//         cosines of the kinematics at 4 Gauss-Legendre points on [k0, k1] (the singular point
+//         lies at least 16 L away, Bernstein-ellipse radius >= 33 + 8 sqrt 17, error ~1e-12).
 // The third structure, m^2 (q.q')/(e e') P_l(x), is a polynomial in k (n = 0, 2, 4): exact
 // on both routes.
 //
@@ -40,14 +40,30 @@ namespace vtx {
 namespace {
 
 constexpr int kMassBlock = 256;
-constexpr double kShortRatio = 0.25;   // short route when L <= kShortRatio k0
+constexpr double kShortRatio = 0.0625;   // short route when L <= kShortRatio k0
 constexpr int64_t kMassSlice = int64_t(1) << 22;   // zones per launch (grid x-dimension)
+
+// 1/x for finite x > 0: the hardware reciprocal refined by two Newton steps, to FP64
+// rounding, instead of the division sequence.
+__device__ __forceinline__ double recip_m(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+  return __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+}
 
 __device__ __forceinline__ int m_partner(int s) { return s == 2 ? 2 : 1 - s; }
 __device__ __forceinline__ int m_tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// 1 / (1 + exp(z)): exp overflows to +inf for large z and the quotient to 0.
-__device__ __forceinline__ double logistic_m(double z) { return 1.0 / (1.0 + exp(z)); }
+// Blocking factor sigma(z) sigma(K - z) of a node, sigma(z) = 1/(1 + e^-z): the two Fermi-Dirac
+// arguments of a task sum to the task constant K = D/T >= 0 (scattering D = omega, pair
+// D = eps_i + eps_j). With t the smaller argument (t <= K/2), a = e^t and C = e^-K,
+//   B = a / ((1 + a)(1 + C a)),
+// one exponential per node; C a <= 1 and t is capped at 700 (both factors are then 1 to FP64
+// precision), a very negative t gives a = 0 and B = 0.
+__device__ __forceinline__ double blocking_m(double z, double K, double C) {
+  const double a = exp(fmin(fmin(z, K - z), 700.0));
+  return a * recip_m((1.0 + a) * (1.0 + C * a));
+}
 
 __device__ __forceinline__ void sort3(double& a, double& b, double& c) {
   double t;
@@ -64,7 +80,7 @@ __device__ __forceinline__ void laurent_means(double x, double y, double h[6]) {
   const double s1 = x + y, s2 = x * s1 + y2, s3 = x * s2 + y3, s4 = x * s3 + y2 * y2, s5 = x * s4 + y2 * y3,
                s6 = x * s5 + y3 * y3;
   const bool pos = y > 0.0;
-  const double ixy = pos ? 1.0 / (x * y) : 0.0;
+  const double ixy = pos ? recip_m(x * y) : 0.0;
   h[0] = s2 * ixy * ixy * ixy * (1.0 / 3.0);
   h[1] = ixy;
   h[2] = 1.0;
@@ -104,6 +120,7 @@ __device__ __forceinline__ void add_long(Acc& A, double wbl, double E, const dou
 // scattering (q, q' on one side of k) and -1 for the pair; Mx the (S = I, S = II) structures.
 struct Kin {
   double e, ep, E, P2;
+  double ie, iep, iee;   // 1/e, 1/e', 1/(e e'): task constants
 };
 
 __device__ __forceinline__ void averages(const Kin& K, double pca, double cb, double cbp, double sbsb, double side,
@@ -115,12 +132,12 @@ __device__ __forceinline__ void averages(const Kin& K, double pca, double cb, do
 }
 
 __device__ __forceinline__ void nes_direct(const Kin& K, double om, double w, double A_, double k, double v[4]) {
-  const double ik = 1.0 / k;
+  const double ik = recip_m(k);
   const double Q2 = (k - om) * (k + om);
-  const double iee = 1.0 / (K.e * K.ep);
+  const double iee = K.iee;
   const double x = 1.0 - 0.5 * Q2 * iee;
   const double pca = 0.5 * (A_ - k * k) * ik;
-  const double cb = 0.5 * (w * om + k * k) * ik / K.e, cbp = 0.5 * (w * om - k * k) * ik / K.ep;
+  const double cb = 0.5 * (w * om + k * k) * ik * K.ie, cbp = 0.5 * (w * om - k * k) * ik * K.iep;
   const double sbsb = 0.25 * Q2 * (w - k) * (w + k) * iee * ik * ik;
   double qp, qpp, qqp;
   averages(K, pca, cb, cbp, sbsb, 1.0, qp, qpp, qqp);
@@ -132,13 +149,13 @@ __device__ __forceinline__ void nes_direct(const Kin& K, double om, double w, do
 }
 
 __device__ __forceinline__ void pair_direct(const Kin& K, double d, double w, double k, double v[4]) {
-  const double ik = 1.0 / k;
+  const double ik = recip_m(k);
   const double s = (w - k) * (w + k);
-  const double iee = 1.0 / (K.e * K.ep);
+  const double iee = K.iee;
   const double x = 1.0 - 0.5 * s * iee;
   const double ad = fabs(d);
   const double pca = 0.5 * (k * k + (2.0 * K.E - w) * w) * ik;
-  const double cb = 0.5 * (d * w + k * k) * ik / K.e, cbp = 0.5 * (k * k - d * w) * ik / K.ep;
+  const double cb = 0.5 * (d * w + k * k) * ik * K.ie, cbp = 0.5 * (k * k - d * w) * ik * K.iep;
   const double sbsb = 0.25 * s * (k - ad) * (k + ad) * iee * ik * ik;
   double qp, qpp, qqp;
   averages(K, pca, cb, cbp, sbsb, -1.0, qp, qpp, qqp);
@@ -164,6 +181,7 @@ __device__ __forceinline__ void node_mass(const DevPlan& P, Acc& A, const Kin& K
     A.M3[0] += wbl;
     A.M3[1] += wbl * h[3];
     A.M3[2] += wbl * h[4];
+#pragma unroll 1
     for (int g = 0; g < kMassGauss; ++g) {
       const double2 gk = P.mass_gauss[g];   // (t, w) on [0, 1]
       const double k = k0 + L * gk.x;
@@ -212,13 +230,17 @@ __device__ void nes_task(const DevPlan& P, int t, double T, double mu, double q[
   Kin K;
   K.e = e;
   K.ep = ep;
+  K.ie = P.inv_eps[i];
+  K.iep = P.inv_eps[j];
+  K.iee = K.ie * K.iep;
+  const double Kt = om * invT, Ct = exp(-Kt);
   auto node = [&](double E, double W) {
-    const double B = logistic_m((E - mu) * invT) * logistic_m((mu - E - om) * invT);
+    const double B = blocking_m((mu - E) * invT, Kt, Ct);
     const double Ep = E + om;
     const double Pn = sqrt((E - m) * (E + m)), Pp = sqrt((Ep - m) * (Ep + m));
     const double sp = Pn + Pp;
     const double A_ = (2.0 * E + om) * om;
-    const double k0 = sp > 0.0 ? A_ / sp : 0.0;
+    const double k0 = sp > 0.0 ? A_ * recip_m(sp) : 0.0;
     K.E = E;
     K.P2 = (E - m) * (E + m);
     node_mass<false>(P, A, K, W * B, k0, fmin(w, sp), om, w, A_);
@@ -250,6 +272,7 @@ __device__ void pair_task(const DevPlan& P, int t, double T, double mu, double q
     return;
   }
   const double invT = 1.0 / T, span = w - 2.0 * m, top = w - m;
+  const double Kp = w * invT, Cp = exp(-Kp);
   double b1 = fmin(fmax(C.k0, m), top), b2 = fmin(fmax(C.k1, m), top), b3 = fmin(fmax(mu, m), top);
   sort3(b1, b2, b3);
   auto theta = [&](double b) { return acos(fmin(fmax(1.0 - 2.0 * (b - m) / span, -1.0), 1.0)) / M_PI; };
@@ -259,6 +282,9 @@ __device__ void pair_task(const DevPlan& P, int t, double T, double mu, double q
   Kin K;
   K.e = e;
   K.ep = ep;
+  K.ie = P.inv_eps[i];
+  K.iep = P.inv_eps[j];
+  K.iee = K.ie * K.iep;
   for (int p = 0; p < 4; ++p) {
     const double ta = th[p], dt = th[p + 1] - th[p];
     for (int k = 0; k < P.m4; ++k) {
@@ -267,10 +293,10 @@ __device__ void pair_task(const DevPlan& P, int t, double T, double mu, double q
       const double sh = sinpi(0.5 * v);
       const double E = m + span * sh * sh, Eb = w - E;
       const double W = dt * g.z * span * 0.5 * M_PI * sinpi(v);
-      const double B = logistic_m((mu - E) * invT) * logistic_m(-(Eb + mu) * invT);
+      const double B = blocking_m((E - mu) * invT, Kp, Cp);
       const double Pn = sqrt((E - m) * (E + m)), Pb = sqrt((Eb - m) * (Eb + m));
       const double sp = Pn + Pb;
-      const double k0 = fmax(fabs(d), fabs((2.0 * E - w) * w) / sp);
+      const double k0 = fmax(fabs(d), fabs((2.0 * E - w) * w) * recip_m(sp));
       K.E = E;
       K.P2 = (E - m) * (E + m);
       node_mass<true>(P, A, K, W * B, k0, sp, d, w, 0.0);
