@@ -12,10 +12,11 @@
 //
 // ray_system_kernel assembles D_r and -G_r (one zone per workgroup; HBM-write bound, like the
 // Jacobian blocks). ray_solve_kernel eliminates along each ray (one ray per workgroup): the
-// Schur complement M_r = D_r - diag(lo_r) M_{r-1}^{-1} diag(up_{r-1}) is built in LDS and inverted
-// there by Gauss-Jordan elimination with partial pivoting (FP64), M_r^{-1} overwrites D_r for
-// the back substitution x_r = y_r + M_r^{-1} (up_r x_{r+1}). The blocks are small dense
-// inversions with pivoting, one after another along the ray: FP64 vector arithmetic in LDS.
+// Schur complement M_r = D_r - diag(lo_r) M_{r-1}^{-1} diag(up_{r-1}) is built in registers and
+// inverted there by Gauss-Jordan elimination with partial pivoting (FP64), M_r^{-1} overwrites D_r
+// for the back substitution x_r = y_r + M_r^{-1} (up_r x_{r+1}). The blocks are small dense
+// inversions with pivoting, one after another along the ray: FP64 vector arithmetic, the block
+// held in the registers of a 1024-lane workgroup, pivot rows and columns exchanged through LDS.
 #include <hip/hip_runtime.h>
 
 #include "../../include/vtx_rates.h"
@@ -100,19 +101,103 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// In-place inverse of the nb x nb matrix M (row-major, LDS) by Gauss-Jordan elimination with
-// partial (row) pivoting: column k takes the row of largest |M[i][k]|, i >= k (the first on ties);
-// the row swaps are undone on the columns of the result at the end. col: nb doubles of LDS.
-__device__ void invert_in_lds(double* M, int nb, double* col, int* perm) {
+// Block elimination along a ray (one ray per 1024-lane workgroup). The Schur complement
+// M_r = D_r - diag(lo_r) M_{r-1}^{-1} diag(up_{r-1}) lives in registers: lane l of wave w holds
+// the entries (i, j) with j = l + 64 h (h < kSolveH) and i = w + 16 c (c < kSolveC), so a wave
+// reads its rows' pivot-column entries as LDS broadcasts and its lanes read consecutive entries
+// of the pivot row. It is inverted in place by Gauss-Jordan elimination with partial pivoting
+// done implicitly: step k takes, among the rows not yet used, the one with the largest |M[i][k]|
+// (the lowest index on ties) and eliminates column k from every other row, without moving any
+// row. That is the in-place elimination of P M (P the pivot order, row k of P M = row pi(k) of
+// M), so the registers end with Z[pi(a)][j] = ((P M)^-1)[a][j] = M^-1[a][pi(j)]: entry (i, j)
+// of Z is M^-1[pi^-1(i)][pi(j)]. The inverse is staged in LDS in its own order, copied to D_r for
+// the back substitution and used for the next zone's Schur complement and for y_r.
+constexpr int kSolveBlock = 1024, kSolveWaves = kSolveBlock / 64;
+constexpr int kMaxNb = 140;   // nb^2 + 5 nb doubles of LDS and the pivot maps within 160 KiB
+constexpr int kSolveH = (kMaxNb + 63) / 64, kSolveC = (kMaxNb + kSolveWaves - 1) / kSolveWaves;
+
+// out[i] = sum_j A[i][j] w[j] + add[i] for an nb x nb row-major A (LDS or global): wave w takes
+// rows w, w + 16, ...; its lanes split j and sum by shuffles.
+__device__ __forceinline__ void matvec(const double* A, const double* w, const double* add, double* out, int nb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wave; i < nb; i += nw) {
+    double s = 0.0;
+    for (int j = lane; j < nb; j += 64) s += A[(int64_t)i * nb + j] * w[j];
+    s = wave_sum64(s);
+    if (lane == 0) out[i] = s + add[i];
+  }
+}
+
+__global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t nrays, int nzr,
+                                                                const double* __restrict__ lo,
+                                                                double* __restrict__ D,
+                                                                const double* __restrict__ up,
+                                                                double* __restrict__ rhs) {
+  const int64_t ray = blockIdx.x;
+  if (ray >= nrays) return;
+  extern __shared__ double sm[];
+  __shared__ int piv[kMaxNb];    // piv[k]: the row pivoted at step k
+  __shared__ int step[kMaxNb];   // step[i]: the step that pivoted row i, -1 while unused
+  const int nb2 = nb * nb;
+  double* Inv = sm;              // [nb][nb] the inverse of the zone's block, logical order
+  double* colb = Inv + nb2;      // 2 x [nb] pivot columns (alternate steps); w of the back substitution
+  double* rowb = colb + 2 * nb;  // [nb] normalised pivot row
+  double* v = rowb + nb;         // right-hand side of the zone, then x of the zone above
+  double* y = v + nb;            // y_r
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int k = 0; k < nb; ++k) {
-    if (wave == 0) {
+  double* Dray = D + ray * nzr * (int64_t)nb2;
+  double* bray = rhs + ray * nzr * (int64_t)nb;
+  const double* lray = lo + ray * nzr * (int64_t)nb;
+  const double* uray = up + ray * nzr * (int64_t)nb;
+  double a[kSolveC][kSolveH];
+  for (int r = 0; r < nzr; ++r) {
+    double* Dr = Dray + (int64_t)r * nb2;
+    const double* lr = lray + (int64_t)r * nb;
+    const double* um = uray + (int64_t)(r - 1) * nb;
+    // M_r, formed in LDS over M_{r-1}^{-1} (coalesced reads of D_r), then into registers
+    for (int e = tid; e < nb2; e += blockDim.x) {
+      double m = Dr[e];
+      if (r > 0) {
+        const int i = e / nb, j = e - i * nb;
+        m -= lr[i] * Inv[e] * um[j];
+      }
+      Inv[e] = m;
+    }
+    for (int i = tid; i < nb; i += blockDim.x) {
+      v[i] = bray[(int64_t)r * nb + i] + (r > 0 ? lr[i] * y[i] : 0.0);
+      step[i] = -1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kSolveC; ++c) {
+      const int i = wave + kSolveWaves * c;
+#pragma unroll
+      for (int h = 0; h < kSolveH; ++h) {
+        const int j = lane + 64 * h;
+        a[c][h] = (i < nb && j < nb) ? Inv[i * nb + j] : 0.0;
+      }
+    }
+    for (int k = 0; k < nb; ++k) {
+      double* cb = colb + (k & 1) * nb;
+      // the pivot column, before this step's update: lane k % 64 of every wave holds it
+      const int hk = k >> 6;
+      if (lane == (k & 63)) {
+#pragma unroll
+        for (int c = 0; c < kSolveC; ++c) {
+          const int i = wave + kSolveWaves * c;
+#pragma unroll
+          for (int h = 0; h < kSolveH; ++h)
+            if (h == hk && i < nb) cb[i] = a[c][h];
+        }
+      }
+      __syncthreads();
+      // every wave finds the pivot row: the unused row of largest |M[i][k]|, lowest index on ties
       double best = -1.0;
-      int bi = k;
-      for (int i = k + lane; i < nb; i += 64) {
-        const double a = fabs(M[i * nb + k]);
-        if (a > best) {
-          best = a;
+      int bi = nb;
+      for (int i = lane; i < nb; i += 64) {
+        const double x = fabs(cb[i]);
+        if (step[i] < 0 && (x > best || (x == best && i < bi))) {
+          best = x;
           bi = i;
         }
       }
@@ -124,105 +209,70 @@ __device__ void invert_in_lds(double* M, int nb, double* col, int* perm) {
           bi = oi;
         }
       }
-      if (lane == 0) perm[k] = bi;
-    }
-    __syncthreads();
-    const int p = perm[k];
-    if (p != k) {   // uniform
-      for (int j = tid; j < nb; j += blockDim.x) {
-        const double t = M[k * nb + j];
-        M[k * nb + j] = M[p * nb + j];
-        M[p * nb + j] = t;
+      const int p = __builtin_amdgcn_readfirstlane(bi);
+      const double pinv = 1.0 / cb[p];
+      // the wave holding row p writes the normalised pivot row; the pivot column takes 1/pivot
+      if (wave == (p % kSolveWaves)) {
+        const int cp = p / kSolveWaves;
+#pragma unroll
+        for (int c = 0; c < kSolveC; ++c) {
+          if (c != cp) continue;
+#pragma unroll
+          for (int h = 0; h < kSolveH; ++h) {
+            const int j = lane + 64 * h;
+            if (j < nb) rowb[j] = j == k ? pinv : a[c][h] * pinv;
+          }
+        }
       }
       __syncthreads();
+      // every wave has its pivot (the search read the pivot maps): record it
+      if (tid == 0) {
+        piv[k] = p;
+        step[p] = k;
+      }
+      // eliminate column k from every row but p; row p becomes the normalised row
+#pragma unroll
+      for (int c = 0; c < kSolveC; ++c) {
+        const int i = wave + kSolveWaves * c;
+        if (i >= nb) continue;
+        const double fi = cb[i];
+#pragma unroll
+        for (int h = 0; h < kSolveH; ++h) {
+          const int j = lane + 64 * h;
+          if (j >= nb) continue;
+          const double rj = rowb[j];
+          a[c][h] = i == p ? rj : (j == k ? 0.0 : a[c][h]) - fi * rj;
+        }
+      }
+      // the next step writes the other column buffer before its first barrier; the pivot row
+      // only after that barrier, which every lane reaches after this update, and the pivot
+      // maps are read again only after it
     }
-    const double pinv = 1.0 / M[k * nb + k];
-    __syncthreads();   // every lane has read the pivot before row k changes
-    for (int t = tid; t < 2 * nb; t += blockDim.x) {
-      if (t < nb) {
-        if (t != k) col[t] = M[t * nb + k];
-      } else {
-        const int j = t - nb;
-        M[k * nb + j] = (j == k ? 1.0 : M[k * nb + j]) * pinv;
+    __syncthreads();
+    // Inv[a][b] = Z[pi(a)][pi^-1(b)]: entry (i, j) of the registers goes to Inv[step[i]][piv[j]]
+#pragma unroll
+    for (int c = 0; c < kSolveC; ++c) {
+      const int i = wave + kSolveWaves * c;
+      if (i >= nb) continue;
+      const int ai = step[i];
+#pragma unroll
+      for (int h = 0; h < kSolveH; ++h) {
+        const int j = lane + 64 * h;
+        if (j < nb) Inv[ai * nb + piv[j]] = a[c][h];
       }
     }
     __syncthreads();
-    for (int e = tid; e < nb * nb; e += blockDim.x) {
-      const int i = e / nb, j = e - i * nb;
-      if (i != k) M[e] = (j == k ? 0.0 : M[e]) - col[i] * M[k * nb + j];
-    }
-    __syncthreads();
-  }
-  for (int k = nb - 1; k >= 0; --k) {
-    const int p = perm[k];
-    if (p != k) {   // uniform
-      for (int i = tid; i < nb; i += blockDim.x) {
-        const double t = M[i * nb + k];
-        M[i * nb + k] = M[i * nb + p];
-        M[i * nb + p] = t;
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// out[i] = sum_j A[i][j] w[j] + add[i] for an nb x nb row-major A (LDS or global): wave w takes
-// rows w, w + 4, ...; its lanes split j and sum by shuffles.
-__device__ __forceinline__ void matvec(const double* A, const double* w, const double* add, double* out, int nb) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = wave; i < nb; i += nw) {
-    double s = 0.0;
-    for (int j = lane; j < nb; j += 64) s += A[(int64_t)i * nb + j] * w[j];
-    s = wave_sum64(s);
-    if (lane == 0) out[i] = s + add[i];
-  }
-}
-
-constexpr int kMaxNb = 140;   // nb^2 + 4 nb doubles and the pivot rows within the 160 KiB of LDS
-
-__global__ __launch_bounds__(kNBlock) void ray_solve_kernel(int nb, int64_t nrays, int nzr,
-                                                            const double* __restrict__ lo, double* __restrict__ D,
-                                                            const double* __restrict__ up,
-                                                            double* __restrict__ rhs) {
-  const int64_t ray = blockIdx.x;
-  if (ray >= nrays) return;
-  extern __shared__ double sm[];
-  __shared__ int perm[kMaxNb];
-  const int nb2 = nb * nb;
-  double* M = sm;          // [nb][nb]
-  double* v = M + nb2;     // right-hand side of the zone, then x of the zone above
-  double* y = v + nb;      // y_r
-  double* w = y + nb;      // scaled vector of the back substitution
-  double* col = w + nb;    // pivot column
-  const int tid = threadIdx.x;
-  double* Dray = D + ray * nzr * (int64_t)nb2;
-  double* bray = rhs + ray * nzr * (int64_t)nb;
-  const double* lray = lo + ray * nzr * (int64_t)nb;
-  const double* uray = up + ray * nzr * (int64_t)nb;
-  for (int r = 0; r < nzr; ++r) {
-    double* Dr = Dray + (int64_t)r * nb2;
-    const double* lr = lray + (int64_t)r * nb;
-    const double* um = uray + (int64_t)(r - 1) * nb;
-    // M holds M_{r-1}^{-1}: M_r = D_r - diag(lo_r) M_{r-1}^{-1} diag(up_{r-1}), in place
-    for (int e = tid; e < nb2; e += blockDim.x) {
-      const int i = e / nb, j = e - i * nb;
-      double m = Dr[e];
-      if (r > 0) m -= lr[i] * M[e] * um[j];
-      M[e] = m;
-    }
-    for (int i = tid; i < nb; i += blockDim.x) v[i] = bray[(int64_t)r * nb + i] + (r > 0 ? lr[i] * y[i] : 0.0);
-    __syncthreads();
-    invert_in_lds(M, nb, col, perm);
     // y_r = M_r^{-1} v; M_r^{-1} replaces D_r for the back substitution, y_r the right-hand side
-    for (int i = tid; i < nb; i += blockDim.x) w[i] = 0.0;
+    for (int e = tid; e < nb2; e += blockDim.x) Dr[e] = Inv[e];
+    for (int i = tid; i < nb; i += blockDim.x) colb[i] = 0.0;
     __syncthreads();
-    matvec(M, v, w, y, nb);
-    for (int e = tid; e < nb2; e += blockDim.x) Dr[e] = M[e];
+    matvec(Inv, v, colb, y, nb);
     __syncthreads();
     for (int i = tid; i < nb; i += blockDim.x) bray[(int64_t)r * nb + i] = y[i];
     __syncthreads();
   }
   // back substitution: x_{N-1} = y_{N-1}; x_r = y_r + M_r^{-1} (up_r x_{r+1}); x kept in v
+  double* w = colb;
   for (int i = tid; i < nb; i += blockDim.x) v[i] = y[i];
   __syncthreads();
   for (int r = nzr - 2; r >= 0; --r) {
@@ -264,14 +314,14 @@ int max_block() { return kMaxNb; }
 
 hipError_t launch_ray_solve(int nb, int64_t nrays, int nzr, const double* lo, double* D, const double* up,
                             double* rhs, hipStream_t s) {
-  const size_t lds = sizeof(double) * ((size_t)nb * nb + 4 * (size_t)nb);
+  const size_t lds = sizeof(double) * ((size_t)nb * nb + 5 * (size_t)nb);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ray_solve_kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   for (int64_t r0 = 0; r0 < nrays; r0 += (int64_t(1) << 22)) {
     const int64_t n = nrays - r0 < (int64_t(1) << 22) ? nrays - r0 : (int64_t(1) << 22);
     const int64_t per = (int64_t)nzr * nb;
-    hipLaunchKernelGGL(ray_solve_kernel, dim3((unsigned)n), dim3(kNBlock), lds, s, nb, n, nzr, lo + r0 * per,
+    hipLaunchKernelGGL(ray_solve_kernel, dim3((unsigned)n), dim3(kSolveBlock), lds, s, nb, n, nzr, lo + r0 * per,
                        D + r0 * per * nb, up + r0 * per, rhs + r0 * per);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -16,6 +16,10 @@ sum over outputs of |g| times the Jacobian entries taken as sums of absolute qua
 (|H| in the kernels), the gradient's counterpart of Aq; and a hash of the oracle's and the
 sampler's sources, which the CPU tests compare with the current files.
 
+The cool-zone workload (lowt) gets a reference of the forward with the electron mass: a
+stratified sample of 512 zones, eta, chi and their scales A (the oracle's oracle/massive.py is
+in its hash).
+
 Calls only oracle/ and the seeded input generators. Usage (about ten minutes on 8 cores):
     python tests/golden/make_reference.py [--workers 8] [--only large] [--grad-scale-only]
 (--grad-scale-only adds aq_g_f to existing files written from the same oracle sources.)
@@ -37,6 +41,8 @@ from paper_1404_1719_amd import synth  # noqa: E402
 
 # workload -> (forward sample, backward sub-sample)
 PLAN = {"large": (4096, 512), "medium": (1024, 128)}
+# the forward with the electron mass (no backward): workload -> forward sample
+PLAN_MASS = {"lowt": 512}
 GRAD_SEED = 7
 SAMPLE_SEED = 0
 
@@ -46,10 +52,10 @@ SOURCES = ("oracle/angular.py", "oracle/grad.py", "oracle/physics.py", "oracle/r
            "paper_1404_1719_amd/synth.py")
 
 
-def source_hash():
+def source_hash(extra=()):
     """sha256 over the sources the stored values depend on (oracle modules, input generator)."""
     h = hashlib.sha256()
-    files = [os.path.join(ROOT, f) for f in SOURCES]
+    files = [os.path.join(ROOT, f) for f in SOURCES + tuple(extra)]
     for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
@@ -149,6 +155,33 @@ def add_grad_scale(name, workers):
     print(f"[ref] {name}: aq_g_f added ({time.time() - t0:.0f} s)", flush=True)
 
 
+def _fwd_mass(args):
+    from oracle import rates as orates
+    eps, w, T, E, f, nquad, rule = args
+    return orates.forward_with_scale(eps, w, T, E, f, orates.Options(nquad=nquad, rule=rule, electron_mass=True))
+
+
+def make_mass(name, workers):
+    """Forward with the electron mass on a stratified sample (default processes), outputs and
+    their output-level scales A."""
+    wl = synth.WORKLOADS[name]
+    t0 = time.time()
+    inp = synth.make_inputs(name)
+    idx = synth.sample_zones_stratified(inp, PLAN_MASS[name], SAMPLE_SEED)
+    sub = synth.subset(inp, idx)
+    del inp
+    pieces = np.array_split(np.arange(len(idx)), 8 * workers)
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        fw = list(ex.map(_fwd_mass, [(sub.eps, sub.w, sub.T[p], sub.eta_e[p], sub.f[p], wl.nquad, wl.rule)
+                                     for p in pieces]))
+    eta, chi, ae, ac = (np.concatenate([r[k] for r in fw]) for k in range(4))
+    np.savez_compressed(path(name), workload=name, source_hash=source_hash(("oracle/massive.py",)), idx=idx,
+                        T=sub.T, eta_e=sub.eta_e, eta=eta, chi=chi, a_eta=ae.astype(np.float32),
+                        a_chi=ac.astype(np.float32))
+    print(f"[ref] {name}: written {path(name)} ({os.path.getsize(path(name)) / 1e6:.1f} MB, "
+          f"{time.time() - t0:.0f} s)", flush=True)
+
+
 def load(name):
     """The stored reference of a workload as a dict of arrays (no pickle)."""
     with np.load(path(name), allow_pickle=False) as z:
@@ -158,9 +191,12 @@ def load(name):
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=min(8, os.cpu_count() or 1))
-    ap.add_argument("--only", default=None, choices=sorted(PLAN))
+    ap.add_argument("--only", default=None, choices=sorted(PLAN) + sorted(PLAN_MASS))
     ap.add_argument("--grad-scale-only", action="store_true")
     a = ap.parse_args()
     for n in PLAN:
         if a.only in (None, n):
             (add_grad_scale if a.grad_scale_only else make)(n, a.workers)
+    for n in PLAN_MASS:
+        if a.only in (None, n) and not a.grad_scale_only:
+            make_mass(n, a.workers)

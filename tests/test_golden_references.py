@@ -46,6 +46,19 @@ def test_reference_is_current_and_whole(name):
         assert np.sum((E > 30) & (T < 2)) >= (nf // 10 if name == "large" else 1)
 
 
+def test_electron_mass_reference_is_current_and_whole():
+    ref = make_reference.load("lowt")
+    assert str(ref["source_hash"]) == make_reference.source_hash(("oracle/massive.py",))
+    n = make_reference.PLAN_MASS["lowt"]
+    assert ref["idx"].shape == (n,) and np.all(np.diff(ref["idx"]) > 0)
+    assert ref["eta"].shape == (n, 3, 2, synth.WORKLOADS["lowt"].ne)
+    for k in ("eta", "chi", "a_eta", "a_chi"):
+        assert np.all(np.isfinite(ref[k])), k
+    inp = synth.make_inputs("lowt")
+    assert np.array_equal(synth.sample_zones_stratified(inp, n, make_reference.SAMPLE_SEED), ref["idx"])
+    assert np.array_equal(inp.T[ref["idx"]], ref["T"])
+
+
 def test_medium_reference_reproduces():
     from oracle import grad as ograd
     from oracle import rates as orates

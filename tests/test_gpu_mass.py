@@ -87,3 +87,27 @@ def test_refused_options():
     for opts in (vtx.make_opts("mixed", 48, "panel"), vtx.make_opts("fp64", 32, "laguerre")):
         with pytest.raises(RuntimeError):
             vtx.forward_mass(grid, opts, T, E, f)
+
+
+def test_full_cool_zone_workload_stored_reference():
+    """The whole cool-zone workload (102,400 zones) in one launch, as the benchmark times it,
+    against the stored oracle outputs on its 512 stratified zones (tests/golden/ref_lowt.npz)."""
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_reference
+    ref = make_reference.load("lowt")
+    wl = synth.WORKLOADS["lowt"]
+    inp = synth.make_inputs("lowt")
+    say(f"[gpu] forward with the electron mass, full lowt: {inp.T.shape[0]} zones, {ref['idx'].size} stored")
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    opts = vtx.make_opts("fp64", wl.nquad, wl.rule)
+    eta, chi = vtx.forward_mass(grid, opts, to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f))
+    torch.cuda.synchronize()
+    it = torch.from_numpy(ref["idx"]).to(DEV)
+    e, c = eta.index_select(0, it).cpu().numpy(), chi.index_select(0, it).cpu().numpy()
+    err_e = np.abs(e - ref["eta"]) / np.maximum(np.maximum(np.abs(ref["eta"]), 1e-3 * ref["a_eta"]), 1e-290)
+    err_c = np.abs(c - ref["chi"]) / np.maximum(np.maximum(np.abs(ref["chi"]), 1e-3 * ref["a_chi"]), 1e-290)
+    say(f"    max rel err eta0 {err_e[:, :, 0].max():.2e} eta1 {err_e[:, :, 1].max():.2e} "
+        f"chi0 {err_c[:, :, 0].max():.2e} chi1 {err_c[:, :, 1].max():.2e}")
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(c))
+    assert max(err_e.max(), err_c.max()) <= TOL
