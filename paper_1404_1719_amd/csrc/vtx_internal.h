@@ -16,7 +16,7 @@ constexpr double kKappa = 10.0;
 constexpr double kGF = 1.1663787e-11;        // MeV^-2
 constexpr double kHbarC = 1.973269804e-11;   // MeV cm
 constexpr double kMe = 0.51099895;           // electron mass, MeV
-constexpr int kMassGauss = 4;                // points of the short momentum-transfer route
+constexpr int kMassGauss = 5;                // points of the short momentum-transfer route
 
 // Angular-weight coefficients of one scattering task (eps_i >= eps_j), comps
 // (S, l) = (I,0), (I,1), (II,0), (II,1); variable u = E / eps_j.

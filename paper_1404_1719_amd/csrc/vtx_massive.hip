@@ -18,8 +18,8 @@
 //         formed from positive terms only; the node accumulates W B L E^a h_n into 16 moments
 //         and the task contracts them with its coefficients once, at the end;
 //   short (L <= k0/16): the Laurent terms cancel there, so f is evaluated directly from the
-//         cosines of the kinematics at 4 Gauss-Legendre points on [k0, k1] (the singular point
-//         lies at least 16 L away, Bernstein-ellipse radius >= 33 + 8 sqrt 17, error ~1e-12).
+//         cosines of the kinematics at 5 Gauss-Legendre points on [k0, k1] (the singular point
+//         lies at least 16 L away, Bernstein-ellipse radius >= 33 + 8 sqrt 17, error ~1e-15).
 // The third structure, m^2 (q.q')/(e e') P_l(x), is a polynomial in k (n = 0, 2, 4): exact
 // on both routes.
 //
