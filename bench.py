@@ -2,8 +2,8 @@
 
 One step = forward (eta, chi) + backward (g_T, g_eta_e, g_f) over every zone of the
 workload, inputs resident in HBM, in 8 chunks issued back to back on one compute stream.
-Default workload: 4096 rays x 600 zones, NE = 21, 64-node rule, mixed precision with FP64
-Fermi-Dirac factors for |eta_e| > 30. Prints ONE JSON line. Units: zones * NE^2 per second
+Default workload: 4096 rays x 600 zones, NE = 21, 64-node rule, mixed precision (zones with
+|eta_e| > 30 entirely in FP64). Prints ONE JSON line. Units: zones * NE^2 per second
 (each unit covers 3 species, both processes, l = 0, 1, one forward and one backward
 evaluation).
 
@@ -14,7 +14,7 @@ stratified zones forward and 512 backward, with the stratum eta_e > 30, T < 2 Me
 a roofline entry for the dominant launch; the oracle timed on the host cores on a bounded
 sample; the whole step end to end with the workload in pinned host memory, streamed through
 the GPU in 8 chunks (package stream.Streamer, PCIe transfers included); the mixed path with
-the FP64 Fermi-Dirac threshold at 64 instead of 30; the explicit Jacobian blocks over one
+the FP64 zone-class threshold at 64 instead of 30; the explicit Jacobian blocks over one
 chunk; the tabulated comparison; all three processes; the fused forward + backward call.
 """
 import argparse
@@ -395,8 +395,8 @@ def mass_leg(launches):
 
 
 def newton_leg(inp, wl, precision, nrays):
-    """Newton step of the radial sweep over nrays rays x the workload's radial zones (one chunk's
-    worth of the first zones): the rates and their explicit blocks (vtx_rates_jacobian), the
+    """Newton step of the radial sweep over nrays rays (at most the workload's) x the workload's
+    radial zones (the first zones): the rates and their explicit blocks (vtx_rates_jacobian), the
     system (vtx_ray_system) and the block-tridiagonal solve (vtx_ray_solve), each timed with HIP
     events on its stream. Time step and radial coupling on the rates' scale (dt = 1/kappa,
     lo, up ~ kappa U(0, 1/2), kappa the median opacity). Algorithmic work of the solve: per zone
@@ -405,6 +405,7 @@ def newton_leg(inp, wl, precision, nrays):
     import torch
     from paper_1404_1719_amd import vtx
     nzr = wl.radial
+    nrays = min(nrays, wl.rays)
     nz = nrays * nzr
     ne, nb = wl.ne, 6 * wl.ne
     dev = torch.device("cuda:0")
@@ -443,8 +444,8 @@ def newton_leg(inp, wl, precision, nrays):
            "solve_frac_fp64_peak": flops / (t_solve * 1e-3) / 78.6e12,
            "solve_GBps": solve_bytes / (t_solve * 1e-3) / 1e9, "solution_finite": finite,
            "note": "one Newton update of the BDF2 radial system along each ray; solve = block "
-                   "elimination with Gauss-Jordan inversion of each diagonal block in LDS, one ray per "
-                   "workgroup"}
+                   "elimination with Gauss-Jordan inversion of each diagonal block in the registers of "
+                   "one 1024-lane workgroup per ray"}
     del jac, eta, chi, D, rhs, lo, up, T, E, f, f_n
     torch.cuda.empty_cache()
     return out
@@ -530,9 +531,8 @@ def tabulated_leg(inp, wl, precision, launches, t_direct_ms, ref):
 
 def roofline(wl, precision, t_fwd, t_bwd, zl):
     """Roofline entry of the dominant launch (the backward call of a chunk): algorithmic FLOPs
-    per launch / its HIP-event duration. In the mixed path that call runs three kernels, one
-    per zone class (FP32; FP64 Fermi-Dirac factors; FP64 above |eta_e| = 64), and its duration
-    is their sum."""
+    per launch / its HIP-event duration. In the mixed path that call runs two kernels, one per
+    zone class (FP32 up to |eta_e| = eta_fp64, FP64 above), and its duration is their sum."""
     dom_ms, dom_bwd = (t_bwd, True) if t_bwd >= t_fwd else (t_fwd, False)
     flops = algorithmic_flops_per_zone(wl.ne, wl.nquad, dom_bwd) * zl
     achieved = flops / (dom_ms * 1e-3) / 1e12
@@ -552,9 +552,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=["mixed", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="steps of the FP64 comparison run (0: skip)")
     ap.add_argument("--eta-fp64", type=float, default=30.0,
-                    help="mixed path: FP64 Fermi-Dirac factors for |eta_e| above this (default 30)")
+                    help="mixed path: zones with |eta_e| above this run in FP64 (default 30, capped at 64)")
     ap.add_argument("--threshold64-steps", type=int, default=2,
-                    help="steps of the mixed run with the FP64 Fermi-Dirac threshold at 64 (0: skip)")
+                    help="steps of the mixed run with the FP64 zone-class threshold at 64 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--stream-steps", type=int, default=2,
@@ -632,7 +632,7 @@ def main():
 
     thr64 = None
     if precision == "mixed" and args.threshold64_steps > 0:
-        print(f"[bench] mixed with the FP64 Fermi-Dirac threshold at 64: {args.threshold64_steps} steps",
+        print(f"[bench] mixed with the FP64 zone-class threshold at 64: {args.threshold64_steps} steps",
               file=sys.stderr, flush=True)
         r64 = Runner(inp, wl, "mixed", wl.chunks, eta_fp64=64.0)
         tt = r64.timed(args.threshold64_steps, 1)
@@ -640,8 +640,8 @@ def main():
         del r64
         torch.cuda.empty_cache()
         thr64 = {"value": units / tt, "ms_per_step": tt * 1e3, "rel_err": et,
-                 "note": "FP32 Fermi-Dirac factors up to |eta_e| = 64 (not the FP64 factors above 30 of the "
-                         "headline); 'stratum' is eta_e > 30, the zones whose factors change precision"}
+                 "note": "FP32 for zones up to |eta_e| = 64 (the headline runs zones above 30 in FP64); "
+                         "'stratum' is eta_e > 30, the zones that change class"}
 
     positron = None
     if args.positron_steps > 0:
@@ -680,7 +680,7 @@ def main():
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(wl)
 
-    mode = (f"FP32 with FP64 Fermi-Dirac factors for |eta_e| > {args.eta_fp64:g} (FP64 throughout above 64)"
+    mode = (f"FP32 quadrature bulk, FP64 contractions; zones with |eta_e| > {min(args.eta_fp64, 64.0):g} entirely in FP64"
             if precision == "mixed" else "FP64")
     line = {
         "metric": "zone*(eps,eps') kernel evals/sec fwd+bwd", "value": value, "unit": "zone*(eps,eps')/s",

@@ -16,7 +16,8 @@
 // inverted there by Gauss-Jordan elimination with partial pivoting (FP64), M_r^{-1} overwrites D_r
 // for the back substitution x_r = y_r + M_r^{-1} (up_r x_{r+1}). The blocks are small dense
 // inversions with pivoting, one after another along the ray: FP64 vector arithmetic, the block
-// held in the registers of a 1024-lane workgroup, pivot rows and columns exchanged through LDS.
+// held in the registers of a 1024-lane workgroup, pivot columns exchanged through LDS and pivot
+// rows read across lanes.
 #include <hip/hip_runtime.h>
 
 #include "../../include/vtx_rates.h"
@@ -103,18 +104,25 @@ __device__ __forceinline__ double wave_sum64(double v) {
 
 // Block elimination along a ray (one ray per 1024-lane workgroup). The Schur complement
 // M_r = D_r - diag(lo_r) M_{r-1}^{-1} diag(up_{r-1}) lives in registers: lane l of wave w holds
-// the entries (i, j) with j = l + 64 h (h < kSolveH) and i = w + 16 c (c < kSolveC), so a wave
-// reads its rows' pivot-column entries as LDS broadcasts and its lanes read consecutive entries
-// of the pivot row. It is inverted in place by Gauss-Jordan elimination with partial pivoting
-// done implicitly: step k takes, among the rows not yet used, the one with the largest |M[i][k]|
-// (the lowest index on ties) and eliminates column k from every other row, without moving any
-// row. That is the in-place elimination of P M (P the pivot order, row k of P M = row pi(k) of
-// M), so the registers end with Z[pi(a)][j] = ((P M)^-1)[a][j] = M^-1[a][pi(j)]: entry (i, j)
-// of Z is M^-1[pi^-1(i)][pi(j)]. The inverse is staged in LDS in its own order, copied to D_r for
-// the back substitution and used for the next zone's Schur complement and for y_r.
+// the entries (i, j) with i = l + 64 h (h < ROWS, ROWS = ceil(nb / 64)) and j = w + 16 c
+// (c < kSolveCols), so a column of the block sits in one wave and a row is spread over one lane of
+// every wave. Entries outside the nb x nb block are zeros and stay zeros, so no step needs a
+// bounds test on them. The block is inverted in place by Gauss-Jordan elimination with partial
+// pivoting done implicitly: step k takes, among the rows not yet used, the one with the largest
+// |M[i][k]| (the lowest index on ties) and eliminates column k from every other row, without
+// moving any row. That is the in-place elimination of P M (P the pivot order, row k of P M = row
+// pi(k) of M), so the registers end with Z[pi(a)][j] = ((P M)^-1)[a][j] = M^-1[a][pi(j)]: entry
+// (i, j) of Z is M^-1[pi^-1(i)][pi(j)]. One barrier per step: the wave holding column k finds the
+// pivot (DPP and readlane, no memory access) and publishes the column and 1/pivot through LDS;
+// every wave then reads the pivot row's entries on its own columns from the pivot's lane
+// (readlane) and updates its registers, the wave holding column k + 1 at a raised issue
+// priority, which it drops once it has published that column. The
+// inverse is staged in LDS in its own order, copied to D_r for the back substitution and used for
+// the next zone's Schur complement and for y_r.
 constexpr int kSolveBlock = 1024, kSolveWaves = kSolveBlock / 64;
-constexpr int kMaxNb = 140;   // nb^2 + 5 nb doubles of LDS and the pivot maps within 160 KiB
-constexpr int kSolveH = (kMaxNb + 63) / 64, kSolveC = (kMaxNb + kSolveWaves - 1) / kSolveWaves;
+constexpr int kMaxNb = 140;   // nb^2 + 2 nb + 386 doubles of LDS and the pivot maps within 160 KiB
+constexpr int kSolveCols = (kMaxNb + kSolveWaves - 1) / kSolveWaves;
+constexpr int kPadRows = 64 * ((kMaxNb + 63) / 64);   // rows a lane pattern covers (column buffers)
 
 // out[i] = sum_j A[i][j] w[j] + add[i] for an nb x nb row-major A (LDS or global): wave w takes
 // rows w, w + 16, ...; its lanes split j and sum by shuffles.
@@ -128,6 +136,144 @@ __device__ __forceinline__ void matvec(const double* A, const double* w, const d
   }
 }
 
+// The value of a double in lane src of the wave (uniform).
+__device__ __forceinline__ double read_lane(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The pivot search's order: a larger key first, on equal keys the lower row.
+__device__ __forceinline__ void pivot_better(double& key, int& row, double okey, int orow) {
+  const bool take = okey > key || (okey == key && orow < row);
+  key = take ? okey : key;
+  row = take ? orow : row;
+}
+
+// v from another lane of the same row of 16 (DPP, no memory access): CTRL is a quad permutation
+// or a rotation within the row, so every source lane exists.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ void pivot_dpp(double& key, int& row) {
+  pivot_better(key, row, dpp_double<CTRL>(key), __builtin_amdgcn_update_dpp(0, row, CTRL, 0xf, 0xf, false));
+}
+
+// The best (key, row) over the wave, uniform: within each row of 16 lanes by DPP (lane order
+// xor 1, xor 2, then rotations by 4 and 8), then over the four rows' results.
+__device__ __forceinline__ int wave_pivot(double key, int row) {
+  constexpr int kXor1 = 0xb1, kXor2 = 0x4e, kRor4 = 0x124, kRor8 = 0x128;
+  pivot_dpp<kXor1>(key, row);
+  pivot_dpp<kXor2>(key, row);
+  pivot_dpp<kRor4>(key, row);
+  pivot_dpp<kRor8>(key, row);
+  double bk = read_lane(key, 0);
+  int br = __builtin_amdgcn_readlane(row, 0);
+#pragma unroll
+  for (int q = 16; q < 64; q += 16) pivot_better(bk, br, read_lane(key, q), __builtin_amdgcn_readlane(row, q));
+  return __builtin_amdgcn_readfirstlane(br);
+}
+
+// One Gauss-Jordan step on the registers: column k = kSolveWaves KC + (the index of the wave
+// holding it). cb: this step's column buffer [kPadRows], pb: its 1/pivot.
+template <int ROWS, int KC>
+__device__ __forceinline__ void gj_step(double (&a)[ROWS][kSolveCols], int k, int nb, int lane, int wave,
+                                        double* cb, double* pb, int* piv, int* step) {
+  if (wave == k - kSolveWaves * KC) {
+    // this wave holds column k: the unused row of largest |M[i][k]|, the lowest index on ties (NaN
+    // counts as largest); the column, before this step's update, and 1/pivot into LDS
+    double best = -1.0;
+    int bi = nb;
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      const int i = lane + 64 * h;
+      if (i < nb && step[i] < 0) {
+        const double ax = fabs(a[h][KC]);
+        pivot_better(best, bi, ax == ax ? ax : INFINITY, i);
+      }
+    }
+    const int p = wave_pivot(best, bi);
+    double xp = a[0][KC];
+#pragma unroll
+    for (int h = 1; h < ROWS; ++h)
+      if (h == (p >> 6)) xp = a[h][KC];
+    const double pv = read_lane(xp, p & 63);
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) cb[lane + 64 * h] = a[h][KC];
+    if (lane == 0) {
+      piv[k] = p;
+      step[p] = k;
+      *pb = 1.0 / pv;
+    }
+    __builtin_amdgcn_s_setprio(0);
+  }
+  __syncthreads();
+  // the wave holding the next column updates first: its pivot search is the next step's path
+  if (wave == (k + 1) % kSolveWaves) __builtin_amdgcn_s_setprio(2);
+  // the pivot, the pivot row on this wave's columns (read from the pivot's lane), this lane's
+  // factors scaled by 1/pivot
+  const int p = __builtin_amdgcn_readfirstlane(piv[k]);
+  const double pinv = *pb;
+  const int hp = p >> 6, lp = p & 63;
+  double rw[kSolveCols];
+  if (ROWS == 1 || hp == 0) {
+#pragma unroll
+    for (int c = 0; c < kSolveCols; ++c) rw[c] = read_lane(a[0][c], lp);
+  } else if (ROWS == 2 || hp == 1) {
+#pragma unroll
+    for (int c = 0; c < kSolveCols; ++c) rw[c] = read_lane(a[ROWS > 1 ? 1 : 0][c], lp);
+  } else {
+#pragma unroll
+    for (int c = 0; c < kSolveCols; ++c) rw[c] = read_lane(a[ROWS - 1][c], lp);
+  }
+  double g[ROWS];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h) g[h] = cb[lane + 64 * h] * pinv;
+  // Row p becomes the pivot row times 1/pivot: zeroed, with factor -1/pivot. Column k becomes
+  // -f_i/pivot (1/pivot in row p): zeroed, with the pivot row's entry there taken as 1.
+  if (lane == lp) {
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h)
+      if (h == hp) {
+        g[h] = -pinv;
+#pragma unroll
+        for (int c = 0; c < kSolveCols; ++c) a[h][c] = 0.0;
+      }
+  }
+  if (wave == k - kSolveWaves * KC) {
+    rw[KC] = 1.0;
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) a[h][KC] = 0.0;
+  }
+  // eliminate column k from every row
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+    for (int c = 0; c < kSolveCols; ++c) a[h][c] = __builtin_fma(-g[h], rw[c], a[h][c]);
+  // the next step writes the other column buffer and the pivot maps' next entries before its
+  // barrier; this step's buffer is written again only after that barrier, which every lane
+  // reaches after this update
+}
+
+template <int ROWS, int KC>
+__device__ __forceinline__ void gj_columns(double (&a)[ROWS][kSolveCols], int nb, int lane, int wave, double* colb,
+                                           int* piv, int* step) {
+  if constexpr (KC < kSolveCols) {
+    const int k1 = nb < kSolveWaves * (KC + 1) ? nb : kSolveWaves * (KC + 1);
+    for (int k = kSolveWaves * KC; k < k1; ++k)
+      gj_step<ROWS, KC>(a, k, nb, lane, wave, colb + (k & 1) * (kPadRows + 1),
+                        colb + (k & 1) * (kPadRows + 1) + kPadRows, piv, step);
+    gj_columns<ROWS, KC + 1>(a, nb, lane, wave, colb, piv, step);
+  }
+}
+
+template <int ROWS>
 __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t nrays, int nzr,
                                                                 const double* __restrict__ lo,
                                                                 double* __restrict__ D,
@@ -140,16 +286,15 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
   __shared__ int step[kMaxNb];   // step[i]: the step that pivoted row i, -1 while unused
   const int nb2 = nb * nb;
   double* Inv = sm;              // [nb][nb] the inverse of the zone's block, logical order
-  double* colb = Inv + nb2;      // 2 x [nb] pivot columns (alternate steps); w of the back substitution
-  double* rowb = colb + 2 * nb;  // [nb] normalised pivot row
-  double* v = rowb + nb;         // right-hand side of the zone, then x of the zone above
-  double* y = v + nb;            // y_r
+  double* colb = Inv + nb2;      // 2 x ([kPadRows] pivot column, 1/pivot), alternate steps; w of the back substitution
+  double* v = colb + 2 * (kPadRows + 1);   // right-hand side of the zone, then x of the zone above
+  double* y = v + nb;                      // y_r
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* Dray = D + ray * nzr * (int64_t)nb2;
   double* bray = rhs + ray * nzr * (int64_t)nb;
   const double* lray = lo + ray * nzr * (int64_t)nb;
   const double* uray = up + ray * nzr * (int64_t)nb;
-  double a[kSolveC][kSolveH];
+  double a[ROWS][kSolveCols];
   for (int r = 0; r < nzr; ++r) {
     double* Dr = Dray + (int64_t)r * nb2;
     const double* lr = lray + (int64_t)r * nb;
@@ -169,96 +314,27 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kSolveC; ++c) {
-      const int i = wave + kSolveWaves * c;
+    for (int h = 0; h < ROWS; ++h) {
+      const int i = lane + 64 * h;
 #pragma unroll
-      for (int h = 0; h < kSolveH; ++h) {
-        const int j = lane + 64 * h;
-        a[c][h] = (i < nb && j < nb) ? Inv[i * nb + j] : 0.0;
+      for (int c = 0; c < kSolveCols; ++c) {
+        const int j = wave + kSolveWaves * c;
+        a[h][c] = (i < nb && j < nb) ? Inv[i * nb + j] : 0.0;
       }
     }
-    for (int k = 0; k < nb; ++k) {
-      double* cb = colb + (k & 1) * nb;
-      // the pivot column, before this step's update: lane k % 64 of every wave holds it
-      const int hk = k >> 6;
-      if (lane == (k & 63)) {
-#pragma unroll
-        for (int c = 0; c < kSolveC; ++c) {
-          const int i = wave + kSolveWaves * c;
-#pragma unroll
-          for (int h = 0; h < kSolveH; ++h)
-            if (h == hk && i < nb) cb[i] = a[c][h];
-        }
-      }
-      __syncthreads();
-      // every wave finds the pivot row: the unused row of largest |M[i][k]|, lowest index on ties
-      double best = -1.0;
-      int bi = nb;
-      for (int i = lane; i < nb; i += 64) {
-        const double x = fabs(cb[i]);
-        if (step[i] < 0 && (x > best || (x == best && i < bi))) {
-          best = x;
-          bi = i;
-        }
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      const int p = __builtin_amdgcn_readfirstlane(bi);
-      const double pinv = 1.0 / cb[p];
-      // the wave holding row p writes the normalised pivot row; the pivot column takes 1/pivot
-      if (wave == (p % kSolveWaves)) {
-        const int cp = p / kSolveWaves;
-#pragma unroll
-        for (int c = 0; c < kSolveC; ++c) {
-          if (c != cp) continue;
-#pragma unroll
-          for (int h = 0; h < kSolveH; ++h) {
-            const int j = lane + 64 * h;
-            if (j < nb) rowb[j] = j == k ? pinv : a[c][h] * pinv;
-          }
-        }
-      }
-      __syncthreads();
-      // every wave has its pivot (the search read the pivot maps): record it
-      if (tid == 0) {
-        piv[k] = p;
-        step[p] = k;
-      }
-      // eliminate column k from every row but p; row p becomes the normalised row
-#pragma unroll
-      for (int c = 0; c < kSolveC; ++c) {
-        const int i = wave + kSolveWaves * c;
-        if (i >= nb) continue;
-        const double fi = cb[i];
-#pragma unroll
-        for (int h = 0; h < kSolveH; ++h) {
-          const int j = lane + 64 * h;
-          if (j >= nb) continue;
-          const double rj = rowb[j];
-          a[c][h] = i == p ? rj : (j == k ? 0.0 : a[c][h]) - fi * rj;
-        }
-      }
-      // the next step writes the other column buffer before its first barrier; the pivot row
-      // only after that barrier, which every lane reaches after this update, and the pivot
-      // maps are read again only after it
-    }
+    gj_columns<ROWS, 0>(a, nb, lane, wave, colb, piv, step);
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     // Inv[a][b] = Z[pi(a)][pi^-1(b)]: entry (i, j) of the registers goes to Inv[step[i]][piv[j]]
 #pragma unroll
-    for (int c = 0; c < kSolveC; ++c) {
-      const int i = wave + kSolveWaves * c;
+    for (int h = 0; h < ROWS; ++h) {
+      const int i = lane + 64 * h;
       if (i >= nb) continue;
       const int ai = step[i];
 #pragma unroll
-      for (int h = 0; h < kSolveH; ++h) {
-        const int j = lane + 64 * h;
-        if (j < nb) Inv[ai * nb + piv[j]] = a[c][h];
+      for (int c = 0; c < kSolveCols; ++c) {
+        const int j = wave + kSolveWaves * c;
+        if (j < nb) Inv[ai * nb + piv[j]] = a[h][c];
       }
     }
     __syncthreads();
@@ -312,21 +388,31 @@ hipError_t launch_ray_system(int ne, int64_t nz, int nzr, double dt, const doubl
 
 int max_block() { return kMaxNb; }
 
-hipError_t launch_ray_solve(int nb, int64_t nrays, int nzr, const double* lo, double* D, const double* up,
-                            double* rhs, hipStream_t s) {
-  const size_t lds = sizeof(double) * ((size_t)nb * nb + 5 * (size_t)nb);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ray_solve_kernel),
+template <int ROWS>
+hipError_t launch_ray_solve_t(int nb, int64_t nrays, int nzr, const double* lo, double* D, const double* up,
+                              double* rhs, hipStream_t s) {
+  const size_t lds = sizeof(double) * ((size_t)nb * nb + 2 * (kPadRows + 1) + 2 * (size_t)nb);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ray_solve_kernel<ROWS>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   for (int64_t r0 = 0; r0 < nrays; r0 += (int64_t(1) << 22)) {
     const int64_t n = nrays - r0 < (int64_t(1) << 22) ? nrays - r0 : (int64_t(1) << 22);
     const int64_t per = (int64_t)nzr * nb;
-    hipLaunchKernelGGL(ray_solve_kernel, dim3((unsigned)n), dim3(kSolveBlock), lds, s, nb, n, nzr, lo + r0 * per,
-                       D + r0 * per * nb, up + r0 * per, rhs + r0 * per);
+    hipLaunchKernelGGL(ray_solve_kernel<ROWS>, dim3((unsigned)n), dim3(kSolveBlock), lds, s, nb, n, nzr,
+                       lo + r0 * per, D + r0 * per * nb, up + r0 * per, rhs + r0 * per);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Rows per lane: the fewest that cover the block (nb <= kMaxNb, checked by the caller).
+hipError_t launch_ray_solve(int nb, int64_t nrays, int nzr, const double* lo, double* D, const double* up,
+                            double* rhs, hipStream_t s) {
+  static_assert(kMaxNb <= 3 * 64, "three rows per lane cover the largest block");
+  if (nb <= 64) return launch_ray_solve_t<1>(nb, nrays, nzr, lo, D, up, rhs, s);
+  if (nb <= 128) return launch_ray_solve_t<2>(nb, nrays, nzr, lo, D, up, rhs, s);
+  return launch_ray_solve_t<3>(nb, nrays, nzr, lo, D, up, rhs, s);
 }
 
 }  // namespace vtx

@@ -10,7 +10,8 @@ device code with the library's own flags and reads the code-object metadata:
 * the FP32 forward and interpolation kernels fit five waves per SIMD (at most 96 VGPRs);
 * the FP32 backward and the FP64 forward fit three (at most 168);
 * the FP64 backward and the FP64 export of task values for tables fit two (at most 256);
-* the forward with the electron mass (FP64, one 256-lane workgroup per zone) fits two.
+* the forward with the electron mass (FP64, one 256-lane workgroup per zone) fits two;
+* the ray solve (a 1024-lane workgroup per ray, four waves per SIMD) fits in 128.
 """
 import os
 import re
@@ -32,6 +33,7 @@ BUDGET = [
     (r"rates_forward_kernelINS0_4Fp64ELi[23]E", 256),
     (r"rates_backward_kernelINS0_4Fp64", 256),
     (r"rates_mass_kernel", 256),
+    (r"ray_solve_kernel", 128),
 ]
 
 
@@ -41,7 +43,7 @@ def kernels(tmp_path_factory):
         pytest.skip("hipcc not available")
     flags = [f for f in build_lib.FLAGS if f not in ("-shared", "-fPIC")]
     text = ""
-    for name in ("vtx_kernels", "vtx_massive"):
+    for name in ("vtx_kernels", "vtx_massive", "vtx_newton"):
         out = tmp_path_factory.mktemp("isa") / (name + ".s")
         src = os.path.join(build_lib.CSRC, name + ".hip")
         subprocess.run([HIPCC] + flags + ["--cuda-device-only", "-S", "-o", str(out), src], check=True,
