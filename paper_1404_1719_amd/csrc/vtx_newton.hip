@@ -104,35 +104,65 @@ __device__ __forceinline__ double wave_sum64(double v) {
 
 // Block elimination along a ray (one ray per 1024-lane workgroup). The Schur complement
 // M_r = D_r - diag(lo_r) M_{r-1}^{-1} diag(up_{r-1}) lives in registers: lane l of wave w holds
-// the entries (i, j) with i = l + 64 h (h < ROWS, ROWS = ceil(nb / 64)) and j = w + 16 c
-// (c < kSolveCols), so a column of the block sits in one wave and a row is spread over one lane of
-// every wave. Entries outside the nb x nb block are zeros and stay zeros, so no step needs a
-// bounds test on them. The block is inverted in place by Gauss-Jordan elimination with partial
+// the entries (i, j) with i = l + 64 h (h < ROWS, ROWS = ceil(nb / 64)) and j = 9 w + c (c < 9),
+// so wave w holds the block's 9-column panel w whole and a row is spread over one lane of every
+// wave. Entries outside the nb x nb block are zeros and stay zeros, so no step needs a bounds
+// test on them. The block is inverted in place by Gauss-Jordan elimination with partial
 // pivoting done implicitly: step k takes, among the rows not yet used, the one with the largest
 // |M[i][k]| (the lowest index on ties) and eliminates column k from every other row, without
 // moving any row. That is the in-place elimination of P M (P the pivot order, row k of P M = row
 // pi(k) of M), so the registers end with Z[pi(a)][j] = ((P M)^-1)[a][j] = M^-1[a][pi(j)]: entry
-// (i, j) of Z is M^-1[pi^-1(i)][pi(j)]. One barrier per step: the wave holding column k finds the
-// pivot (DPP and readlane, no memory access) and publishes the column and 1/pivot through LDS;
-// every wave then reads the pivot row's entries on its own columns from the pivot's lane
-// (readlane) and updates its registers, the wave holding column k + 1 at a raised issue
-// priority, which it drops once it has published that column. The
-// inverse is staged in LDS in its own order, copied to D_r for the back substitution and used for
-// the next zone's Schur complement and for y_r.
+// (i, j) of Z is M^-1[pi^-1(i)][pi(j)].
+//
+// The steps go by panels: the wave holding panel q runs its 9 steps alone (pivot search by DPP
+// and readlane, pivot row by readlane, no barrier between them) and publishes the factored panel
+// G in LDS; one barrier; every other wave then applies the 9 steps at once. The 9 steps act on a
+// column x as x + U x[pivots] (they only mix in the pivot rows), and the factored panel holds
+// G[i][t] = delta(i, p_t) + U[i][t], so the other columns take x'[i] = (i a pivot row ? 0 :
+// x[i]) + sum_t G[i][t] x[p_t]. A wave reads its own pivot rows x[p_t] through a small LDS area
+// of its own. The wave of the next panel applies the current one first. The inverse is staged
+// in LDS in its own order (the panels' buffers share that space while the block is in
+// registers), copied to D_r for the back substitution and used for the next zone's Schur
+// complement and for y_r.
 constexpr int kSolveBlock = 1024, kSolveWaves = kSolveBlock / 64;
-constexpr int kMaxNb = 140;   // nb^2 + 2 nb + 386 doubles of LDS and the pivot maps within 160 KiB
-constexpr int kSolveCols = (kMaxNb + kSolveWaves - 1) / kSolveWaves;
-constexpr int kPadRows = 64 * ((kMaxNb + 63) / 64);   // rows a lane pattern covers (column buffers)
+constexpr int kPanel = 9;     // columns per wave (a multiple of 3: the update reads them in threes)
+constexpr int kMaxNb = 140;   // nb^2 + 3 nb doubles of LDS and the pivot maps within 160 KiB
+static_assert(kMaxNb <= kPanel * kSolveWaves, "the waves' panels cover the largest block");
+constexpr int kFormIter = (kMaxNb * kMaxNb + kSolveBlock - 1) / kSolveBlock;   // block entries per lane
+constexpr int kFormBatch = 5;   // loads in flight per lane while forming the block
+
+// LDS doubles the panels need inside the block's space: two factored panels (alternate
+// panels) and each wave's 9 x 9 pivot rows.
+constexpr int panel_space(int rows) { return 2 * kPanel * 64 * rows + kSolveWaves * kPanel * kPanel; }
 
 // out[i] = sum_j A[i][j] w[j] + add[i] for an nb x nb row-major A (LDS or global): wave w takes
-// rows w, w + 16, ...; its lanes split j and sum by shuffles.
+// rows w, w + 16, ...; its lanes split j and sum by shuffles. The loads of three rows are issued
+// before their sums, so a global A costs a memory latency per three rows, not per row.
+constexpr int kMatvecRows = (kMaxNb + kSolveWaves - 1) / kSolveWaves;   // rows per wave
+constexpr int kMatvecCols = (kMaxNb + 63) / 64;                         // entries per lane and row
+constexpr int kMatvecBatch = 3;
+static_assert(kMatvecRows % kMatvecBatch == 0, "rows per wave come in whole batches");
 __device__ __forceinline__ void matvec(const double* A, const double* w, const double* add, double* out, int nb) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = wave; i < nb; i += nw) {
-    double s = 0.0;
-    for (int j = lane; j < nb; j += 64) s += A[(int64_t)i * nb + j] * w[j];
-    s = wave_sum64(s);
-    if (lane == 0) out[i] = s + add[i];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll 1
+  for (int t0 = 0; t0 < kMatvecRows; t0 += kMatvecBatch) {
+    double s[kMatvecBatch];
+#pragma unroll
+    for (int t = 0; t < kMatvecBatch; ++t) {
+      const int i = wave + kSolveWaves * (t0 + t);
+      s[t] = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMatvecCols; ++u) {
+        const int j = lane + 64 * u;
+        if (i < nb && j < nb) s[t] = __builtin_fma(A[(int64_t)i * nb + j], w[j], s[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kMatvecBatch; ++t) {
+      const int i = wave + kSolveWaves * (t0 + t);
+      const double r = wave_sum64(s[t]);
+      if (lane == 0 && i < nb) out[i] = r + add[i];
+    }
   }
 }
 
@@ -180,97 +210,142 @@ __device__ __forceinline__ int wave_pivot(double key, int row) {
   return __builtin_amdgcn_readfirstlane(br);
 }
 
-// One Gauss-Jordan step on the registers: column k = kSolveWaves KC + (the index of the wave
-// holding it). cb: this step's column buffer [kPadRows], pb: its 1/pivot.
-template <int ROWS, int KC>
-__device__ __forceinline__ void gj_step(double (&a)[ROWS][kSolveCols], int k, int nb, int lane, int wave,
-                                        double* cb, double* pb, int* piv, int* step) {
-  if (wave == k - kSolveWaves * KC) {
-    // this wave holds column k: the unused row of largest |M[i][k]|, the lowest index on ties (NaN
-    // counts as largest); the column, before this step's update, and 1/pivot into LDS
+// The same pivot, first by the keys' upper 32 bits: for keys >= 0 they order as the keys do,
+// up to ties. Where one lane alone holds the largest upper word, its (key, row) is the best
+// (each lane's pair is already its own best); otherwise the full comparison decides.
+__device__ __forceinline__ int wave_pivot_fast(double key, int row) {
+  const long long b = __builtin_bit_cast(long long, key);
+  const unsigned int hi = key >= 0.0 ? (unsigned int)(b >> 32) : 0u;
+  constexpr int kXor1 = 0xb1, kXor2 = 0x4e, kRor4 = 0x124, kRor8 = 0x128;
+  unsigned int m = hi;
+  m = max(m, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)m, kXor1, 0xf, 0xf, false));
+  m = max(m, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)m, kXor2, 0xf, 0xf, false));
+  m = max(m, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)m, kRor4, 0xf, 0xf, false));
+  m = max(m, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)m, kRor8, 0xf, 0xf, false));
+  unsigned int top = (unsigned int)__builtin_amdgcn_readlane((int)m, 0);
+#pragma unroll
+  for (int q = 16; q < 64; q += 16) top = max(top, (unsigned int)__builtin_amdgcn_readlane((int)m, q));
+  const unsigned long long at = __ballot(hi == top);
+  if (__popcll(at) == 1) return __builtin_amdgcn_readlane(row, __ffsll((long long)at) - 1);
+  return wave_pivot(key, row);
+}
+
+// The wave holding panel q runs the panel's steps k = 9 q + s on its columns and publishes the
+// factored panel: G[s][i] (row i = lane + 64 h) into g_out, the pivots into piv and step.
+template <int ROWS>
+__device__ __forceinline__ void panel_factor(double (&a)[ROWS][kPanel], int q, int nb, int lane, double* g_out,
+                                             int* piv, int* step) {
+  bool used[ROWS];
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h) {
+    const int i = lane + 64 * h;
+    used[h] = i >= nb || step[i] >= 0;
+  }
+#pragma unroll
+  for (int s = 0; s < kPanel; ++s) {
+    const int k = kPanel * q + s;
+    if (k >= nb) break;
+    // the unused row of largest |M[i][k]|, the lowest index on ties (NaN counts as largest)
     double best = -1.0;
     int bi = nb;
 #pragma unroll
-    for (int h = 0; h < ROWS; ++h) {
-      const int i = lane + 64 * h;
-      if (i < nb && step[i] < 0) {
-        const double ax = fabs(a[h][KC]);
-        pivot_better(best, bi, ax == ax ? ax : INFINITY, i);
+    for (int h = 0; h < ROWS; ++h)
+      if (!used[h]) {
+        const double ax = fabs(a[h][s]);
+        pivot_better(best, bi, ax == ax ? ax : INFINITY, lane + 64 * h);
       }
+    const int p = wave_pivot_fast(best, bi);
+    const int hp = p >> 6, lp = p & 63;
+    double rw[kPanel];
+    if (ROWS == 1 || hp == 0) {
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) rw[c] = read_lane(a[0][c], lp);
+    } else if (ROWS == 2 || hp == 1) {
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) rw[c] = read_lane(a[ROWS > 1 ? 1 : 0][c], lp);
+    } else {
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) rw[c] = read_lane(a[ROWS - 1][c], lp);
     }
-    const int p = wave_pivot(best, bi);
-    double xp = a[0][KC];
+    const double pinv = 1.0 / rw[s];
+    // factors f_i / pivot; row p becomes the pivot row times 1/pivot (zeroed, factor -1/pivot),
+    // column k becomes -f_i / pivot and 1/pivot in row p (zeroed, the pivot row's entry taken as 1)
+    double g[ROWS];
 #pragma unroll
-    for (int h = 1; h < ROWS; ++h)
-      if (h == (p >> 6)) xp = a[h][KC];
-    const double pv = read_lane(xp, p & 63);
+    for (int h = 0; h < ROWS; ++h) g[h] = a[h][s] * pinv;
+    if (lane == lp) {
 #pragma unroll
-    for (int h = 0; h < ROWS; ++h) cb[lane + 64 * h] = a[h][KC];
+      for (int h = 0; h < ROWS; ++h)
+        if (h == hp) {
+          g[h] = -pinv;
+          used[h] = true;
+#pragma unroll
+          for (int c = 0; c < kPanel; ++c) a[h][c] = 0.0;
+        }
+    }
+    rw[s] = 1.0;
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) a[h][s] = 0.0;
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) a[h][c] = __builtin_fma(-g[h], rw[c], a[h][c]);
     if (lane == 0) {
       piv[k] = p;
       step[p] = k;
-      *pb = 1.0 / pv;
     }
-    __builtin_amdgcn_s_setprio(0);
   }
-  __syncthreads();
-  // the wave holding the next column updates first: its pivot search is the next step's path
-  if (wave == (k + 1) % kSolveWaves) __builtin_amdgcn_s_setprio(2);
-  // the pivot, the pivot row on this wave's columns (read from the pivot's lane), this lane's
-  // factors scaled by 1/pivot
-  const int p = __builtin_amdgcn_readfirstlane(piv[k]);
-  const double pinv = *pb;
-  const int hp = p >> 6, lp = p & 63;
-  double rw[kSolveCols];
-  if (ROWS == 1 || hp == 0) {
 #pragma unroll
-    for (int c = 0; c < kSolveCols; ++c) rw[c] = read_lane(a[0][c], lp);
-  } else if (ROWS == 2 || hp == 1) {
+  for (int s = 0; s < kPanel; ++s)
 #pragma unroll
-    for (int c = 0; c < kSolveCols; ++c) rw[c] = read_lane(a[ROWS > 1 ? 1 : 0][c], lp);
-  } else {
+    for (int h = 0; h < ROWS; ++h) g_out[s * 64 * ROWS + lane + 64 * h] = a[h][s];
+}
+
+// Another wave applies panel q's steps to its columns: x'[i] = (i a pivot row of the panel ? 0 :
+// x[i]) + sum_t G[t][i] x[p_t]. cw: the wave's own 9 x 9 area, x[p_t] on its columns.
+template <int ROWS>
+__device__ __forceinline__ void panel_apply(double (&a)[ROWS][kPanel], int q, int nb, int lane, const double* g_in,
+                                            double* cw, const int* step) {
+  const int k0 = kPanel * q;
+  const int ns = nb - k0 < kPanel ? nb - k0 : kPanel;
+  double keep[ROWS];
 #pragma unroll
-    for (int c = 0; c < kSolveCols; ++c) rw[c] = read_lane(a[ROWS - 1][c], lp);
+  for (int h = 0; h < ROWS; ++h) {
+    const int i = lane + 64 * h;
+    const int t = i < nb ? step[i] - k0 : -1;
+    const bool pv = t >= 0 && t < ns;
+    keep[h] = pv ? 0.0 : 1.0;
+    if (pv) {
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) cw[t * kPanel + c] = a[h][c];
+    }
   }
-  double g[ROWS];
-#pragma unroll
-  for (int h = 0; h < ROWS; ++h) g[h] = cb[lane + 64 * h] * pinv;
-  // Row p becomes the pivot row times 1/pivot: zeroed, with factor -1/pivot. Column k becomes
-  // -f_i/pivot (1/pivot in row p): zeroed, with the pivot row's entry there taken as 1.
-  if (lane == lp) {
-#pragma unroll
-    for (int h = 0; h < ROWS; ++h)
-      if (h == hp) {
-        g[h] = -pinv;
-#pragma unroll
-        for (int c = 0; c < kSolveCols; ++c) a[h][c] = 0.0;
-      }
-  }
-  if (wave == k - kSolveWaves * KC) {
-    rw[KC] = 1.0;
-#pragma unroll
-    for (int h = 0; h < ROWS; ++h) a[h][KC] = 0.0;
-  }
-  // eliminate column k from every row
+  // the pivot rows reach the whole wave through its own LDS area (in order within the wave)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
   for (int h = 0; h < ROWS; ++h)
 #pragma unroll
-    for (int c = 0; c < kSolveCols; ++c) a[h][c] = __builtin_fma(-g[h], rw[c], a[h][c]);
-  // the next step writes the other column buffer and the pivot maps' next entries before its
-  // barrier; this step's buffer is written again only after that barrier, which every lane
-  // reaches after this update
-}
-
-template <int ROWS, int KC>
-__device__ __forceinline__ void gj_columns(double (&a)[ROWS][kSolveCols], int nb, int lane, int wave, double* colb,
-                                           int* piv, int* step) {
-  if constexpr (KC < kSolveCols) {
-    const int k1 = nb < kSolveWaves * (KC + 1) ? nb : kSolveWaves * (KC + 1);
-    for (int k = kSolveWaves * KC; k < k1; ++k)
-      gj_step<ROWS, KC>(a, k, nb, lane, wave, colb + (k & 1) * (kPadRows + 1),
-                        colb + (k & 1) * (kPadRows + 1) + kPadRows, piv, step);
-    gj_columns<ROWS, KC + 1>(a, nb, lane, wave, colb, piv, step);
+    for (int c = 0; c < kPanel; ++c) a[h][c] *= keep[h];
+  for (int t = 0; t < ns; ++t) {
+    double gt[ROWS];
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) gt[h] = g_in[t * 64 * ROWS + lane + 64 * h];
+#pragma unroll
+    for (int c0 = 0; c0 < kPanel; c0 += 3) {
+      double x[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) x[c] = cw[t * kPanel + c0 + c];
+#pragma unroll
+      for (int h = 0; h < ROWS; ++h)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a[h][c0 + c] = __builtin_fma(gt[h], x[c], a[h][c0 + c]);
+    }
   }
+  // the area is written again at the next panel, after this wave's reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 template <int ROWS>
@@ -285,31 +360,50 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
   __shared__ int piv[kMaxNb];    // piv[k]: the row pivoted at step k
   __shared__ int step[kMaxNb];   // step[i]: the step that pivoted row i, -1 while unused
   const int nb2 = nb * nb;
+  const int space = nb2 > panel_space(ROWS) ? nb2 : panel_space(ROWS);
   double* Inv = sm;              // [nb][nb] the inverse of the zone's block, logical order
-  double* colb = Inv + nb2;      // 2 x ([kPadRows] pivot column, 1/pivot), alternate steps; w of the back substitution
-  double* v = colb + 2 * (kPadRows + 1);   // right-hand side of the zone, then x of the zone above
-  double* y = v + nb;                      // y_r
+  double* gbuf = sm;             // while the block is in registers: 2 factored panels | pivot rows
+  double* v = sm + space;        // right-hand side of the zone, then x of the zone above
+  double* y = v + nb;            // y_r
+  double* w = y + nb;            // zeros, then up_r x_{r+1} of the back substitution
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* cw = gbuf + 2 * kPanel * 64 * ROWS + wave * kPanel * kPanel;
   double* Dray = D + ray * nzr * (int64_t)nb2;
   double* bray = rhs + ray * nzr * (int64_t)nb;
   const double* lray = lo + ray * nzr * (int64_t)nb;
   const double* uray = up + ray * nzr * (int64_t)nb;
-  double a[ROWS][kSolveCols];
+  const int npanels = (nb + kPanel - 1) / kPanel;
+  double a[ROWS][kPanel];
   for (int r = 0; r < nzr; ++r) {
     double* Dr = Dray + (int64_t)r * nb2;
     const double* lr = lray + (int64_t)r * nb;
     const double* um = uray + (int64_t)(r - 1) * nb;
-    // M_r, formed in LDS over M_{r-1}^{-1} (coalesced reads of D_r), then into registers
-    for (int e = tid; e < nb2; e += blockDim.x) {
-      double m = Dr[e];
-      if (r > 0) {
-        const int i = e / nb, j = e - i * nb;
-        m -= lr[i] * Inv[e] * um[j];
+    // M_r, formed in LDS over M_{r-1}^{-1} (coalesced reads of D_r, all issued before the first
+    // use), then into registers
+#pragma unroll 1
+    for (int t0 = 0; t0 < kFormIter; t0 += kFormBatch) {
+      double dv[kFormBatch];
+#pragma unroll
+      for (int t = 0; t < kFormBatch; ++t) {
+        const int e = tid + kSolveBlock * (t0 + t);
+        dv[t] = e < nb2 ? Dr[e] : 0.0;
       }
-      Inv[e] = m;
+#pragma unroll
+      for (int t = 0; t < kFormBatch; ++t) {
+        const int e = tid + kSolveBlock * (t0 + t);
+        if (e < nb2) {
+          double m = dv[t];
+          if (r > 0) {
+            const int i = e / nb, j = e - i * nb;
+            m -= lr[i] * Inv[e] * um[j];
+          }
+          Inv[e] = m;
+        }
+      }
     }
     for (int i = tid; i < nb; i += blockDim.x) {
       v[i] = bray[(int64_t)r * nb + i] + (r > 0 ? lr[i] * y[i] : 0.0);
+      w[i] = 0.0;
       step[i] = -1;
     }
     __syncthreads();
@@ -317,13 +411,20 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
     for (int h = 0; h < ROWS; ++h) {
       const int i = lane + 64 * h;
 #pragma unroll
-      for (int c = 0; c < kSolveCols; ++c) {
-        const int j = wave + kSolveWaves * c;
+      for (int c = 0; c < kPanel; ++c) {
+        const int j = kPanel * wave + c;
         a[h][c] = (i < nb && j < nb) ? Inv[i * nb + j] : 0.0;
       }
     }
-    gj_columns<ROWS, 0>(a, nb, lane, wave, colb, piv, step);
-    __builtin_amdgcn_s_setprio(0);
+    __syncthreads();   // the panels' buffers take the block's space
+    for (int q = 0; q < npanels; ++q) {
+      if (q > 0 && wave != q - 1)
+        panel_apply<ROWS>(a, q - 1, nb, lane, gbuf + ((q - 1) & 1) * kPanel * 64 * ROWS, cw, step);
+      if (wave == q) panel_factor<ROWS>(a, q, nb, lane, gbuf + (q & 1) * kPanel * 64 * ROWS, piv, step);
+      __syncthreads();
+    }
+    if (wave != npanels - 1)
+      panel_apply<ROWS>(a, npanels - 1, nb, lane, gbuf + ((npanels - 1) & 1) * kPanel * 64 * ROWS, cw, step);
     __syncthreads();
     // Inv[a][b] = Z[pi(a)][pi^-1(b)]: entry (i, j) of the registers goes to Inv[step[i]][piv[j]]
 #pragma unroll
@@ -332,23 +433,20 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
       if (i >= nb) continue;
       const int ai = step[i];
 #pragma unroll
-      for (int c = 0; c < kSolveCols; ++c) {
-        const int j = wave + kSolveWaves * c;
+      for (int c = 0; c < kPanel; ++c) {
+        const int j = kPanel * wave + c;
         if (j < nb) Inv[ai * nb + piv[j]] = a[h][c];
       }
     }
     __syncthreads();
     // y_r = M_r^{-1} v; M_r^{-1} replaces D_r for the back substitution, y_r the right-hand side
     for (int e = tid; e < nb2; e += blockDim.x) Dr[e] = Inv[e];
-    for (int i = tid; i < nb; i += blockDim.x) colb[i] = 0.0;
-    __syncthreads();
-    matvec(Inv, v, colb, y, nb);
+    matvec(Inv, v, w, y, nb);
     __syncthreads();
     for (int i = tid; i < nb; i += blockDim.x) bray[(int64_t)r * nb + i] = y[i];
     __syncthreads();
   }
   // back substitution: x_{N-1} = y_{N-1}; x_r = y_r + M_r^{-1} (up_r x_{r+1}); x kept in v
-  double* w = colb;
   for (int i = tid; i < nb; i += blockDim.x) v[i] = y[i];
   __syncthreads();
   for (int r = nzr - 2; r >= 0; --r) {
@@ -391,7 +489,8 @@ int max_block() { return kMaxNb; }
 template <int ROWS>
 hipError_t launch_ray_solve_t(int nb, int64_t nrays, int nzr, const double* lo, double* D, const double* up,
                               double* rhs, hipStream_t s) {
-  const size_t lds = sizeof(double) * ((size_t)nb * nb + 2 * (kPadRows + 1) + 2 * (size_t)nb);
+  const size_t nb2 = (size_t)nb * nb, ps = (size_t)panel_space(ROWS);
+  const size_t lds = sizeof(double) * ((nb2 > ps ? nb2 : ps) + 3 * (size_t)nb);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ray_solve_kernel<ROWS>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
