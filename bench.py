@@ -419,7 +419,7 @@ def newton_leg(inp, wl, precision, nrays):
     f_n = (f * (1 + 0.01 * torch.randn(f.shape, dtype=torch.float64, device=dev, generator=g))).clamp(0, 1)
     s = torch.cuda.Stream(device=dev)
     s.wait_stream(torch.cuda.current_stream())
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     with torch.cuda.stream(s):
         ev[0].record(s)
         jac, eta, chi = vtx.jacobian(grid, opts, T, E, stream=s, f=f)
@@ -428,13 +428,16 @@ def newton_leg(inp, wl, precision, nrays):
         lo = kappa * 0.5 * torch.rand((nz, nb), dtype=torch.float64, device=dev, generator=g)
         up = kappa * 0.5 * torch.rand((nz, nb), dtype=torch.float64, device=dev, generator=g)
         dt = 1.0 / float(kappa.item())
-        D, rhs = vtx.ray_system(ne, nrays, nzr, dt, jac, f, f_n, f_n, eta, chi, lo, up, stream=s)
+        D = torch.empty((nz, nb, nb), dtype=torch.float64, device=dev)
+        rhs = torch.empty((nz, nb), dtype=torch.float64, device=dev)
         ev[2].record(s)
-        vtx.ray_solve(nrays, nzr, lo, D, up, rhs, stream=s)
+        vtx.ray_system(ne, nrays, nzr, dt, jac, f, f_n, f_n, eta, chi, lo, up, D=D, rhs=rhs, stream=s)
         ev[3].record(s)
+        vtx.ray_solve(nrays, nzr, lo, D, up, rhs, stream=s)
+        ev[4].record(s)
     s.synchronize()
     finite = bool(torch.isfinite(rhs).all().item())
-    t_rates, t_sys, t_solve = (ev[k].elapsed_time(ev[k + 1]) for k in range(3))
+    t_rates, t_sys, t_solve = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), ev[3].elapsed_time(ev[4])
     flops = nz * (2.0 * nb ** 3 + 6.0 * nb ** 2)
     sys_bytes = nz * 8.0 * (nb * nb + nb + 24 * ne * ne + 10 * nb)
     solve_bytes = nz * 8.0 * (3 * nb * nb + 6 * nb)

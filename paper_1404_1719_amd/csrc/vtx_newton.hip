@@ -27,6 +27,7 @@ namespace vtx {
 namespace {
 
 constexpr int kNBlock = 256;
+constexpr int kSysCols = (6 * kMaxNE + 63) / 64;   // columns per lane of a zone's block
 
 __device__ __forceinline__ int partner_of(int s) { return s == 2 ? 2 : 1 - s; }
 
@@ -60,28 +61,45 @@ __global__ __launch_bounds__(kNBlock) void ray_system_kernel(int ne, int64_t nz,
   const double* J = jac + z * (int64_t)(24 * n2);
   const double c0 = 1.5 / dt;
   double* Dz = D + z * (int64_t)nb * nb;
-  // columns run over consecutive lanes: reads of J along j and writes of D along col coalesce
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int row = e / nb, col = e - row * nb;
-    const int s = row / (2 * ne), m = (row / ne) & 1, i = row % ne;
-    const int s2 = col / (2 * ne), m2 = (col / ne) & 1, j = col % ne;
+  // rows go to waves, columns to consecutive lanes: reads of J along j and writes of D along col
+  // coalesce; a lane's columns and a wave's row are decomposed into (species, moment, bin) once
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int cs[kSysCols], cm[kSysCols], cj[kSysCols];
+#pragma unroll
+  for (int u = 0; u < kSysCols; ++u) {
+    const int col = lane + 64 * u;
+    cs[u] = col / (2 * ne);
+    cm[u] = (col / ne) & 1;
+    cj[u] = col % ne;
+  }
+  for (int row = wave; row < nb; row += nw) {
+    const int s = row / (2 * ne), m = (row / ne) & 1, i = row % ne, sp = partner_of(s);
     const double f0 = sf[(2 * s) * ne + i], f1 = sf[(2 * s + 1) * ne + i];
-    double dS = 0.0;
-    for (int p = 0; p < 2; ++p) {
-      if (s2 != (p == 0 ? s : partner_of(s))) continue;
-      const double* Jp = J + ((s * 2 + p) * 4) * n2 + i * ne + j;   // [o][i][j] of (s, p)
-      if (m == 0)
-        dS += m2 == 0 ? Jp[0] - f0 * Jp[n2] : -3.0 * f1 * Jp[3 * n2];
-      else
-        dS += m2 == 0 ? -f1 * Jp[n2] : Jp[2 * n2] - f0 * Jp[3 * n2];
+    const double x0 = sc[(2 * s) * ne + i], x1 = sc[(2 * s + 1) * ne + i];
+    const double diag = c0 + lo[z * nb + row] + up[z * nb + row];
+    double* Drow = Dz + (int64_t)row * nb;
+#pragma unroll
+    for (int u = 0; u < kSysCols; ++u) {
+      const int col = lane + 64 * u;
+      if (col >= nb) continue;
+      const int s2 = cs[u], m2 = cm[u], j = cj[u];
+      double dS = 0.0;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        if (s2 != (p == 0 ? s : sp)) continue;
+        const double* Jp = J + ((s * 2 + p) * 4) * n2 + i * ne + j;   // [o][i][j] of (s, p)
+        if (m == 0)
+          dS += m2 == 0 ? Jp[0] - f0 * Jp[n2] : -3.0 * f1 * Jp[3 * n2];
+        else
+          dS += m2 == 0 ? -f1 * Jp[n2] : Jp[2 * n2] - f0 * Jp[3 * n2];
+      }
+      double d = -dS;
+      if (s2 == s && j == i) {
+        d += m == 0 ? (m2 == 0 ? x0 : 3.0 * x1) : (m2 == 0 ? x1 : x0);
+        if (m2 == m) d += diag;
+      }
+      Drow[col] = d;
     }
-    double d = -dS;
-    if (s2 == s && j == i) {
-      const double x0 = sc[(2 * s) * ne + i], x1 = sc[(2 * s + 1) * ne + i];
-      d += m == 0 ? (m2 == 0 ? x0 : 3.0 * x1) : (m2 == 0 ? x1 : x0);
-      if (m2 == m) d += c0 + lo[z * nb + row] + up[z * nb + row];
-    }
-    Dz[e] = d;
   }
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     const int s = k / (2 * ne), m = (k / ne) & 1, i = k % ne;
