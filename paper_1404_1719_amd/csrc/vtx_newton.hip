@@ -146,19 +146,18 @@ constexpr int kSolveBlock = 1024, kSolveWaves = kSolveBlock / 64;
 constexpr int kPanel = 9;     // columns per wave (a multiple of 3: the update reads them in threes)
 constexpr int kMaxNb = 140;   // nb^2 + 3 nb doubles of LDS and the pivot maps within 160 KiB
 static_assert(kMaxNb <= kPanel * kSolveWaves, "the waves' panels cover the largest block");
-constexpr int kFormIter = (kMaxNb * kMaxNb + kSolveBlock - 1) / kSolveBlock;   // block entries per lane
-constexpr int kFormBatch = 5;   // loads in flight per lane while forming the block
+constexpr int kFormRows = 3;   // rows per wave whose loads are in flight while forming the block
 
 // LDS doubles the panels need inside the block's space: two factored panels (alternate
 // panels) and each wave's 9 x 9 pivot rows.
 constexpr int panel_space(int rows) { return 2 * kPanel * 64 * rows + kSolveWaves * kPanel * kPanel; }
 
 // out[i] = sum_j A[i][j] w[j] + add[i] for an nb x nb row-major A (LDS or global): wave w takes
-// rows w, w + 16, ...; its lanes split j and sum by shuffles. The loads of three rows are issued
-// before their sums, so a global A costs a memory latency per three rows, not per row.
+// rows w, w + 16, ...; its lanes split j and sum by shuffles. The loads of all its rows are issued
+// before their sums, so a global A costs one memory latency, not one per row.
 constexpr int kMatvecRows = (kMaxNb + kSolveWaves - 1) / kSolveWaves;   // rows per wave
 constexpr int kMatvecCols = (kMaxNb + 63) / 64;                         // entries per lane and row
-constexpr int kMatvecBatch = 3;
+constexpr int kMatvecBatch = 9;
 static_assert(kMatvecRows % kMatvecBatch == 0, "rows per wave come in whole batches");
 __device__ __forceinline__ void matvec(const double* A, const double* w, const double* add, double* out, int nb) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -181,6 +180,45 @@ __device__ __forceinline__ void matvec(const double* A, const double* w, const d
       const double r = wave_sum64(s[t]);
       if (lane == 0 && i < nb) out[i] = r + add[i];
     }
+  }
+}
+
+// The rows of A that matvec gives this lane (wave w: rows w, w + 16, ...), loaded ahead of
+// their use; and the product from them.
+template <int COLS>
+__device__ __forceinline__ void matvec_load(const double* A, int nb, double (&m)[kMatvecRows][COLS]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < kMatvecRows; ++t) {
+    const int i = wave + kSolveWaves * t;
+#pragma unroll
+    for (int u = 0; u < COLS; ++u) {
+      const int j = lane + 64 * u;
+      m[t][u] = (i < nb && j < nb) ? A[(int64_t)i * nb + j] : 0.0;
+    }
+  }
+}
+template <int COLS>
+__device__ __forceinline__ void matvec_partial(const double (&m)[kMatvecRows][COLS], const double* w, int nb,
+                                               double (&s)[kMatvecRows]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < kMatvecRows; ++t) {
+    s[t] = 0.0;
+#pragma unroll
+    for (int u = 0; u < COLS; ++u) {
+      const int j = lane + 64 * u;
+      if (j < nb) s[t] = __builtin_fma(m[t][u], w[j], s[t]);
+    }
+  }
+}
+__device__ __forceinline__ void matvec_finish(double (&s)[kMatvecRows], const double* add, double* out, int nb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < kMatvecRows; ++t) {
+    const int i = wave + kSolveWaves * t;
+    const double r = wave_sum64(s[t]);
+    if (lane == 0 && i < nb) out[i] = r + add[i];
   }
 }
 
@@ -346,7 +384,9 @@ __device__ __forceinline__ void panel_apply(double (&a)[ROWS][kPanel], int q, in
   for (int h = 0; h < ROWS; ++h)
 #pragma unroll
     for (int c = 0; c < kPanel; ++c) a[h][c] *= keep[h];
-  for (int t = 0; t < ns; ++t) {
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) {
+    if (t >= ns) break;
     double gt[ROWS];
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) gt[h] = g_in[t * 64 * ROWS + lane + 64 * h];
@@ -364,6 +404,14 @@ __device__ __forceinline__ void panel_apply(double (&a)[ROWS][kPanel], int q, in
   // the area is written again at the next panel, after this wave's reads
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// A workgroup barrier for LDS only: it waits for the wave's LDS operations, not for its global
+// stores, which the elimination never reads back before its closing full barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <int ROWS>
@@ -396,27 +444,42 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
     double* Dr = Dray + (int64_t)r * nb2;
     const double* lr = lray + (int64_t)r * nb;
     const double* um = uray + (int64_t)(r - 1) * nb;
-    // M_r, formed in LDS over M_{r-1}^{-1} (coalesced reads of D_r, all issued before the first
-    // use), then into registers
+    // M_r, formed in LDS over M_{r-1}^{-1}: waves take rows, lanes columns (coalesced reads of D_r,
+    // a wave's rows' loads issued before their first use). At three rows per lane, entry by entry,
+    // with fewer registers: the elimination there needs every one.
+    if constexpr (ROWS < 3) {
 #pragma unroll 1
-    for (int t0 = 0; t0 < kFormIter; t0 += kFormBatch) {
-      double dv[kFormBatch];
+      for (int i0 = wave; i0 < nb; i0 += kSolveWaves * kFormRows) {
+        double dv[kFormRows][ROWS];   // columns per lane: ceil(nb / 64), as rows
 #pragma unroll
-      for (int t = 0; t < kFormBatch; ++t) {
-        const int e = tid + kSolveBlock * (t0 + t);
-        dv[t] = e < nb2 ? Dr[e] : 0.0;
-      }
+        for (int t = 0; t < kFormRows; ++t) {
+          const int i = i0 + kSolveWaves * t;
 #pragma unroll
-      for (int t = 0; t < kFormBatch; ++t) {
-        const int e = tid + kSolveBlock * (t0 + t);
-        if (e < nb2) {
-          double m = dv[t];
-          if (r > 0) {
-            const int i = e / nb, j = e - i * nb;
-            m -= lr[i] * Inv[e] * um[j];
+          for (int u = 0; u < ROWS; ++u) {
+            const int j = lane + 64 * u;
+            dv[t][u] = (i < nb && j < nb) ? Dr[(int64_t)i * nb + j] : 0.0;
           }
-          Inv[e] = m;
         }
+#pragma unroll
+        for (int t = 0; t < kFormRows; ++t) {
+          const int i = i0 + kSolveWaves * t;
+          if (i >= nb) break;
+          const double li = r > 0 ? lr[i] : 0.0;
+#pragma unroll
+          for (int u = 0; u < ROWS; ++u) {
+            const int j = lane + 64 * u;
+            if (j < nb) Inv[i * nb + j] = r > 0 ? dv[t][u] - li * Inv[i * nb + j] * um[j] : dv[t][u];
+          }
+        }
+      }
+    } else {
+      for (int e = tid; e < nb2; e += blockDim.x) {
+        double m = Dr[e];
+        if (r > 0) {
+          const int i = e / nb, j = e - i * nb;
+          m -= lr[i] * Inv[e] * um[j];
+        }
+        Inv[e] = m;
       }
     }
     for (int i = tid; i < nb; i += blockDim.x) {
@@ -424,7 +487,7 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
       w[i] = 0.0;
       step[i] = -1;
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) {
       const int i = lane + 64 * h;
@@ -434,16 +497,16 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
         a[h][c] = (i < nb && j < nb) ? Inv[i * nb + j] : 0.0;
       }
     }
-    __syncthreads();   // the panels' buffers take the block's space
+    lds_barrier();   // the panels' buffers take the block's space
     for (int q = 0; q < npanels; ++q) {
       if (q > 0 && wave != q - 1)
         panel_apply<ROWS>(a, q - 1, nb, lane, gbuf + ((q - 1) & 1) * kPanel * 64 * ROWS, cw, step);
       if (wave == q) panel_factor<ROWS>(a, q, nb, lane, gbuf + (q & 1) * kPanel * 64 * ROWS, piv, step);
-      __syncthreads();
+      lds_barrier();
     }
     if (wave != npanels - 1)
       panel_apply<ROWS>(a, npanels - 1, nb, lane, gbuf + ((npanels - 1) & 1) * kPanel * 64 * ROWS, cw, step);
-    __syncthreads();
+    lds_barrier();
     // Inv[a][b] = Z[pi(a)][pi^-1(b)]: entry (i, j) of the registers goes to Inv[step[i]][piv[j]]
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) {
@@ -456,28 +519,40 @@ __global__ __launch_bounds__(kSolveBlock) void ray_solve_kernel(int nb, int64_t 
         if (j < nb) Inv[ai * nb + piv[j]] = a[h][c];
       }
     }
-    __syncthreads();
+    lds_barrier();
     // y_r = M_r^{-1} v; M_r^{-1} replaces D_r for the back substitution, y_r the right-hand side
     for (int e = tid; e < nb2; e += blockDim.x) Dr[e] = Inv[e];
     matvec(Inv, v, w, y, nb);
-    __syncthreads();
+    lds_barrier();
     for (int i = tid; i < nb; i += blockDim.x) bray[(int64_t)r * nb + i] = y[i];
-    __syncthreads();
+    lds_barrier();
   }
   // back substitution: x_{N-1} = y_{N-1}; x_r = y_r + M_r^{-1} (up_r x_{r+1}); x kept in v
   for (int i = tid; i < nb; i += blockDim.x) v[i] = y[i];
-  __syncthreads();
+  __syncthreads();   // also makes the sweep's writes of D and rhs visible to the whole workgroup
+  // the rows of the next zone's M_r^{-1} are loaded while this zone's sums and barriers run
+  // (at three rows per lane, zone by zone: the prefetch would spill the elimination's registers)
+  constexpr int kPre = ROWS < 3 ? ROWS : 1;
+  double mrow[kMatvecRows][kPre];
+  if (ROWS < 3 && nzr > 1) matvec_load(Dray + (int64_t)(nzr - 2) * nb2, nb, mrow);
   for (int r = nzr - 2; r >= 0; --r) {
     const double* ur = uray + (int64_t)r * nb;
     for (int i = tid; i < nb; i += blockDim.x) {
       w[i] = ur[i] * v[i];
       y[i] = bray[(int64_t)r * nb + i];
     }
-    __syncthreads();
-    matvec(Dray + (int64_t)r * nb2, w, y, v, nb);
-    __syncthreads();
+    lds_barrier();
+    if constexpr (ROWS < 3) {
+      double sums[kMatvecRows];
+      matvec_partial(mrow, w, nb, sums);
+      if (r > 0) matvec_load(Dray + (int64_t)(r - 1) * nb2, nb, mrow);
+      matvec_finish(sums, y, v, nb);
+    } else {
+      matvec(Dray + (int64_t)r * nb2, w, y, v, nb);
+    }
+    lds_barrier();
     for (int i = tid; i < nb; i += blockDim.x) bray[(int64_t)r * nb + i] = v[i];
-    __syncthreads();
+    lds_barrier();
   }
 }
 
