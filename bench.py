@@ -532,18 +532,30 @@ def tabulated_leg(inp, wl, precision, launches, t_direct_ms, ref):
     return out
 
 
-def roofline(wl, precision, t_fwd, t_bwd, zl):
+def roofline(wl, precision, t_fwd, t_bwd, zl, f64_share=None):
     """Roofline entry of the dominant launch (the backward call of a chunk): algorithmic FLOPs
     per launch / its HIP-event duration. In the mixed path that call runs two kernels, one per
-    zone class (FP32 up to |eta_e| = eta_fp64, FP64 above), and its duration is their sum."""
+    zone class (FP32 up to |eta_e| = eta_fp64, FP64 above), and its duration is their sum. Its
+    peak is then the one its arithmetic can reach: the share f of zones in the FP64 class runs
+    the same algorithm at the FP64 vector rate, so the call's attainable rate is
+    1 / ((1 - f) / P32 + f / P64) (f from the workload's eta_e); the FP32 peak is reported
+    beside it."""
     dom_ms, dom_bwd = (t_bwd, True) if t_bwd >= t_fwd else (t_fwd, False)
     flops = algorithmic_flops_per_zone(wl.ne, wl.nquad, dom_bwd) * zl
     achieved = flops / (dom_ms * 1e-3) / 1e12
     tag = f"rates_{'backward' if dom_bwd else 'forward'}_{precision}_{wl.name}"
-    return {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS[precision], "traffic": traffic_from_profiles(tag),
-            "kernel": tag, "launch_ms": dom_ms, "zones_per_launch": zl,
-            "valu_issue": valu_issue_from_profiles(tag), "fwd_launch_ms": t_fwd, "bwd_launch_ms": t_bwd}
+    peak = PEAK_TFLOPS[precision]
+    out = {"bound": "alu", "achieved": achieved, "unit": "TFLOP/s"}
+    if precision == "mixed" and f64_share is not None:
+        peak = 1.0 / ((1.0 - f64_share) / PEAK_TFLOPS["mixed"] + f64_share / PEAK_TFLOPS["fp64"])
+        out["peak_derivation"] = (f"{f64_share:.4f} of the zones in the FP64 class: "
+                                  f"1 / ((1 - f) / {PEAK_TFLOPS['mixed']} + f / {PEAK_TFLOPS['fp64']})")
+        out["peak_fp32"] = PEAK_TFLOPS["mixed"]
+        out["frac_of_fp32_peak"] = achieved / PEAK_TFLOPS["mixed"]
+    out.update({"peak": peak, "frac": achieved / peak, "traffic": traffic_from_profiles(tag), "kernel": tag,
+                "launch_ms": dom_ms, "zones_per_launch": zl, "valu_issue": valu_issue_from_profiles(tag),
+                "fwd_launch_ms": t_fwd, "bwd_launch_ms": t_bwd})
+    return out
 
 
 def main():
@@ -619,7 +631,8 @@ def main():
     del run
     torch.cuda.empty_cache()
 
-    roof = roofline(wl, precision, t_fwd, t_bwd, zl)
+    f64_share = float(np.mean(np.abs(inp.eta_e) > min(args.eta_fp64, 64.0))) if precision == "mixed" else None
+    roof = roofline(wl, precision, t_fwd, t_bwd, zl, f64_share)
 
     fp64 = None
     if precision == "mixed" and args.fp64_steps > 0:
