@@ -126,6 +126,28 @@ def test_pivoting_edge_cases():
         vtx.ray_solve(1, 1, z, torch.zeros((1, 141, 141), dtype=torch.float64, device=DEV), z, z.clone())
 
 
+def test_pivot_search_ties():
+    """Columns whose unused entries tie in the upper 32 bits of their magnitude take the pivot
+    search's full comparison: equal entries (the lowest row pivots) and entries a few units apart
+    in the low mantissa bits (the largest pivots), at one, two and three rows per lane."""
+    rng = np.random.default_rng(21)
+    for nb in (40, 126, 140):
+        nrays, nzr = 2, 3
+        D = rng.standard_normal((nrays, nzr, nb, nb)) + 0.5 * nb ** 0.5 * np.eye(nb)
+        D[:, :, :, 0] = 4.0
+        D[:, :, 1::2, 1] = -3.0 * (1.0 + 2.0 ** -40 * rng.integers(1, 8, (nrays, nzr, nb // 2)))
+        lo, up = rng.uniform(0, 1, (nrays, nzr, nb)), rng.uniform(0, 1, (nrays, nzr, nb))
+        b = rng.standard_normal((nrays, nzr, nb))
+        xref = onewton.solve(lo, D, up, b)
+        bd = dev(b.reshape(-1, nb))
+        print(f"[gpu] ray solve, pivot ties: nb={nb}", flush=True)
+        vtx.ray_solve(nrays, nzr, dev(lo.reshape(-1, nb)), dev(D.reshape(-1, nb, nb)), dev(up.reshape(-1, nb)), bd)
+        torch.cuda.synchronize()
+        x = bd.cpu().numpy().reshape(xref.shape)
+        err = np.abs(x - xref).max() / np.abs(xref).max()
+        assert err <= 1e-9, (nb, err)
+
+
 def test_solve_at_chunk_scale_residual():
     """64 rays x 600 zones at NE = 21 (blocks of 126), the system of the medium workload's zone
     states: on sampled rays, the saved blocks times the solution reproduce the right-hand side."""

@@ -331,6 +331,51 @@ def test_mixed_zone_classes():
         assert err <= MIXED_TOL and gerr <= MIXED_TOL
 
 
+def test_zone_class_tiles():
+    """The mixed passes give each workgroup the k-th zone of its class in a tile of 64 zones.
+    Tiles all of one class, mixed tiles and a ragged last tile: every zone is written once, by its
+    own class (outputs prefilled with NaN), FP64-class zones match the FP64 path bit for bit, and
+    each FP32-class zone matches the same zone run alone, bit for bit."""
+    rng = np.random.default_rng(31)
+    inp = synth.make_inputs("medium", nzones=200)
+    nz = inp.T.shape[0]
+    eta = rng.uniform(0.0, 28.0, nz) * np.where(rng.random(nz) < 0.5, -1.0, 1.0)
+    eta[0:64] = rng.uniform(31.0, 60.0, 64)              # tile 0: FP64 class only
+    eta[64:128] = rng.uniform(-28.0, 28.0, 64)           # tile 1: FP32 class only
+    mix = rng.random(72) < 0.5                           # tile 2 and the ragged tail: mixed
+    eta[128:][mix] = rng.uniform(31.0, 60.0, int(mix.sum())) * np.where(rng.random(int(mix.sum())) < 0.5, -1.0, 1.0)
+    inp.eta_e[:] = eta
+    high = np.abs(eta) > 30.0
+    say(f"[gpu] zone-class tiles: {nz} zones, {int(high.sum())} in the FP64 class")
+    grid = vtx.GridHandle(inp.eps, inp.w)
+    T, E, f = to_dev(inp.T), to_dev(inp.eta_e), to_dev(inp.f)
+    out = {}
+    for prec in ("mixed", "fp64"):
+        opts = vtx.make_opts(prec, 48, "panel", 3, eta_fp64=30.0)
+        e = torch.full((nz, 3, 2, inp.eps.shape[0]), float("nan"), dtype=torch.float64, device=DEV)
+        c = torch.full_like(e, float("nan"))
+        vtx.forward(grid, opts, T, E, f, eta=e, chi=c)
+        torch.cuda.synchronize()
+        out[prec] = (e.cpu().numpy(), c.cpu().numpy())
+    em, cm = out["mixed"]
+    assert np.all(np.isfinite(em)) and np.all(np.isfinite(cm))
+    assert np.array_equal(em[high], out["fp64"][0][high]) and np.array_equal(cm[high], out["fp64"][1][high])
+    low = np.flatnonzero(~high)
+    picks = {int(low[0]), int(low[low < 128][-1]), int(low[low >= 128][0]), int(low[low >= 192][-1])}
+    for z in sorted(picks):
+        one_e, one_c = gpu_forward(synth.subset(inp, [z]), "mixed", 48, "panel")
+        assert np.array_equal(one_e[0], em[z]) and np.array_equal(one_c[0], cm[z]), z
+    ge, gc = synth.random_gradients(nz, inp.eps.shape[0], 12)
+    gm = gpu_backward(inp, ge, gc, "mixed", 48, "panel")
+    g64 = gpu_backward(inp, ge, gc, "fp64", 48, "panel")
+    for got, ref in zip(gm, g64):
+        assert np.all(np.isfinite(got)) and np.array_equal(got[high], ref[high])
+    z = int(np.flatnonzero(~high)[-1])
+    one = gpu_backward(synth.subset(inp, [z]), ge[z:z + 1], gc[z:z + 1], "mixed", 48, "panel")
+    for a, b in zip(one, gm):
+        assert np.array_equal(a[0], b[z])
+
+
 def test_backward_batch_independent():
     """A zone's gradients do not depend on the other zones of the launch (bit for bit)."""
     inp = synth.make_inputs("medium", nzones=9)
