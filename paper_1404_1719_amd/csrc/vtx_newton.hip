@@ -157,29 +157,24 @@ constexpr int panel_space(int rows) { return 2 * kPanel * 64 * rows + kSolveWave
 // before their sums, so a global A costs one memory latency, not one per row.
 constexpr int kMatvecRows = (kMaxNb + kSolveWaves - 1) / kSolveWaves;   // rows per wave
 constexpr int kMatvecCols = (kMaxNb + 63) / 64;                         // entries per lane and row
-constexpr int kMatvecBatch = 9;
-static_assert(kMatvecRows % kMatvecBatch == 0, "rows per wave come in whole batches");
 __device__ __forceinline__ void matvec(const double* A, const double* w, const double* add, double* out, int nb) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll 1
-  for (int t0 = 0; t0 < kMatvecRows; t0 += kMatvecBatch) {
-    double s[kMatvecBatch];
+  double s[kMatvecRows];
 #pragma unroll
-    for (int t = 0; t < kMatvecBatch; ++t) {
-      const int i = wave + kSolveWaves * (t0 + t);
-      s[t] = 0.0;
+  for (int t = 0; t < kMatvecRows; ++t) {
+    const int i = wave + kSolveWaves * t;
+    s[t] = 0.0;
 #pragma unroll
-      for (int u = 0; u < kMatvecCols; ++u) {
-        const int j = lane + 64 * u;
-        if (i < nb && j < nb) s[t] = __builtin_fma(A[(int64_t)i * nb + j], w[j], s[t]);
-      }
+    for (int u = 0; u < kMatvecCols; ++u) {
+      const int j = lane + 64 * u;
+      if (i < nb && j < nb) s[t] = __builtin_fma(A[(int64_t)i * nb + j], w[j], s[t]);
     }
+  }
 #pragma unroll
-    for (int t = 0; t < kMatvecBatch; ++t) {
-      const int i = wave + kSolveWaves * (t0 + t);
-      const double r = wave_sum64(s[t]);
-      if (lane == 0 && i < nb) out[i] = r + add[i];
-    }
+  for (int t = 0; t < kMatvecRows; ++t) {
+    const int i = wave + kSolveWaves * t;
+    const double r = wave_sum64(s[t]);
+    if (lane == 0 && i < nb) out[i] = r + add[i];
   }
 }
 
