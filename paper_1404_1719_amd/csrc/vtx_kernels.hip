@@ -55,19 +55,18 @@ __device__ __forceinline__ double beta_of(const DevPlan& P, int s, int S) {
 }
 
 // 2^x in FP64 for x <= 1000 (callers cap larger arguments): x = n + f with n = rint(x),
-// |f| <= 1/2, and 2^f = e^t, t = f ln 2 (|t| < 0.35), from the degree-10 Chebyshev interpolant of
-// e^t on [-ln2/2, ln2/2] in monomial form (derived by gen/exp2_coeffs.py; worst relative error
-// of the whole evaluation 4.2e-16); 2^n enters through ldexp. x is clamped below at -2100,
-// beyond which 2^x rounds to 0 anyway, so -inf gives 0 too.
+// |f| <= 1/2, and 2^f from the degree-10 Chebyshev interpolant of 2^f on [-1/2, 1/2] in
+// monomial form (derived by gen/exp2_coeffs.py; worst relative error of the whole evaluation
+// 3.9e-16); 2^n enters through ldexp. x is clamped below at -2100, beyond which 2^x rounds to 0
+// anyway, so -inf gives 0 too.
 __device__ __forceinline__ double exp2_fp64(double x) {
-  constexpr double kLn2 = 0.6931471805599453;
-  constexpr double kExpPoly[11] = {1.0, 1.0000000000000067, 0.5000000000000006, 0.16666666666554406,
-                                   0.04166666666657314, 0.008333333385667782, 0.0013888888932488599,
-                                   0.00019841170270440067, 2.4801504346997686e-05, 2.764018079620985e-06,
-                                   2.7626357241447223e-07};
+  constexpr double kExpPoly[11] = {1.0, 0.69314718055995, 0.24022650695910097, 0.05550410866444772,
+                                   0.009618129107606888, 0.0013333558230164974, 0.0001540353044173605,
+                                   1.5252657260200837e-05, 1.321544258792169e-06, 1.0208690299958306e-07,
+                                   7.072585949269223e-09};
   const double xc = fmax(x, -2100.0);
   const double n = rint(xc);
-  const double t = (xc - n) * kLn2;
+  const double t = xc - n;
   double p = kExpPoly[10];
 #pragma unroll
   for (int k = 9; k >= 0; --k) p = __builtin_fma(p, t, kExpPoly[k]);
@@ -141,7 +140,7 @@ __device__ __forceinline__ void blocking_bwd(float z1, float z2, float, R& B, R&
 template <typename R>
 __device__ __forceinline__ void blocking_bwd(double z1, double z2, double C, R& B, R& r1, R& r2) {
   const bool first = z1 <= z2;
-  const double a = exp2_fp64(fmin(first ? z1 : z2, 1000.0));
+  const double a = exp2_fp64(fmin(fmin(z1, z2), 1000.0));
   const double ca = C * a, d1 = 1.0 + a, d2 = 1.0 + ca;
   const double q = recip_pos(d1 * d2);
   B = R(a * q);

@@ -1,10 +1,10 @@
 """Derive the polynomial of the FP64 exp2 in csrc/vtx_kernels.hip (exp2_fp64).
 
-exp2_fp64 reduces 2^x to 2^n e^t with n = rint(x) and t = (x - n) ln 2, |t| <= ln2/2. This
-script interpolates e^t at the degree-10 Chebyshev nodes of [-ln2/2, ln2/2] in 200-bit
-arithmetic, converts the interpolant to monomial coefficients, rounds them to double, and
-checks the resulting evaluation (Horner with exact fma emulated in rationals, then ldexp)
-against 200-bit 2^x: the worst relative error is 4.2e-16.
+exp2_fp64 reduces 2^x to 2^n 2^f with n = rint(x) and f = x - n, |f| <= 1/2. This script
+interpolates 2^f at the degree-10 Chebyshev nodes of [-1/2, 1/2] in 200-bit arithmetic,
+converts the interpolant to monomial coefficients, rounds them to double, and checks the
+resulting evaluation (Horner in f with exact fma emulated in rationals, then ldexp) against
+200-bit 2^x.
 
 Usage: python -m paper_1404_1719_amd.gen.exp2_coeffs   (prints the C initialiser)
 Needs mpmath; it is not run by the build.
@@ -16,15 +16,14 @@ from fractions import Fraction
 import mpmath
 
 DEGREE = 10
-LN2 = 0.6931471805599453
 
 
 def coefficients(degree=DEGREE):
     mpmath.mp.prec = 200
-    half = mpmath.log(2) / 2
+    half = mpmath.mpf(1) / 2
     nodes = [half * mpmath.cos(mpmath.pi * (2 * k + 1) / (2 * (degree + 1))) for k in range(degree + 1)]
     vander = mpmath.matrix([[x ** j for j in range(degree + 1)] for x in nodes])
-    values = mpmath.matrix([mpmath.exp(x) for x in nodes])
+    values = mpmath.matrix([mpmath.power(2, x) for x in nodes])
     return [float(c) for c in mpmath.lu_solve(vander, values)]
 
 
@@ -36,7 +35,7 @@ def exp2(x, c):
     """The kernel's evaluation order, with exact fma (the kernel's callers cap x at 1000)."""
     x = max(x, -2100.0)
     n = float(round(x))   # round half to even, as rint
-    t = (x - n) * LN2
+    t = x - n
     p = c[-1]
     for k in range(len(c) - 2, -1, -1):
         p = _fma(p, t, c[k])

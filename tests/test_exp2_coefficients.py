@@ -1,8 +1,8 @@
 """The FP64 exp2 polynomial in the kernel source (host only).
 
-exp2_fp64 in csrc/vtx_kernels.hip evaluates 2^x as ldexp(P(t), n), t = (x - n) ln 2, with
-P the degree-10 Chebyshev interpolant of e^t on [-ln2/2, ln2/2]. gen/exp2_coeffs.py derives
-P in 200-bit arithmetic. Here: the constants in the source are the ones it derives, and the
+exp2_fp64 in csrc/vtx_kernels.hip evaluates 2^x as ldexp(P(f), n), f = x - n, with P the
+degree-10 Chebyshev interpolant of 2^f on [-1/2, 1/2]. gen/exp2_coeffs.py derives P in 200-bit
+arithmetic. Here: the constants in the source are the ones it derives, and the
 evaluation in the kernel's order, with exact fma, is within 5e-16 of 200-bit 2^x, also at the
 ends of the reduced interval and of the normal double range (subnormal results carry the
 rounding of the subnormal format itself), and it gives +inf and 0 beyond the range (its callers
