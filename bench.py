@@ -42,6 +42,18 @@ FLOP_FWD_NES, FLOP_FWD_PAIR = 4 + 7 + 1 + 4 * 16, 4 + 7 + 1 + 2 * 16
 FLOP_BWD_EXTRA = 10 + 4 + 26 + 8
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}   # MI355X vector peaks, FP32 / FP64
 
+# The paper's own performance figures: whole-application rates of the CPU code on its clusters,
+# context for the numbers above, not a baseline for them (the paper gives none for the rates).
+PAPER_CONTEXT = {
+    "note": "whole PROMETHEUS-VERTEX application on CPU clusters; not comparable with the rates kernels",
+    "node": {"value": 10.0, "unit": "GFlop/s", "hardware": "2x Intel Xeon E5540 (Nehalem), 8 cores, 2.53 GHz",
+             "detail": "more than 12 % of the node's 81 GFlop/s peak, memory bound at an arithmetic intensity of "
+                       "0.96 flop/byte (Sect. 3.2, Fig. 3)"},
+    "system": {"value": 0.25, "unit": "PFlop/s", "hardware": "SuperMUC",
+               "detail": "sustained, about 10 % of nominal peak; derived from about 35 GFlop/s per SandyBridge node "
+                         "and the weak-scaling efficiency over 1-8192 nodes (Sect. 3.2)"},
+}
+
 
 def algorithmic_flops_per_zone(ne, nquad, backward):
     ntn, ntp = ne * (ne + 1) // 2, ne * ne
@@ -713,6 +725,7 @@ def main():
         "end_to_end_streamed": streaming, "threshold_64": thr64, "jacobian": jac, "newton_step": newton,
         "with_positron_scattering": positron, "fused_forward_backward": fused, "tabulated": tabulated,
         "electron_mass": mass,
+        "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(line), flush=True)
 
