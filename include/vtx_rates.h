@@ -106,8 +106,19 @@ typedef struct {
 void vtx_opts_default(vtx_opts* opts);
 
 /*
- * Forward: eta, chi for nzones zones (nzones >= 0; 0 is a no-op).
- * Inputs T, eta_e, f; outputs eta, chi, all device pointers as laid out above.
+ * Forward: the emissivities eta and opacities chi of nzones zones, i.e. the interaction rates
+ * that the paper lists among the model's components and that enter the source terms of the
+ * moment equations for J and H (Sect. 2.1, Eq. 1), computed by the definitions and the rule
+ * above.
+ *   grid, opts: host structs, read during the call only.
+ *   T, eta_e [nz], f [nz][3][2][ne]: device inputs, read only.
+ *   eta, chi [nz][3][2][ne]: device outputs; every entry of the nz zones is overwritten. They
+ *   must not overlap the inputs or each other.
+ *   nzones: 0 <= nzones <= 2^31 - 1; 0 is a no-op (pointers unused).
+ * Errors, all detected before any launch: VTX_EINVAL (null grid/opts, a null array with
+ * nzones > 0, bad grid or options, nzones out of range), VTX_EDEVICE (no gfx950 device
+ * current), VTX_ENOMEM (tables could not be allocated). VTX_EHIP: a launch failed; outputs
+ * are then unspecified.
  */
 int vtx_rates_forward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
                       const double* T, const double* eta_e, const double* f,
@@ -138,10 +149,14 @@ int vtx_rates_forward_mass(const vtx_grid* grid, const vtx_opts* opts, int64_t n
 
 /*
  * Backward (vector-Jacobian product): given upstream gradients g_eta, g_chi of a scalar L,
- * writes g_T = dL/dT (at fixed eta_e), g_eta_e = dL/deta_e (at fixed T) and g_f = dL/df.
- * These are the exact derivatives of the discrete rule above, including the motion of the
- * quadrature nodes with T and mu_e = eta_e T. The kernels are recomputed; nothing is saved
- * from the forward call. All pointers are device memory; outputs are overwritten.
+ * writes g_T = dL/dT (at fixed eta_e), g_eta_e = dL/deta_e (at fixed T) and g_f = dL/df:
+ * the derivatives of the rates that the implicit ray-by-ray Newton-Raphson solve needs
+ * (Sect. 2.1, radial sweep). They are the exact derivatives of the discrete rule above,
+ * including the motion of the quadrature nodes with T and mu_e = eta_e T. The kernels are
+ * recomputed; nothing is saved from the forward call.
+ *   T, eta_e [nz], f, g_eta, g_chi [nz][3][2][ne]: device inputs, read only.
+ *   g_T, g_eta_e [nz], g_f [nz][3][2][ne]: device outputs, overwritten; no overlaps.
+ *   grid, opts, nzones and the error codes as for vtx_rates_forward.
  */
 int vtx_rates_backward(const vtx_grid* grid, const vtx_opts* opts, int64_t nzones,
                        const double* T, const double* eta_e, const double* f,
