@@ -331,6 +331,31 @@ def test_mixed_zone_classes():
         assert err <= MIXED_TOL and gerr <= MIXED_TOL
 
 
+def test_class_threshold_boundaries():
+    """Zones exactly at the class boundaries: |eta_e| equal to the threshold stays in the FP32
+    class and the next double above it goes to FP64; |eta_e| = 64 is FP32 when the threshold
+    is 64 or more (the range cap). An FP64-class zone matches the FP64 path bit for bit and an
+    FP32-class zone does not (its FP32 quadrature rounds differently), so bit equality tells
+    which class ran a zone; every zone stays within the mixed bar of the oracle (floor 1e-2 of
+    the outputs' absolute quadrature scale Aq, the mixed path's metric)."""
+    above = np.nextafter(30.0, 31.0)
+    inp = synth.make_inputs("medium", nzones=8)
+    inp.eta_e[:] = [30.0, -30.0, above, -above, 64.0, -64.0, 12.5, 29.0]
+    inp.T[:] = [2.0, 1.0, 2.0, 1.0, 1.5, 3.0, 4.0, 0.8]
+    re, rc, _, _, qe, qc = orates.forward_with_scale(inp.eps, inp.w, inp.T, inp.eta_e, inp.f,
+                                                     orates.Options(nquad=48, rule="panel"), quadrature=True)
+    e64, c64 = gpu_forward(inp, "fp64", 48, "panel")
+    expect = {30.0: [False, False, True, True, True, True, False, False],
+              64.0: [False] * 8, 100.0: [False] * 8}
+    for thr, want in expect.items():
+        em, cm = gpu_forward(inp, "mixed", 48, "panel", eta_fp64=thr)
+        same = [bool(np.array_equal(em[z], e64[z]) and np.array_equal(cm[z], c64[z])) for z in range(8)]
+        err = max(rel_err(em, re, 10.0 * qe).max(), rel_err(cm, rc, 10.0 * qc).max())   # floor 1e-2 Aq
+        say(f"[gpu] class boundaries at threshold {thr}: FP64 class {same}, max err {err:.2e}")
+        assert same == want
+        assert err <= MIXED_TOL
+
+
 def test_zone_class_tiles():
     """The mixed passes give each workgroup the k-th zone of its class in a tile of 64 zones.
     Tiles all of one class, mixed tiles and a ragged last tile: every zone is written once, by its
